@@ -1,0 +1,502 @@
+/*
+ * ising_oracle.c -- plain CPU oracle (TEST INFRASTRUCTURE ONLY).
+ *
+ * Slow on purpose: one replica at a time, one vertex at a time, in the order
+ * the method defines.  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg may call it; the product path never links it.
+ *
+ * The paper defers the algorithm of its own solver to later work (Sec. I and
+ * Sec. III.A), so what is written out here is the classical neighbour it
+ * names (Sec. II.C: simulated annealing, replicas) in the form the HIP path
+ * computes: many independent replicas, each doing single-spin-flip Metropolis
+ * sweeps under an annealing schedule of inverse temperatures, visiting the
+ * vertices colour class by colour class, with an incrementally maintained
+ * local field.  Readings of everything the paper leaves open are listed in
+ * the design notes of the repository; the ones that change numbers are
+ * restated next to the code that applies them.
+ *
+ * Pins (tests/): Philox known-answer vectors; thresholds against a
+ * 50-digit exp; colouring properness and the torus checkerboard; fields and
+ * energy recomputed from scratch after every sweep; the cut identity; brute
+ * force optima for n <= 20; beta = 0 and beta = infinity closed forms; planted
+ * and gauge-transformed instances; a Boltzmann chi-square test.
+ */
+#include "ising_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers:  */
+/* as easy as 1, 2, 3", SC'11).  Round: two 32x32->64 products of the    */
+/* even counter words with fixed multipliers; the high halves are XORed  */
+/* with the odd words and the key, the low halves move to the odd slots. */
+/* The key is advanced by the Weyl constants between rounds.             */
+/* ------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                          uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    uint32_t n1 = (uint32_t)p1;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    uint32_t n3 = (uint32_t)p0;
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+    k0 += PHILOX_W0;
+    k1 += PHILOX_W1;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* ------------------------------------------------------------------ */
+/* Annealing schedule: inverse temperature beta_t for sweep t.           */
+/* ------------------------------------------------------------------ */
+static double beta_at(int32_t kind, int32_t S, double b0, double b1,
+                      const double* betas, int32_t t) {
+  if (kind == OR_EXPLICIT) return betas[t];
+  if (S == 1) return b0;
+  double frac = (double)t / (double)(S - 1);
+  if (kind == OR_LINEAR) return b0 + (b1 - b0) * frac;
+  return b0 * pow(b1 / b0, frac); /* OR_GEOMETRIC */
+}
+
+int oracle_schedule(int32_t kind, int32_t S, double b0, double b1,
+                    const double* betas, double* out) {
+  if (S <= 0) return -1;
+  if (kind != OR_LINEAR && kind != OR_GEOMETRIC && kind != OR_EXPLICIT)
+    return -1;
+  if (kind == OR_EXPLICIT) {
+    if (!betas) return -1;
+  } else {
+    if (!isfinite(b0) || !isfinite(b1) || b0 < 0 || b1 < 0) return -1;
+    if (kind == OR_GEOMETRIC && (b0 <= 0 || b1 <= 0)) return -1;
+  }
+  for (int32_t t = 0; t < S; ++t) {
+    double b = beta_at(kind, S, b0, b1, betas, t);
+    if (!isfinite(b) || b < 0) return -1;
+    if (out) out[t] = b;
+  }
+  return 0;
+}
+
+/* Metropolis acceptance of a move raising the energy by dE = 2k > 0 has
+ * probability exp(-beta dE).  It is quantised to a 32-bit threshold so that
+ * the decision is an integer compare of a uniform u32 against Tq. */
+uint64_t oracle_threshold(double beta, int64_t k) {
+  double x = -2.0 * (double)k;
+  x = x * beta;
+  double a = exp(x);
+  if (a >= 1.0) return (uint64_t)1 << 32;
+  return (uint64_t)floor(ldexp(a, 32));
+}
+
+/* ------------------------------------------------------------------ */
+/* Graph handling                                                        */
+/* ------------------------------------------------------------------ */
+static int cmp_u64(const void* a, const void* b) {
+  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return (x > y) - (x < y);
+}
+
+int oracle_validate(const or_graph_in* g) {
+  if (g->n <= 0 || g->m < 0) return -1;
+  if (g->m > 0 && (!g->u || !g->v || !g->w)) return -1;
+  int64_t total = 0;
+  uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(g->m + 1));
+  if (!keys) return -1;
+  for (int64_t e = 0; e < g->m; ++e) {
+    int32_t a = g->u[e], b = g->v[e], w = g->w[e];
+    if (a < 0 || b < 0 || a >= g->n || b >= g->n || a == b || w == 0 ||
+        w > 32768 || w < -32768) {
+      free(keys);
+      return -1;
+    }
+    total += 2 * (int64_t)(w < 0 ? -w : w);
+    uint32_t lo = (uint32_t)(a < b ? a : b), hi = (uint32_t)(a < b ? b : a);
+    keys[e] = ((uint64_t)lo << 32) | hi;
+  }
+  if (total >= ((int64_t)1 << 30)) {
+    free(keys);
+    return -1;
+  }
+  qsort(keys, (size_t)g->m, sizeof(uint64_t), cmp_u64);
+  for (int64_t e = 1; e < g->m; ++e)
+    if (keys[e] == keys[e - 1]) {
+      free(keys);
+      return -1;
+    }
+  free(keys);
+  if (g->colour) {
+    for (int32_t i = 0; i < g->n; ++i)
+      if (g->colour[i] < 0 || g->colour[i] >= 1024) return -1;
+    for (int64_t e = 0; e < g->m; ++e)
+      if (g->colour[g->u[e]] == g->colour[g->v[e]]) return -1;
+  }
+  return 0;
+}
+
+typedef struct {
+  int32_t n;
+  int64_t m;
+  int32_t* row;  /* [n+1] */
+  int32_t* nbr;  /* [2m] neighbour id */
+  int32_t* wt;   /* [2m] MaxCut weight w of that edge */
+  int32_t n_colours;
+  int32_t* colour;       /* [n] */
+  int32_t* class_start;  /* [C+1] into members */
+  int32_t* members;      /* [n] vertices of each class, ascending id */
+  int32_t* leader;       /* [n] RNG counter word 0 for vertex v */
+  int32_t* rank;         /* [n] which Philox output word vertex v uses */
+  int64_t W;
+  int64_t kmax;          /* max_v sum_j |w_vj| */
+} or_graph;
+
+static void graph_free(or_graph* G) {
+  free(G->row);
+  free(G->nbr);
+  free(G->wt);
+  free(G->colour);
+  free(G->class_start);
+  free(G->members);
+  free(G->leader);
+  free(G->rank);
+}
+
+int32_t oracle_colouring(int32_t n, int64_t m, const int32_t* u,
+                         const int32_t* v, int32_t* colour) {
+  if (n <= 0 || m < 0) return -1;
+  int32_t* deg = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+  int32_t* nbr = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+  for (int64_t e = 0; e < m; ++e) {
+    if (u[e] < 0 || v[e] < 0 || u[e] >= n || v[e] >= n) {
+      free(deg);
+      free(nbr);
+      return -1;
+    }
+    deg[u[e] + 1]++;
+    deg[v[e] + 1]++;
+  }
+  for (int32_t i = 0; i < n; ++i) deg[i + 1] += deg[i];
+  int32_t* fill = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  for (int32_t i = 0; i < n; ++i) fill[i] = deg[i];
+  for (int64_t e = 0; e < m; ++e) {
+    nbr[fill[u[e]]++] = v[e];
+    nbr[fill[v[e]]++] = u[e];
+  }
+  /* First fit in index order: vertex i takes the smallest colour that no
+   * already-coloured neighbour (id < i) holds. */
+  int32_t* used = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 2));
+  for (int32_t i = 0; i < n + 2; ++i) used[i] = -1;
+  int32_t C = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t a = deg[i]; a < deg[i + 1]; ++a)
+      if (nbr[a] < i) used[colour[nbr[a]]] = i;
+    int32_t c = 0;
+    while (used[c] == i) ++c;
+    colour[i] = c;
+    if (c + 1 > C) C = c + 1;
+  }
+  free(used);
+  free(fill);
+  free(nbr);
+  free(deg);
+  return C;
+}
+
+static int graph_build(const or_graph_in* in, or_graph* G) {
+  memset(G, 0, sizeof(*G));
+  if (oracle_validate(in) != 0) return -1;
+  int32_t n = in->n;
+  int64_t m = in->m;
+  G->n = n;
+  G->m = m;
+  G->row = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+  G->nbr = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+  G->wt = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+  for (int64_t e = 0; e < m; ++e) {
+    G->row[in->u[e] + 1]++;
+    G->row[in->v[e] + 1]++;
+  }
+  for (int32_t i = 0; i < n; ++i) G->row[i + 1] += G->row[i];
+  int32_t* fill = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  for (int32_t i = 0; i < n; ++i) fill[i] = G->row[i];
+  G->W = 0;
+  for (int64_t e = 0; e < m; ++e) {
+    int32_t a = in->u[e], b = in->v[e];
+    G->nbr[fill[a]] = b;
+    G->wt[fill[a]++] = in->w[e];
+    G->nbr[fill[b]] = a;
+    G->wt[fill[b]++] = in->w[e];
+    G->W += in->w[e];
+  }
+  free(fill);
+  G->kmax = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int64_t s = 0;
+    for (int32_t a = G->row[i]; a < G->row[i + 1]; ++a)
+      s += G->wt[a] < 0 ? -G->wt[a] : G->wt[a];
+    if (s > G->kmax) G->kmax = s;
+  }
+  G->colour = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (in->colour) {
+    int32_t C = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      G->colour[i] = in->colour[i];
+      if (in->colour[i] + 1 > C) C = in->colour[i] + 1;
+    }
+    G->n_colours = C;
+  } else {
+    G->n_colours = oracle_colouring(n, m, in->u, in->v, G->colour);
+  }
+  int32_t C = G->n_colours;
+  G->class_start = (int32_t*)calloc((size_t)C + 1, sizeof(int32_t));
+  for (int32_t i = 0; i < n; ++i) G->class_start[G->colour[i] + 1]++;
+  for (int32_t c = 0; c < C; ++c) G->class_start[c + 1] += G->class_start[c];
+  G->members = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  G->leader = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  G->rank = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * ((size_t)C + 1));
+  for (int32_t c = 0; c <= C; ++c) pos[c] = G->class_start[c];
+  for (int32_t i = 0; i < n; ++i) G->members[pos[G->colour[i]]++] = i;
+  free(pos);
+  /* Random-number groups: inside each colour class, taken in ascending id
+   * order, consecutive runs of four vertices share one Philox block.  The
+   * block's counter names the first vertex of the run (the leader); the
+   * i-th vertex of the run uses output word i. */
+  for (int32_t c = 0; c < C; ++c) {
+    for (int32_t idx = G->class_start[c]; idx < G->class_start[c + 1]; ++idx) {
+      int32_t local = idx - G->class_start[c];
+      int32_t vtx = G->members[idx];
+      G->rank[vtx] = local % 4;
+      G->leader[vtx] = G->members[idx - local % 4];
+    }
+  }
+  return 0;
+}
+
+/* u32 random number for (vertex, sweep, replica, purpose): word rank(v) of
+ * Philox4x32-10 with key = seed and counter = (leader(v), t, r, tag). */
+static uint32_t draw(const or_graph* G, uint64_t seed, int32_t v, uint32_t t,
+                     uint32_t r, uint32_t tag) {
+  uint32_t ctr[4] = {(uint32_t)G->leader[v], t, r, tag};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t out[4];
+  oracle_philox4x32_10(ctr, key, out);
+  return out[G->rank[v]];
+}
+
+int64_t oracle_cut(int32_t n, int64_t m, const int32_t* u, const int32_t* v,
+                   const int32_t* w, const int8_t* s) {
+  (void)n;
+  int64_t cut = 0;
+  for (int64_t e = 0; e < m; ++e)
+    if (s[u[e]] != s[v[e]]) cut += w[e];
+  return cut;
+}
+
+/* Local field h_i = sum_j J_ij s_j = -sum_j w_ij s_j, from scratch. */
+static void fields_from_scratch(const or_graph* G, const int8_t* s,
+                                int64_t* h) {
+  for (int32_t i = 0; i < G->n; ++i) {
+    int64_t acc = 0;
+    for (int32_t a = G->row[i]; a < G->row[i + 1]; ++a)
+      acc -= (int64_t)G->wt[a] * s[G->nbr[a]];
+    h[i] = acc;
+  }
+}
+
+/* E(s) = sum_e w_e s_u s_v, from scratch (each edge seen from both ends). */
+static int64_t energy_from_scratch(const or_graph* G, const int8_t* s) {
+  int64_t twice = 0;
+  for (int32_t i = 0; i < G->n; ++i)
+    for (int32_t a = G->row[i]; a < G->row[i + 1]; ++a)
+      twice += (int64_t)G->wt[a] * s[i] * s[G->nbr[a]];
+  return twice / 2;
+}
+
+static uint64_t splitmix64(uint64_t* x) {
+  uint64_t z = (*x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+typedef struct {
+  const or_graph* G;
+  const or_run_in* run;
+  or_run_out* out;
+  const double* betas;
+  int32_t first, stride; /* replicas first, first+stride, ... of the range */
+  int64_t failures;
+  int status;
+} worker_arg;
+
+static void run_replica(worker_arg* A, int32_t r, int8_t* s, int64_t* h,
+                        int64_t* hchk, uint64_t* tq, int32_t* order) {
+  const or_graph* G = A->G;
+  const or_run_in* run = A->run;
+  or_run_out* out = A->out;
+  const int32_t n = G->n, S = run->n_sweeps;
+  const int64_t slot = r - run->r_begin;
+  const int64_t kmax = G->kmax;
+
+  /* Initial state: given, or s_v = +1 iff bit 31 of draw(v, 0, r, tag 1). */
+  for (int32_t i = 0; i < n; ++i) {
+    if (run->init_spins)
+      s[i] = run->init_spins[(int64_t)r * n + i];
+    else
+      s[i] = (draw(G, run->seed, i, 0, (uint32_t)r, 1) >> 31) ? 1 : -1;
+  }
+  fields_from_scratch(G, s, h);
+  int64_t E = energy_from_scratch(G, s);
+  int64_t best_cut = (G->W - E) / 2;
+  int32_t best_sweep = -1;
+  int64_t accepts = 0;
+  if (out->best_state) memcpy(out->best_state + slot * n, s, (size_t)n);
+  uint64_t shuf = run->shuffle_seed ^ ((uint64_t)r * 0x632BE59BD9B4E019ull);
+
+  for (int32_t t = 0; t < S; ++t) {
+    const double beta = A->betas[t];
+    for (int64_t k = 1; k <= kmax; ++k) tq[k] = oracle_threshold(beta, k);
+    for (int32_t c = 0; c < G->n_colours; ++c) {
+      const int32_t lo = G->class_start[c], hi = G->class_start[c + 1];
+      for (int32_t idx = lo; idx < hi; ++idx) order[idx - lo] = G->members[idx];
+      if (run->shuffle_seed) { /* any order inside a class is equivalent */
+        for (int32_t a = hi - lo - 1; a > 0; --a) {
+          int32_t b = (int32_t)(splitmix64(&shuf) % (uint64_t)(a + 1));
+          int32_t tmp = order[a];
+          order[a] = order[b];
+          order[b] = tmp;
+        }
+      }
+      for (int32_t q = 0; q < hi - lo; ++q) {
+        const int32_t i = order[q];
+        const int64_t k = s[i] * h[i]; /* flipping s_i changes E by 2k */
+        int accept;
+        if (k <= 0) {
+          accept = 1;
+        } else {
+          uint32_t u = draw(G, run->seed, i, (uint32_t)t, (uint32_t)r, 0);
+          accept = (uint64_t)u < tq[k];
+        }
+        if (accept) {
+          s[i] = (int8_t)-s[i];
+          E += 2 * k;
+          ++accepts;
+          for (int32_t a = G->row[i]; a < G->row[i + 1]; ++a)
+            h[G->nbr[a]] -= 2 * (int64_t)G->wt[a] * s[i];
+        }
+      }
+    }
+    /* End of sweep: the best is taken over end-of-sweep states only, strict
+     * improvement, so the earliest sweep reaching a value keeps it. */
+    int64_t cut = (G->W - E) / 2;
+    if (cut > best_cut) {
+      best_cut = cut;
+      best_sweep = t;
+      if (out->best_state) memcpy(out->best_state + slot * n, s, (size_t)n);
+    }
+    if (out->energy_trace) out->energy_trace[slot * S + t] = E;
+    if (run->check_every_sweep) {
+      fields_from_scratch(G, s, hchk);
+      int bad = energy_from_scratch(G, s) != E;
+      for (int32_t i = 0; i < n && !bad; ++i) bad = hchk[i] != h[i];
+      if (bad) A->failures++;
+    }
+  }
+  out->best_cut[slot] = best_cut;
+  out->best_sweep[slot] = best_sweep;
+  out->accepts[slot] = accepts;
+  out->final_energy[slot] = E;
+  if (out->final_state) memcpy(out->final_state + slot * n, s, (size_t)n);
+  if (out->final_field)
+    for (int32_t i = 0; i < n; ++i) out->final_field[slot * n + i] = (int32_t)h[i];
+}
+
+static void* worker(void* p) {
+  worker_arg* A = (worker_arg*)p;
+  const int32_t n = A->G->n;
+  int8_t* s = (int8_t*)malloc((size_t)n);
+  int64_t* h = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  int64_t* hchk = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  uint64_t* tq = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(A->G->kmax + 1));
+  int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!s || !h || !hchk || !tq || !order) {
+    A->status = -1;
+  } else {
+    for (int32_t r = A->run->r_begin + A->first; r < A->run->r_end; r += A->stride)
+      run_replica(A, r, s, h, hchk, tq, order);
+  }
+  free(s);
+  free(h);
+  free(hchk);
+  free(tq);
+  free(order);
+  return NULL;
+}
+
+int oracle_anneal(const or_graph_in* gin, const or_run_in* run,
+                  or_run_out* out) {
+  if (!gin || !run || !out) return -1;
+  if (run->n_replicas <= 0 || run->r_begin < 0 || run->r_end > run->n_replicas ||
+      run->r_begin >= run->r_end)
+    return -1;
+  double* betas = (double*)malloc(sizeof(double) * (size_t)(run->n_sweeps > 0 ? run->n_sweeps : 1));
+  if (oracle_schedule(run->kind, run->n_sweeps, run->beta0, run->beta1,
+                      run->betas, betas) != 0) {
+    free(betas);
+    return -1;
+  }
+  or_graph G;
+  if (graph_build(gin, &G) != 0) {
+    free(betas);
+    graph_free(&G);
+    return -1;
+  }
+  int32_t nt = run->n_threads < 1 ? 1 : run->n_threads;
+  int32_t nr = run->r_end - run->r_begin;
+  if (nt > nr) nt = nr;
+  worker_arg* args = (worker_arg*)calloc((size_t)nt, sizeof(worker_arg));
+  pthread_t* th = (pthread_t*)calloc((size_t)nt, sizeof(pthread_t));
+  for (int32_t i = 0; i < nt; ++i) {
+    args[i].G = &G;
+    args[i].run = run;
+    args[i].out = out;
+    args[i].betas = betas;
+    args[i].first = i;
+    args[i].stride = nt;
+  }
+  if (nt == 1) {
+    worker(&args[0]);
+  } else {
+    for (int32_t i = 0; i < nt; ++i) pthread_create(&th[i], NULL, worker, &args[i]);
+    for (int32_t i = 0; i < nt; ++i) pthread_join(th[i], NULL);
+  }
+  int status = 0;
+  out->check_failures = 0;
+  for (int32_t i = 0; i < nt; ++i) {
+    out->check_failures += args[i].failures;
+    if (args[i].status) status = -1;
+  }
+  free(args);
+  free(th);
+  free(betas);
+  graph_free(&G);
+  return status;
+}

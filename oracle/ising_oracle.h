@@ -1,0 +1,88 @@
+/*
+ * ising_oracle.h -- plain CPU oracle for many-replica single-spin-flip
+ * Metropolis annealing of sparse Ising / MaxCut problems.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously correct
+ * definition against which the HIP path is checked.  It shares no code with
+ * the HIP library and must never be called by the product path; only the
+ * tests, the smoke check and the CPU-baseline leg of the benchmark use it.
+ *
+ * Problem statement (paper Sec. II.A): weighted MaxCut on n variables with
+ * integer edge weights w; the Gset tori are "formulated as weighted MaxCut"
+ * and represent 2D Edwards-Anderson spin glasses.  Reading used here: the
+ * Ising couplings are J = -w, so with s in {-1,+1}^n
+ *     E(s)   = sum_e w_e s_u s_v,      cut(s) = sum_e w_e (1 - s_u s_v)/2
+ *     cut(s) = (W - E(s)) / 2  with W = sum_e w_e.
+ * Work is counted in sweeps (paper Sec. III.A); one sweep here visits every
+ * vertex once, colour class by colour class.
+ */
+#ifndef ISING_ORACLE_H
+#define ISING_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_LINEAR = 0, OR_GEOMETRIC = 1, OR_EXPLICIT = 2 };
+
+typedef struct {
+  int32_t n;
+  int64_t m;
+  const int32_t* u;
+  const int32_t* v;
+  const int32_t* w;
+  const int32_t* colour; /* NULL: greedy first-fit colouring in index order */
+} or_graph_in;
+
+typedef struct {
+  int32_t kind;          /* OR_LINEAR / OR_GEOMETRIC / OR_EXPLICIT */
+  int32_t n_sweeps;
+  double beta0, beta1;
+  const double* betas;   /* [n_sweeps] for OR_EXPLICIT */
+  int32_t n_replicas;
+  uint64_t seed;
+  const int8_t* init_spins; /* NULL, or [n_replicas][n] +-1 */
+  int32_t r_begin, r_end;   /* simulate replicas r_begin .. r_end-1 */
+  int32_t n_threads;        /* host threads over replicas (>= 1) */
+  int32_t check_every_sweep;/* recompute h and E from scratch each sweep */
+  uint64_t shuffle_seed;    /* 0: ascending order inside a colour class */
+} or_run_in;
+
+typedef struct { /* per-replica arrays are indexed by r - r_begin */
+  int64_t* best_cut;     /* [nr] */
+  int32_t* best_sweep;   /* [nr]; -1 = the initial state */
+  int64_t* accepts;      /* [nr] accepted flips */
+  int64_t* final_energy; /* [nr] */
+  int8_t* best_state;    /* [nr][n] or NULL */
+  int8_t* final_state;   /* [nr][n] or NULL */
+  int32_t* final_field;  /* [nr][n] or NULL */
+  int64_t* energy_trace; /* [nr][n_sweeps] or NULL: E after every sweep */
+  int64_t check_failures;/* sweeps where maintained h/E != recomputed */
+} or_run_out;
+
+/* Philox4x32-10 block function (Salmon et al., SC'11). */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                          uint32_t out[4]);
+/* beta_t for t = 0 .. S-1.  Returns 0, or -1 on an invalid schedule. */
+int oracle_schedule(int32_t kind, int32_t n_sweeps, double beta0, double beta1,
+                    const double* betas, double* out);
+/* Acceptance threshold Tq(beta, k) = floor(2^32 exp(-2 k beta)), 2^32 when
+ * exp(...) >= 1.  Accept a flip with k > 0 iff u32 < Tq. */
+uint64_t oracle_threshold(double beta, int64_t k);
+/* Greedy first-fit colouring in index order; returns the number of colours
+ * or -1 on invalid input. */
+int32_t oracle_colouring(int32_t n, int64_t m, const int32_t* u,
+                         const int32_t* v, int32_t* colour);
+/* MaxCut value of a +-1 assignment. */
+int64_t oracle_cut(int32_t n, int64_t m, const int32_t* u, const int32_t* v,
+                   const int32_t* w, const int8_t* spins);
+/* Validate a problem the way the library does: 0 ok, -1 invalid. */
+int oracle_validate(const or_graph_in* g);
+/* Run the anneal.  Returns 0, or -1 on invalid input. */
+int oracle_anneal(const or_graph_in* g, const or_run_in* run, or_run_out* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
