@@ -1,0 +1,292 @@
+/*
+ * ising.h -- C ABI of libising, an MI355X (gfx950) many-replica Metropolis
+ * annealer for sparse Ising / MaxCut problems.
+ *
+ * Problem (paper Sec. II.A): weighted MaxCut on n variables with integer
+ * edge weights, as in the Gset instances (toroidal +-1 spin glasses, sparse
+ * random unweighted graphs; Table I).  The library maximises
+ *     cut(s) = sum_e w_e (1 - s_u s_v) / 2,   s in {-1,+1}^n,
+ * through the Ising energy E(s) = sum_e w_e s_u s_v (couplings J = -w), with
+ * cut = (W - E)/2 and W = sum_e w_e.  A solution is reported per variable
+ * in the original numbering (the paper's appendices list variables 1..N;
+ * here ids are 0-based, and x = (1+s)/2 gives the paper's bits).
+ *
+ * Method: R independent replicas, each doing single-spin-flip Metropolis
+ * sweeps under an annealing schedule beta_t (work is counted in sweeps,
+ * Sec. III.A; independent trials, Sec. III.A and II.B).  Inside a sweep the
+ * vertices are visited one colour class at a time (a proper colouring, so
+ * the updates of one class are independent), each with
+ *     k = s_i h_i,  h_i = -sum_j w_ij s_j   (flipping s_i changes E by 2k)
+ *     accept iff k <= 0 or u < Tq(beta_t, k),  Tq = floor(2^32 exp(-2 k beta_t))
+ * where u is word r of Philox4x32-10(key = seed, counter = (leader, t, r,
+ * 0)) -- see ising_create for the leader/word assignment.  The best cut of a
+ * replica is taken over its initial state and its end-of-sweep states
+ * (strict improvement, earliest sweep wins).  Every step is integer
+ * arithmetic on the device, so results are bit-identical across kernel
+ * variants, batch compositions and runs.
+ *
+ * Conventions
+ *  - Every call returns an int status: ISING_OK (0) or a negative code.
+ *  - Out-parameters are written only on success.
+ *  - Inputs are copied; the caller keeps ownership of every pointer it
+ *    passes.  Output buffers are caller-owned host memory unless a name
+ *    says "device".
+ *  - A handle is not thread-safe; distinct handles may be used concurrently
+ *    from different threads.
+ *  - `stream` arguments are hipStream_t values passed as void*; NULL means
+ *    the null stream.  Work is enqueued and the call returns; calls that
+ *    return results to the host synchronise that stream first.
+ *  - No exception crosses the ABI.
+ */
+#ifndef ISING_H
+#define ISING_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define ISING_OK 0
+#define ISING_ERR_INVALID -1     /* argument or problem rejected */
+#define ISING_ERR_NOMEM -2       /* host or device allocation failed, or
+                                    a request exceeds the server budget */
+#define ISING_ERR_DEVICE -3      /* a HIP call failed (no GPU, fault, ...) */
+#define ISING_ERR_STATE -4       /* call not valid in the handle's state */
+#define ISING_ERR_UNSUPPORTED -5 /* e.g. the multispin path on weights != +-1 */
+#define ISING_ERR_TIMEOUT -6     /* server wait timed out */
+
+/* Human-readable text of a status code (static storage). */
+const char* ising_status_string(int status);
+/* Detail of the last error raised on the calling thread (thread-local
+ * storage, valid until the thread's next failing call). */
+const char* ising_last_error(void);
+
+/* --------------------------------------------------------------- problem */
+typedef struct ising_problem ising_problem;
+
+/*
+ * Compile a MaxCut problem (paper Sec. II.A: n variables, m weighted edges).
+ *   n        number of vertices, 1 <= n < 2^28
+ *   m        number of undirected edges, m >= 0
+ *   u, v, w  edge e joins u[e] and v[e] (0-based) with weight w[e]
+ *   colour   NULL: greedy first-fit colouring in index order (each vertex
+ *            takes the smallest colour not held by a lower-numbered
+ *            neighbour; on an even-sided row-major torus this is the
+ *            checkerboard).  Otherwise colour[i] in [0, 1024) per vertex; it
+ *            must be proper.  Classes are swept in colour order 0, 1, ...
+ * Random-number runs: inside each colour class, in ascending vertex id,
+ * consecutive runs of four vertices share one Philox block; the first
+ * vertex of a run is its leader and the i-th vertex uses output word i.
+ * Errors (ISING_ERR_INVALID): n out of range; m < 0; NULL arrays with
+ * m > 0; an id out of range; a self loop; a repeated undirected edge;
+ * w == 0 or |w| > 32768; 2 * sum_e |w_e| >= 2^30; an improper or
+ * out-of-range colouring.  ISING_ERR_NOMEM on allocation failure.
+ * This call is host-only; device memory is allocated on first use.
+ * *out is library-owned until ising_destroy.
+ */
+int ising_create(int32_t n, int64_t m, const int32_t* u, const int32_t* v,
+                 const int32_t* w, const int32_t* colour, ising_problem** out);
+
+/* Free a problem and all its host and device memory.  NULL is a no-op. */
+int ising_destroy(ising_problem* p);
+
+typedef struct {
+  int32_t n, n_colours;
+  int64_t m;
+  int64_t total_weight;   /* W = sum_e w_e */
+  int32_t kmax;           /* max_i sum_j |w_ij| (largest |k|) */
+  int32_t max_degree;
+  int32_t unit_weights;   /* 1 when every |w| == 1 (multispin path allowed) */
+  int32_t n_padded;       /* vertices after padding each class to 4 */
+} ising_info;
+
+/* Facts about a compiled problem (host-only). */
+int ising_problem_info(const ising_problem* p, ising_info* out);
+/* The colour of every vertex, original order (host-only).  [n] */
+int ising_colouring(const ising_problem* p, int32_t* colour);
+/* MaxCut value of a +-1 assignment in original order (host-only). */
+int ising_eval_cut(const ising_problem* p, const int8_t* spins, int64_t* cut);
+
+/* -------------------------------------------------------------- schedule */
+enum { ISING_SCHED_LINEAR = 0, ISING_SCHED_GEOMETRIC = 1, ISING_SCHED_EXPLICIT = 2 };
+
+/*
+ * Annealing schedule of inverse temperatures beta_t, t = 0 .. n_sweeps-1:
+ *   LINEAR     beta0 + (beta1 - beta0) * t/(S-1)
+ *   GEOMETRIC  beta0 * (beta1/beta0)^(t/(S-1))     (beta0, beta1 > 0)
+ *   EXPLICIT   betas[t]
+ * (S = 1 gives beta0.)  Every beta_t must be finite and >= 0.
+ */
+typedef struct {
+  int32_t kind;
+  int32_t n_sweeps;
+  double beta0, beta1;
+  const double* betas;
+} ising_schedule;
+
+/*
+ * The acceptance thresholds the library uses, Tq(beta_t, k) for
+ * k = 1..kmax, written to out[t*kmax + (k-1)] as uint64 (2^32 = always).
+ * Host-only; used to check the table against an independent computation
+ * before any device run.  ISING_ERR_INVALID on a bad schedule or kmax < 1.
+ */
+int ising_threshold_table(const ising_schedule* s, int32_t kmax, uint64_t* out);
+
+/* ---------------------------------------------------------------- anneal */
+enum {
+  ISING_PATH_AUTO = 0,  /* the autotuner's (cached) choice */
+  ISING_PATH_PLAIN = 1, /* state in HBM, one launch per colour pass */
+  ISING_PATH_FIELD = 2, /* persistent: replica blocks resident in LDS */
+  ISING_PATH_MSC = 3    /* persistent multispin: 32 replicas per word */
+};
+
+/*
+ * Launch choices.  All of them compute identical results.
+ *   path                 ISING_PATH_*
+ *   replicas_per_block   FIELD: replicas per workgroup (1..16);
+ *                        MSC: 32-replica words per workgroup (1..4)
+ *   block_threads        64..1024, multiple of 64 (0 = default)
+ */
+typedef struct {
+  int32_t path;
+  int32_t replicas_per_block;
+  int32_t block_threads;
+} ising_tuning;
+
+/*
+ * Anneal R = n_replicas replicas of p from their initial states (Philox
+ * init draws, or the states given by ising_set_initial_state) through the
+ * whole schedule.  Enqueued on `stream`; returns without waiting.  Each
+ * call starts afresh.  `tuning` NULL = ISING_PATH_AUTO.
+ * Errors: ISING_ERR_INVALID (bad schedule, R < 1, tuning out of range, a
+ * threshold table over 2^26 entries); ISING_ERR_UNSUPPORTED (MSC on
+ * non-unit weights, or a problem too large for the requested LDS path);
+ * ISING_ERR_NOMEM; ISING_ERR_DEVICE.
+ */
+int ising_anneal(ising_problem* p, const ising_schedule* s, int32_t n_replicas,
+                 uint64_t seed, void* stream);
+int ising_anneal_tuned(ising_problem* p, const ising_schedule* s,
+                       int32_t n_replicas, uint64_t seed,
+                       const ising_tuning* tuning, void* stream);
+
+/*
+ * Initial states for subsequent anneals: spins[r*n + i] in {-1,+1}, original
+ * order, for r < n_replicas; NULL restores the Philox initial draw.  An
+ * anneal with a different R than given here is rejected (ISING_ERR_STATE).
+ */
+int ising_set_initial_state(ising_problem* p, const int8_t* spins,
+                            int32_t n_replicas);
+
+/* Record E after every sweep of every replica in the next anneals
+ * (enable = 1) or not (0). */
+int ising_set_trace(ising_problem* p, int32_t enable);
+
+/*
+ * Results of the last anneal (synchronises its stream).
+ *   best_cut       the largest best cut over replicas
+ *   best_replica   its replica (lowest index on ties)
+ *   per_replica    NULL or [R] best cut of each replica
+ * ISING_ERR_STATE before any anneal.
+ */
+int ising_cut(ising_problem* p, int64_t* best_cut, int32_t* best_replica,
+              int64_t* per_replica);
+
+/* Best state of the argmax replica, +-1 per vertex, original order [n]. */
+int ising_best_state(ising_problem* p, int8_t* spins);
+
+/*
+ * Per-replica detail of the last anneal, any pointer may be NULL, each [R]:
+ * best_sweep (-1 = the initial state), accepted flips, final energy E.
+ */
+int ising_replica_results(ising_problem* p, int32_t* best_sweep,
+                          int64_t* accepts, int64_t* final_energy);
+/* Best and final state of replica r (either NULL), original order [n]. */
+int ising_replica_state(ising_problem* p, int32_t r, int8_t* best_spins,
+                        int8_t* final_spins);
+/* Final local fields h of replica r, original order [n]; available after
+ * PLAIN and FIELD anneals (ISING_ERR_UNSUPPORTED after MSC). */
+int ising_replica_field(ising_problem* p, int32_t r, int32_t* field);
+/* Energy trace of the last anneal, out[r*S + t] (needs ising_set_trace). */
+int ising_energy_trace(ising_problem* p, int64_t* out);
+/* Device time of the last anneal in milliseconds (HIP events around the
+ * enqueued work; synchronises). */
+int ising_last_anneal_ms(ising_problem* p, double* ms);
+
+/* --------------------------------------------------------------- batching */
+/*
+ * Anneal `count` problems in one persistent launch (captured once into a
+ * hipGraph and replayed while the batch shape is unchanged).  Problem i uses
+ * seeds[i], the shared schedule and R replicas; results are read per
+ * problem with ising_cut / ising_best_state / ising_replica_*.  Results
+ * equal those of separate ising_anneal calls bit for bit.  `tuning` NULL =
+ * autotune.  Errors as ising_anneal.
+ */
+int ising_anneal_batch(ising_problem* const* ps, int32_t count,
+                       const ising_schedule* s, int32_t n_replicas,
+                       const uint64_t* seeds, const ising_tuning* tuning,
+                       void* stream);
+/* Device time of the last batch launch in milliseconds (synchronises). */
+int ising_last_batch_ms(double* ms);
+
+/*
+ * Autotuner: time each launch candidate on a short prefix of sweeps of the
+ * given batch and return the fastest in *best (also cached in memory and in
+ * the file named by $ISING_TUNE_CACHE when set).  prefix_sweeps <= 0 picks
+ * a default.
+ */
+int ising_autotune(ising_problem* const* ps, int32_t count,
+                   const ising_schedule* s, int32_t n_replicas,
+                   int32_t prefix_sweeps, ising_tuning* best, void* stream);
+
+/* ---------------------------------------------------------------- serving */
+typedef struct ising_server ising_server;
+
+typedef struct {
+  int32_t status;          /* ISING_OK, or the error that ended the request */
+  int32_t reached_target;  /* 1 when some replica reached target_cut */
+  int32_t sweeps_done;
+  int32_t best_replica;
+  int64_t best_cut;
+  double t_submit, t_admit, t_done; /* seconds on the server's clock */
+} ising_result;
+
+/*
+ * Continuous-batching server.  Requests are admitted while the device bytes
+ * they need (state, graph, tables) fit in hbm_budget and fewer than
+ * max_slots are resident; all resident requests advance chunk_sweeps sweeps
+ * per step in one persistent launch, finished ones retire and queued ones
+ * are admitted between steps.  State stays on the device across steps.
+ * backend: 0 = GPU; 1 = host-only null backend that advances sweep counters
+ * without computing (to exercise the scheduling logic without a GPU).
+ */
+int ising_server_create(uint64_t hbm_budget, int32_t max_slots,
+                        int32_t chunk_sweeps, int32_t backend, void* stream,
+                        ising_server** out);
+/*
+ * Queue one anneal of p (the problem must outlive the request).  It stops
+ * early, after a multiple of check_every of its own sweeps, once a replica's
+ * best cut reaches target_cut (check_every <= 0: never early).  A request
+ * whose footprint exceeds the budget returns ISING_ERR_NOMEM.
+ */
+int ising_server_submit(ising_server* srv, ising_problem* p,
+                        const ising_schedule* s, int32_t n_replicas,
+                        uint64_t seed, int64_t target_cut, int32_t check_every,
+                        uint64_t* ticket);
+/* Wait for a request (timeout_s < 0: forever). */
+int ising_server_wait(ising_server* srv, uint64_t ticket, double timeout_s,
+                      ising_result* out);
+/* Best state of a finished request's argmax replica, original order. */
+int ising_server_best_state(ising_server* srv, uint64_t ticket, int8_t* spins);
+/* Device bytes a request would need (the admission footprint). */
+int ising_server_footprint(const ising_problem* p, const ising_schedule* s,
+                           int32_t n_replicas, uint64_t* bytes);
+/* Running totals: steps launched, requests finished, peak resident. */
+int ising_server_stats(ising_server* srv, int64_t* steps, int64_t* finished,
+                       int32_t* peak_resident);
+int ising_server_destroy(ising_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISING_H */

@@ -1,0 +1,822 @@
+// anneal.cpp -- device memory, launch planning and the single-problem C ABI.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <numeric>
+
+#include "runtime.h"
+
+namespace ising {
+
+// ---------------------------------------------------------------- memory
+DeviceArena::~DeviceArena() { release(); }
+
+void DeviceArena::release() {
+  if (base) {
+    DeviceGuard g(device);
+    (void)hipFree(base);
+  }
+  base = nullptr;
+  cap = used = 0;
+}
+
+int DeviceArena::reserve(size_t bytes) {
+  used = 0;
+  if (bytes <= cap && base) return ISING_OK;
+  release();
+  bytes = std::max<size_t>(bytes, 4096);
+  if (hipGetDevice(&device) != hipSuccess) {
+    set_error("no HIP device");
+    return ISING_ERR_DEVICE;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? ISING_ERR_NOMEM : ISING_ERR_DEVICE;
+  }
+  base = static_cast<char*>(p);
+  cap = bytes;
+  return ISING_OK;
+}
+
+RunBuffers::~RunBuffers() {
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+}
+
+Launcher::~Launcher() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (staging) (void)hipHostFree(staging);
+  if (staged) (void)hipEventDestroy(staged);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+}
+
+int device_cu_count() {
+  static std::mutex mu;
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!cached[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n = 0;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+size_t lds_budget(int path) {
+  const size_t total = 160 * 1024;
+  return total - (path == ISING_PATH_MSC ? kMscStaticLds : kFieldStaticLds);
+}
+
+int msc_planes(int max_deg) {
+  int planes = 1;
+  while ((1 << planes) <= max_deg) ++planes;
+  return planes;
+}
+
+// ---------------------------------------------------------------- graph
+int upload_graph(const HostGraph& g, DevGraph& d) {
+  const size_t e2 = (size_t)(2 * g.m);
+  size_t bytes = DeviceArena::span(sizeof(int32_t) * (g.n_pad + 1)) +
+                 3 * DeviceArena::span(sizeof(int32_t) * e2) +
+                 DeviceArena::span(sizeof(int2) * e2) +
+                 3 * DeviceArena::span(sizeof(int32_t) * g.grp.size()) +
+                 DeviceArena::span(sizeof(int32_t) * g.cls.size()) +
+                 DeviceArena::span(sizeof(int32_t) * g.n);
+  IRET(d.arena.reserve(bytes));
+  d.device = d.arena.device;
+  d.row = d.arena.take<int32_t>(g.n_pad + 1);
+  d.adj = d.arena.take<int32_t>(e2);
+  d.wgt = d.arena.take<int32_t>(e2);
+  d.adjm = d.arena.take<uint32_t>(e2);
+  d.aw = d.arena.take<int2>(e2);
+  d.grp = d.arena.take<int32_t>(g.grp.size());
+  d.gbase = d.arena.take<int32_t>(g.grp.size());
+  d.gdeg = d.arena.take<uint32_t>(g.grp.size());
+  d.cls = d.arena.take<int32_t>(g.cls.size());
+  d.pos = d.arena.take<int32_t>(g.n);
+  ICHK(hipMemcpy(d.row, g.row.data(), sizeof(int32_t) * g.row.size(), hipMemcpyHostToDevice));
+  if (e2) {
+    ICHK(hipMemcpy(d.adj, g.adj.data(), sizeof(int32_t) * e2, hipMemcpyHostToDevice));
+    ICHK(hipMemcpy(d.wgt, g.wgt.data(), sizeof(int32_t) * e2, hipMemcpyHostToDevice));
+    ICHK(hipMemcpy(d.adjm, g.adjm.data(), sizeof(uint32_t) * e2, hipMemcpyHostToDevice));
+    ICHK(hipMemcpy(d.aw, g.aw.data(), sizeof(int2) * e2, hipMemcpyHostToDevice));
+  }
+  ICHK(hipMemcpy(d.gbase, g.gbase.data(), sizeof(int32_t) * g.grp.size(), hipMemcpyHostToDevice));
+  ICHK(hipMemcpy(d.gdeg, g.gdeg.data(), sizeof(uint32_t) * g.grp.size(), hipMemcpyHostToDevice));
+  ICHK(hipMemcpy(d.grp, g.grp.data(), sizeof(int32_t) * g.grp.size(), hipMemcpyHostToDevice));
+  ICHK(hipMemcpy(d.cls, g.cls.data(), sizeof(int32_t) * g.cls.size(), hipMemcpyHostToDevice));
+  ICHK(hipMemcpy(d.pos, g.pos.data(), sizeof(int32_t) * g.n, hipMemcpyHostToDevice));
+  return ISING_OK;
+}
+
+static int ensure_device(ising_problem* p) {
+  if (p->dg.device >= 0) return ISING_OK;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    set_error("no HIP device available");
+    return ISING_ERR_DEVICE;
+  }
+  return upload_graph(p->g, p->dg);
+}
+
+// ---------------------------------------------------------------- planning
+static bool pow2_upto(int x, int hi) { return x >= 1 && x <= hi && (x & (x - 1)) == 0; }
+
+// LDS of one unit: state words, two threshold rows, and the group
+// descriptors (leader word, adjacency base, packed degrees).
+static size_t persistent_lds(const HostGraph& g, const Table& t, const PersistentConfig& c) {
+  return sizeof(int32_t) * ((size_t)c.G * g.n_pad + 2 * (size_t)std::max(t.kw, 1)) +
+         3 * sizeof(int32_t) * (size_t)(g.n_pad / 4);
+}
+
+int check_config(const HostGraph& g, const Table& t, int R, const PersistentConfig& c) {
+  (void)R;
+  if (c.path == ISING_PATH_PLAIN) return ISING_OK;
+  if (c.path != ISING_PATH_FIELD && c.path != ISING_PATH_MSC) {
+    set_error("unknown path %d", c.path);
+    return ISING_ERR_INVALID;
+  }
+  if (c.block != 256 && c.block != 512 && c.block != 1024) {
+    set_error("block_threads must be 256, 512 or 1024");
+    return ISING_ERR_INVALID;
+  }
+  const int gmax = c.path == ISING_PATH_FIELD ? kMaxReplicasPerBlock : kMaxWordsPerBlock;
+  if (!pow2_upto(c.G, gmax) || c.block / c.G < 64) {
+    set_error("replicas_per_block %d invalid for %d threads", c.G, c.block);
+    return ISING_ERR_INVALID;
+  }
+  if (c.path == ISING_PATH_MSC) {
+    if (!g.unit) {
+      set_error("the multispin path needs all |w| == 1");
+      return ISING_ERR_UNSUPPORTED;
+    }
+    if (g.max_deg > 31) {
+      set_error("the multispin path supports degree <= 31");
+      return ISING_ERR_UNSUPPORTED;
+    }
+    if (c.block == 1024) {
+      set_error("the multispin path runs 256 or 512 threads");
+      return ISING_ERR_INVALID;
+    }
+  }
+  if (g.max_deg > kMaxLdsDegree) {
+    set_error("degrees above %d need the plain path", kMaxLdsDegree);
+    return ISING_ERR_UNSUPPORTED;
+  }
+  if (t.kw > kMaxThresholdRow) {
+    set_error("threshold rows longer than %d need the plain path", kMaxThresholdRow);
+    return ISING_ERR_UNSUPPORTED;
+  }
+  if (persistent_lds(g, t, c) > lds_budget(c.path)) {
+    set_error("problem does not fit the %zu-byte LDS budget with %d replica(s) per block",
+              lds_budget(c.path), c.G);
+    return ISING_ERR_UNSUPPORTED;
+  }
+  return ISING_OK;
+}
+
+PersistentConfig heuristic_config(const HostGraph& g, const Table& t, int R) {
+  PersistentConfig c;
+  c.path = ISING_PATH_FIELD;
+  c.G = 1;
+  c.block = 1024;
+  const int cus = std::max(device_cu_count(), 1);
+  // Several replicas per block only when replicas are plentiful, so that
+  // the unit count stays above the CU count.
+  while (c.G < kMaxReplicasPerBlock && (R / (2 * c.G)) >= 2 * cus) {
+    PersistentConfig n = c;
+    n.G *= 2;
+    if (persistent_lds(g, t, n) > lds_budget(n.path)) break;
+    c = n;
+  }
+  // Small classes leave most of a 1024-thread block idle.
+  const int per_class = std::max(1, g.n_pad / 4 / std::max(g.C, 1));
+  while (c.block > 256 && c.block / c.G / 2 >= 64 && per_class * 2 <= c.block / c.G) c.block /= 2;
+  if (check_config(g, t, R, c) != ISING_OK) c.path = ISING_PATH_PLAIN;
+  return c;
+}
+
+// ---------------------------------------------------------------- run state
+int prepare_run(ising_problem* p, const Table& table, int R, const PersistentConfig& cfg,
+                hipStream_t stream) {
+  RunBuffers& b = p->run;
+  const HostGraph& g = p->g;
+  if (b.valid && b.stream) (void)hipStreamSynchronize(b.stream);
+  b.valid = false;
+  const size_t np = (size_t)g.n_pad, RR = (size_t)R;
+  const int nw = (R + 31) / 32;
+  const int S = table.S;
+  const bool plain = cfg.path == ISING_PATH_PLAIN, msc = cfg.path == ISING_PATH_MSC;
+  const bool init_given = p->init_R > 0;
+  if (init_given && p->init_R != R) {
+    set_error("initial states were given for %d replicas, anneal asks %d", p->init_R, R);
+    return ISING_ERR_STATE;
+  }
+  size_t best_bytes = msc ? sizeof(uint32_t) * nw * np : np * RR;
+  size_t save_bytes = plain ? 0 : (msc ? sizeof(uint32_t) * nw * np : sizeof(int32_t) * RR * np);
+  size_t bytes = DeviceArena::span(best_bytes) + DeviceArena::span(save_bytes) +
+                 (plain ? DeviceArena::span(np * RR) + DeviceArena::span(sizeof(int32_t) * np * RR)
+                        : 0) +
+                 5 * DeviceArena::span(sizeof(int32_t) * RR) +
+                 DeviceArena::span(sizeof(unsigned long long) * RR) +
+                 DeviceArena::span(sizeof(unsigned long long)) +
+                 (p->trace ? DeviceArena::span(sizeof(int32_t) * (size_t)S * RR) : 0) +
+                 DeviceArena::span(sizeof(int32_t) * (size_t)g.n) +
+                 DeviceArena::span(sizeof(uint32_t) * table.tq.size()) +
+                 2 * DeviceArena::span(sizeof(int32_t) * (size_t)S) +
+                 (init_given ? DeviceArena::span(RR * np) : 0) + DeviceArena::span(sizeof(JobDev));
+  IRET(b.arena.reserve(bytes));
+  b.R = R;
+  b.S = S;
+  b.path = cfg.path;
+  b.G = cfg.G;
+  b.block = cfg.block;
+  b.nw = nw;
+  b.trace = p->trace;
+  b.best = msc ? (void*)b.arena.take<uint32_t>(nw * np) : (void*)b.arena.take<int8_t>(np * RR);
+  b.save = plain ? nullptr : b.arena.take<int32_t>(msc ? nw * np : RR * np);
+  b.spins = plain ? b.arena.take<int8_t>(np * RR) : nullptr;
+  b.field = plain ? b.arena.take<int32_t>(np * RR) : nullptr;
+  b.best_cut = b.arena.take<int32_t>(RR);
+  b.best_sweep = b.arena.take<int32_t>(RR);
+  b.energy = b.arena.take<int32_t>(RR);
+  b.eacc = b.arena.take<int32_t>(RR);
+  b.snap = b.arena.take<int32_t>(RR);
+  b.accepts = b.arena.take<unsigned long long>(RR);
+  b.argmax = b.arena.take<unsigned long long>(1);
+  b.trace_buf = p->trace ? b.arena.take<int32_t>((size_t)S * RR) : nullptr;
+  b.gather = b.arena.take<int32_t>((size_t)g.n);
+  b.tq = b.arena.take<uint32_t>(table.tq.size());
+  b.tq_off = b.arena.take<int32_t>((size_t)S);
+  b.tq_len = b.arena.take<int32_t>((size_t)S);
+  b.init_dev = init_given ? b.arena.take<int8_t>(RR * np) : nullptr;
+  b.job_dev = b.arena.take<JobDev>(1);
+  if (plain) {
+    b.layout_best = kLayoutNR_I8;
+    b.layout_final = kLayoutNR_I8;
+    b.layout_field = kLayoutNR_I32;
+  } else if (msc) {
+    b.layout_best = kLayoutWords;
+    b.layout_final = kLayoutWords;
+    b.layout_field = -1;
+  } else {
+    b.layout_best = kLayoutRN_I8;
+    b.layout_final = kLayoutRN_Spin;
+    b.layout_field = kLayoutRN_Field;
+  }
+  if (!b.ev0) ICHK(hipEventCreate(&b.ev0));
+  if (!b.ev1) ICHK(hipEventCreate(&b.ev1));
+  b.stream = stream;
+  // host copies live in the problem until the next anneal (async uploads)
+  static_assert(sizeof(uint32_t) == 4, "");
+  ICHK(hipMemcpyAsync(b.tq, table.tq.data(), sizeof(uint32_t) * table.tq.size(),
+                      hipMemcpyHostToDevice, stream));
+  ICHK(hipMemcpyAsync(b.tq_off, table.off.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice,
+                      stream));
+  ICHK(hipMemcpyAsync(b.tq_len, table.len.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice,
+                      stream));
+  if (init_given) {
+    std::vector<int8_t> perm(RR * np, 1);
+    for (size_t r = 0; r < RR; ++r)
+      for (int32_t v = 0; v < g.n; ++v)
+        perm[r * np + (size_t)g.pos[(size_t)v]] = p->init[r * (size_t)g.n + (size_t)v];
+    // synchronous: the temporary buffer dies at return
+    ICHK(hipMemcpy(b.init_dev, perm.data(), RR * np, hipMemcpyHostToDevice));
+  }
+  return ISING_OK;
+}
+
+JobDev make_job(ising_problem* p, const Table& table, int R, uint64_t seed, int t_begin,
+                int t_end, const PersistentConfig& cfg) {
+  const HostGraph& g = p->g;
+  const DevGraph& d = p->dg;
+  const RunBuffers& b = p->run;
+  JobDev J;
+  memset(&J, 0, sizeof J);
+  J.row = d.row;
+  J.adj = d.adj;
+  J.wgt = d.wgt;
+  J.adjm = d.adjm;
+  J.aw = d.aw;
+  J.grp = d.grp;
+  J.gbase = d.gbase;
+  J.gdeg = d.gdeg;
+  J.cls = d.cls;
+  J.n_pad = g.n_pad;
+  J.n_colours = g.C;
+  J.W = (int32_t)g.W;
+  J.M = (int32_t)g.m;
+  J.tq = b.tq;
+  J.tq_off = b.tq_off;
+  J.tq_len = b.tq_len;
+  J.S = table.S;
+  J.t_begin = t_begin;
+  J.t_end = t_end;
+  J.flags = (b.trace ? kJobTrace : 0) | (b.init_dev ? kJobInitGiven : 0);
+  J.kw = std::max(table.kw, 1);
+  J.seed_lo = (uint32_t)seed;
+  J.seed_hi = (uint32_t)(seed >> 32);
+  J.R = R;
+  J.G = cfg.G;
+  J.init_spins = b.init_dev;
+  J.save = b.save;
+  J.best = b.best;
+  J.best_cut = b.best_cut;
+  J.best_sweep = b.best_sweep;
+  J.energy = b.energy;
+  J.accepts = b.accepts;
+  J.trace = b.trace_buf;
+  J.argmax = b.argmax;
+  return J;
+}
+
+// ---------------------------------------------------------------- persistent
+int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const PersistentConfig& cfg,
+                   hipStream_t stream, bool use_graph) {
+  const int n_jobs = (int)specs.size();
+  std::vector<JobDev> jobs((size_t)n_jobs);
+  struct U {
+    double cost;
+    int job, block;
+  };
+  std::vector<U> all;
+  size_t lds = 0;
+  int planes = 1;
+  for (int j = 0; j < n_jobs; ++j) {
+    const JobSpec& s = specs[(size_t)j];
+    jobs[(size_t)j] = make_job(s.p, *s.table, s.R, s.seed, s.t_begin, s.t_end, cfg);
+    lds = std::max(lds, persistent_lds(s.p->g, *s.table, cfg));
+    planes = std::max(planes, msc_planes(s.p->g.max_deg));
+    const int per = cfg.path == ISING_PATH_MSC ? 32 * cfg.G : cfg.G;
+    const int nb = (s.R + per - 1) / per;
+    const double cost = (double)s.p->g.n_pad * (s.t_end - s.t_begin) * per + 1.0;
+    for (int k = 0; k < nb; ++k) all.push_back(U{cost, j, k});
+  }
+  if (lds > lds_budget(cfg.path)) {
+    set_error("batch does not fit the LDS budget");
+    return ISING_ERR_UNSUPPORTED;
+  }
+  // longest processing time first, over eight lists (one per XCD)
+  std::stable_sort(all.begin(), all.end(), [](const U& a, const U& b) { return a.cost > b.cost; });
+  std::vector<std::vector<int2>> lists(8);
+  double load[8] = {0};
+  for (const U& u : all) {
+    int best = 0;
+    for (int i = 1; i < 8; ++i)
+      if (load[i] < load[best]) best = i;
+    load[best] += u.cost;
+    lists[(size_t)best].push_back(make_int2(u.job, u.block));
+  }
+  std::vector<int2> units;
+  int32_t list_off[9];
+  list_off[0] = 0;
+  for (int i = 0; i < 8; ++i) {
+    units.insert(units.end(), lists[(size_t)i].begin(), lists[(size_t)i].end());
+    list_off[i + 1] = (int32_t)units.size();
+  }
+  const int n_units = (int)units.size();
+  if (n_units == 0) return ISING_OK;
+
+  // device and pinned staging buffers
+  if (L.jobs_cap < (size_t)n_jobs || L.units_cap < (size_t)n_units || !L.arena.base) {
+    L.jobs_cap = std::max<size_t>(n_jobs, 16);
+    L.units_cap = std::max<size_t>(n_units, 1024);
+    size_t bytes = DeviceArena::span(sizeof(JobDev) * L.jobs_cap) +
+                   DeviceArena::span(sizeof(int2) * L.units_cap) + 2 * DeviceArena::span(64);
+    IRET(L.arena.reserve(bytes));
+    L.jobs_d = L.arena.take<JobDev>(L.jobs_cap);
+    L.units_d = L.arena.take<int2>(L.units_cap);
+    L.list_off_d = L.arena.take<int32_t>(16);
+    L.ctr_d = L.arena.take<int32_t>(16);
+  }
+  const size_t stage_bytes = sizeof(JobDev) * n_jobs + sizeof(int2) * n_units + sizeof(list_off);
+  if (!L.staged) ICHK(hipEventCreateWithFlags(&L.staged, hipEventDisableTiming));
+  (void)hipEventSynchronize(L.staged);  // the previous upload has left the buffer
+  if (L.staging_cap < stage_bytes) {
+    if (L.staging) (void)hipHostFree(L.staging);
+    L.staging = nullptr;
+    L.staging_cap = std::max<size_t>(stage_bytes, 1 << 16);
+    ICHK(hipHostMalloc((void**)&L.staging, L.staging_cap, hipHostMallocDefault));
+  }
+  char* sp = L.staging;
+  memcpy(sp, jobs.data(), sizeof(JobDev) * n_jobs);
+  memcpy(sp + sizeof(JobDev) * n_jobs, units.data(), sizeof(int2) * n_units);
+  memcpy(sp + sizeof(JobDev) * n_jobs + sizeof(int2) * n_units, list_off, sizeof(list_off));
+  ICHK(hipMemcpyAsync(L.jobs_d, sp, sizeof(JobDev) * n_jobs, hipMemcpyHostToDevice, stream));
+  ICHK(hipMemcpyAsync(L.units_d, sp + sizeof(JobDev) * n_jobs, sizeof(int2) * n_units,
+                      hipMemcpyHostToDevice, stream));
+  ICHK(hipMemcpyAsync(L.list_off_d, sp + sizeof(JobDev) * n_jobs + sizeof(int2) * n_units,
+                      sizeof(list_off), hipMemcpyHostToDevice, stream));
+  ICHK(hipEventRecord(L.staged, stream));
+
+  // raising the dynamic LDS limit is advisory on this runtime
+  if (set_persistent_lds_limit(cfg.path, cfg.block, lds) != hipSuccess) (void)hipGetLastError();
+  const int occ = persistent_occupancy(cfg.path, cfg.block, lds);
+  if (occ <= 0) {
+    set_error("persistent kernel cannot be resident with %zu bytes of LDS", lds);
+    return ISING_ERR_UNSUPPORTED;
+  }
+  const int cus = std::max(device_cu_count(), 1);
+  LaunchPersistent lp;
+  lp.jobs = L.jobs_d;
+  lp.units = L.units_d;
+  lp.list_off = L.list_off_d;
+  lp.ctr = L.ctr_d;
+  lp.grid = std::min(n_units, cus * occ);
+  lp.lds_bytes = lds;
+  lp.planes = planes;
+
+  auto enqueue = [&](hipStream_t s) -> hipError_t {
+    hipError_t e = launch_fill_i32(L.ctr_d, 0, 8, s);
+    if (e != hipSuccess) return e;
+    e = cfg.path == ISING_PATH_MSC ? launch_msc(lp, cfg.block, s) : launch_field(lp, cfg.block, s);
+    if (e != hipSuccess) return e;
+    return launch_argmax(L.jobs_d, n_jobs, s);
+  };
+
+  if (!L.ev0) ICHK(hipEventCreate(&L.ev0));
+  if (!L.ev1) ICHK(hipEventCreate(&L.ev1));
+  ICHK(hipEventRecord(L.ev0, stream));
+  if (use_graph && stream) {
+    char key[256];
+    snprintf(key, sizeof key, "%d/%d/%d/%d/%zu/%d/%d/%d/%p", cfg.path, cfg.block, cfg.G, planes,
+             lds, lp.grid, n_jobs, n_units, (void*)L.arena.base);
+    if (!L.exec || L.graph_key != key) {
+      if (L.exec) (void)hipGraphExecDestroy(L.exec);
+      if (L.graph) (void)hipGraphDestroy(L.graph);
+      L.exec = nullptr;
+      L.graph = nullptr;
+      ICHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = enqueue(stream);
+      hipGraph_t gr = nullptr;
+      hipError_t e2 = hipStreamEndCapture(stream, &gr);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        set_error("graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        return ISING_ERR_DEVICE;
+      }
+      L.graph = gr;
+      ICHK(hipGraphInstantiate(&L.exec, L.graph, nullptr, nullptr, 0));
+      L.graph_key = key;
+    }
+    ICHK(hipGraphLaunch(L.exec, stream));
+  } else {
+    ICHK(enqueue(stream));
+  }
+  ICHK(hipEventRecord(L.ev1, stream));
+  return ISING_OK;
+}
+
+}  // namespace ising
+
+using namespace ising;
+
+// ================================================================ C ABI
+extern "C" {
+
+const char* ising_status_string(int status) {
+  switch (status) {
+    case ISING_OK: return "ok";
+    case ISING_ERR_INVALID: return "invalid argument";
+    case ISING_ERR_NOMEM: return "out of memory";
+    case ISING_ERR_DEVICE: return "device error";
+    case ISING_ERR_STATE: return "invalid state";
+    case ISING_ERR_UNSUPPORTED: return "unsupported";
+    case ISING_ERR_TIMEOUT: return "timed out";
+    default: return "unknown status";
+  }
+}
+
+const char* ising_last_error(void) { return last_error(); }
+
+int ising_create(int32_t n, int64_t m, const int32_t* u, const int32_t* v, const int32_t* w,
+                 const int32_t* colour, ising_problem** out) {
+  if (!out) return ISING_ERR_INVALID;
+  ising_problem* p = nullptr;
+  try {
+    p = new ising_problem();
+  } catch (...) {
+    return ISING_ERR_NOMEM;
+  }
+  int rc;
+  try {
+    rc = compile_graph(n, m, u, v, w, colour, p->g);
+  } catch (...) {
+    rc = ISING_ERR_NOMEM;
+  }
+  if (rc != ISING_OK) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return ISING_OK;
+}
+
+int ising_destroy(ising_problem* p) {
+  if (!p) return ISING_OK;
+  if (p->run.valid && p->run.stream) (void)hipStreamSynchronize(p->run.stream);
+  DeviceGuard g(p->dg.device);
+  delete p;
+  return ISING_OK;
+}
+
+int ising_problem_info(const ising_problem* p, ising_info* out) {
+  if (!p || !out) return ISING_ERR_INVALID;
+  ising_info i;
+  i.n = p->g.n;
+  i.n_colours = p->g.C;
+  i.m = p->g.m;
+  i.total_weight = p->g.W;
+  i.kmax = p->g.kmax;
+  i.max_degree = p->g.max_deg;
+  i.unit_weights = p->g.unit ? 1 : 0;
+  i.n_padded = p->g.n_pad;
+  *out = i;
+  return ISING_OK;
+}
+
+int ising_colouring(const ising_problem* p, int32_t* colour) {
+  if (!p || !colour) return ISING_ERR_INVALID;
+  memcpy(colour, p->g.colour.data(), sizeof(int32_t) * (size_t)p->g.n);
+  return ISING_OK;
+}
+
+int ising_eval_cut(const ising_problem* p, const int8_t* spins, int64_t* cut) {
+  if (!p || !spins || !cut) return ISING_ERR_INVALID;
+  int64_t c = 0;
+  for (int64_t e = 0; e < p->g.m; ++e)
+    if (spins[p->g.u[(size_t)e]] != spins[p->g.v[(size_t)e]]) c += p->g.w[(size_t)e];
+  *cut = c;
+  return ISING_OK;
+}
+
+int ising_threshold_table(const ising_schedule* s, int32_t kmax, uint64_t* out) {
+  if (!s || kmax < 1 || !out) return ISING_ERR_INVALID;
+  std::vector<double> beta;
+  IRET(eval_schedule(s, beta));
+  Table t;
+  IRET(build_table(beta, kmax, t));
+  for (int r = 0; r < t.S; ++r) {
+    const int len = t.len[(size_t)r];
+    for (int k = 1; k <= kmax; ++k) {
+      uint64_t q;
+      if (len == kAcceptAll) q = (uint64_t)1 << 32;
+      else if (k <= len) q = (uint64_t)t.tq[(size_t)(t.off[(size_t)r] + k - 1)] + 1;
+      else q = 0;
+      out[(size_t)r * kmax + (k - 1)] = q;
+    }
+  }
+  return ISING_OK;
+}
+
+int ising_set_initial_state(ising_problem* p, const int8_t* spins, int32_t n_replicas) {
+  if (!p) return ISING_ERR_INVALID;
+  if (!spins) {
+    p->init.clear();
+    p->init_R = 0;
+    return ISING_OK;
+  }
+  if (n_replicas < 1) return ISING_ERR_INVALID;
+  const size_t cnt = (size_t)n_replicas * (size_t)p->g.n;
+  for (size_t i = 0; i < cnt; ++i)
+    if (spins[i] != 1 && spins[i] != -1) {
+      set_error("initial spins must be +-1");
+      return ISING_ERR_INVALID;
+    }
+  p->init.assign(spins, spins + cnt);
+  p->init_R = n_replicas;
+  return ISING_OK;
+}
+
+int ising_set_trace(ising_problem* p, int32_t enable) {
+  if (!p) return ISING_ERR_INVALID;
+  p->trace = enable != 0;
+  return ISING_OK;
+}
+
+static int resolve_config(ising_problem* p, const Table& table, int R, const ising_tuning* t,
+                          PersistentConfig& cfg);
+
+int ising_anneal_tuned(ising_problem* p, const ising_schedule* s, int32_t n_replicas,
+                       uint64_t seed, const ising_tuning* tuning, void* stream) {
+  if (!p || !s || n_replicas < 1) return ISING_ERR_INVALID;
+  std::vector<double> beta;
+  IRET(eval_schedule(s, beta));
+  Table table;
+  IRET(build_table(beta, p->g.kmax, table));
+  IRET(ensure_device(p));
+  DeviceGuard dg(p->dg.device);
+  PersistentConfig cfg;
+  IRET(resolve_config(p, table, n_replicas, tuning, cfg));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  IRET(prepare_run(p, table, n_replicas, cfg, st));
+  RunBuffers& b = p->run;
+  if (cfg.path == ISING_PATH_PLAIN) {
+    PlainDev P;
+    memset(&P, 0, sizeof P);
+    P.row = p->dg.row;
+    P.adj = p->dg.adj;
+    P.wgt = p->dg.wgt;
+    P.grp = p->dg.grp;
+    P.n_pad = p->g.n_pad;
+    P.R = n_replicas;
+    P.W = (int32_t)p->g.W;
+    P.flags = (b.trace ? kJobTrace : 0);
+    P.tq = b.tq;
+    P.tq_off = b.tq_off;
+    P.tq_len = b.tq_len;
+    P.seed_lo = (uint32_t)seed;
+    P.seed_hi = (uint32_t)(seed >> 32);
+    P.init_spins = b.init_dev;
+    P.spins = b.spins;
+    P.field = b.field;
+    P.best = static_cast<int8_t*>(b.best);
+    P.energy = b.energy;
+    P.eacc = b.eacc;
+    P.best_cut = b.best_cut;
+    P.best_sweep = b.best_sweep;
+    P.snap = b.snap;
+    P.accepts = b.accepts;
+    P.trace = b.trace_buf;
+    static thread_local JobDev hjob;
+    hjob = make_job(p, table, n_replicas, seed, 0, table.S, cfg);
+    ICHK(hipMemcpy(b.job_dev, &hjob, sizeof(JobDev), hipMemcpyHostToDevice));
+    PlainPlan plan{table.S, p->g.C, p->g.cls.data()};
+    ICHK(hipEventRecord(b.ev0, st));
+    ICHK(launch_plain_anneal(P, plan, st));
+    ICHK(launch_argmax(b.job_dev, 1, st));
+    ICHK(hipEventRecord(b.ev1, st));
+  } else {
+    std::vector<JobSpec> js{JobSpec{p, &table, n_replicas, seed, 0, table.S}};
+    ICHK(hipEventRecord(b.ev0, st));
+    IRET(run_persistent(p->launcher, js, cfg, st, st != nullptr));
+    ICHK(hipEventRecord(b.ev1, st));
+  }
+  b.valid = true;
+  return ISING_OK;
+}
+
+int ising_anneal(ising_problem* p, const ising_schedule* s, int32_t n_replicas, uint64_t seed,
+                 void* stream) {
+  return ising_anneal_tuned(p, s, n_replicas, seed, nullptr, stream);
+}
+
+static int sync_results(ising_problem* p) {
+  if (!p) return ISING_ERR_INVALID;
+  if (!p->run.valid) {
+    set_error("no anneal has run on this problem");
+    return ISING_ERR_STATE;
+  }
+  DeviceGuard g(p->dg.device);
+  ICHK(hipStreamSynchronize(p->run.stream));
+  return ISING_OK;
+}
+
+int ising_cut(ising_problem* p, int64_t* best_cut, int32_t* best_replica, int64_t* per_replica) {
+  IRET(sync_results(p));
+  DeviceGuard g(p->dg.device);
+  RunBuffers& b = p->run;
+  unsigned long long key = 0;
+  ICHK(hipMemcpy(&key, b.argmax, sizeof key, hipMemcpyDeviceToHost));
+  if (per_replica) {
+    std::vector<int32_t> tmp((size_t)b.R);
+    ICHK(hipMemcpy(tmp.data(), b.best_cut, sizeof(int32_t) * b.R, hipMemcpyDeviceToHost));
+    for (int r = 0; r < b.R; ++r) per_replica[r] = tmp[(size_t)r];
+  }
+  const uint32_t hi = (uint32_t)(key >> 32), lo = (uint32_t)key;
+  if (best_cut) *best_cut = (int64_t)(int32_t)(hi ^ 0x80000000u);
+  if (best_replica) *best_replica = (int32_t)(0xFFFFFFFFu - lo);
+  return ISING_OK;
+}
+
+static int gather_state(ising_problem* p, const void* buf, int layout, int r,
+                        std::vector<int32_t>& out) {
+  RunBuffers& b = p->run;
+  out.assign((size_t)p->g.n, 0);
+  ICHK(launch_gather(buf, layout, b.R, p->g.n_pad, r, p->dg.pos, p->g.n, b.gather, b.stream));
+  ICHK(hipStreamSynchronize(b.stream));
+  ICHK(hipMemcpy(out.data(), b.gather, sizeof(int32_t) * (size_t)p->g.n, hipMemcpyDeviceToHost));
+  return ISING_OK;
+}
+
+int ising_best_state(ising_problem* p, int8_t* spins) {
+  if (!spins) return ISING_ERR_INVALID;
+  int32_t r = 0;
+  IRET(ising_cut(p, nullptr, &r, nullptr));
+  DeviceGuard g(p->dg.device);
+  std::vector<int32_t> tmp;
+  IRET(gather_state(p, p->run.best, p->run.layout_best, r, tmp));
+  for (int32_t v = 0; v < p->g.n; ++v) spins[v] = (int8_t)tmp[(size_t)v];
+  return ISING_OK;
+}
+
+int ising_replica_results(ising_problem* p, int32_t* best_sweep, int64_t* accepts,
+                          int64_t* final_energy) {
+  IRET(sync_results(p));
+  DeviceGuard g(p->dg.device);
+  RunBuffers& b = p->run;
+  if (best_sweep)
+    ICHK(hipMemcpy(best_sweep, b.best_sweep, sizeof(int32_t) * b.R, hipMemcpyDeviceToHost));
+  if (accepts) {
+    std::vector<unsigned long long> tmp((size_t)b.R);
+    ICHK(hipMemcpy(tmp.data(), b.accepts, sizeof(unsigned long long) * b.R, hipMemcpyDeviceToHost));
+    for (int r = 0; r < b.R; ++r) accepts[r] = (int64_t)tmp[(size_t)r];
+  }
+  if (final_energy) {
+    std::vector<int32_t> tmp((size_t)b.R);
+    ICHK(hipMemcpy(tmp.data(), b.energy, sizeof(int32_t) * b.R, hipMemcpyDeviceToHost));
+    for (int r = 0; r < b.R; ++r) final_energy[r] = tmp[(size_t)r];
+  }
+  return ISING_OK;
+}
+
+int ising_replica_state(ising_problem* p, int32_t r, int8_t* best_spins, int8_t* final_spins) {
+  IRET(sync_results(p));
+  if (r < 0 || r >= p->run.R) return ISING_ERR_INVALID;
+  DeviceGuard g(p->dg.device);
+  RunBuffers& b = p->run;
+  std::vector<int32_t> tmp;
+  if (best_spins) {
+    IRET(gather_state(p, b.best, b.layout_best, r, tmp));
+    for (int32_t v = 0; v < p->g.n; ++v) best_spins[v] = (int8_t)tmp[(size_t)v];
+  }
+  if (final_spins) {
+    const void* src = b.path == ISING_PATH_PLAIN ? (const void*)b.spins : (const void*)b.save;
+    IRET(gather_state(p, src, b.layout_final, r, tmp));
+    for (int32_t v = 0; v < p->g.n; ++v) final_spins[v] = (int8_t)tmp[(size_t)v];
+  }
+  return ISING_OK;
+}
+
+int ising_replica_field(ising_problem* p, int32_t r, int32_t* field) {
+  IRET(sync_results(p));
+  if (r < 0 || r >= p->run.R || !field) return ISING_ERR_INVALID;
+  RunBuffers& b = p->run;
+  if (b.layout_field < 0) {
+    set_error("the multispin path keeps no field array");
+    return ISING_ERR_UNSUPPORTED;
+  }
+  DeviceGuard g(p->dg.device);
+  std::vector<int32_t> tmp;
+  const void* src = b.path == ISING_PATH_PLAIN ? (const void*)b.field : (const void*)b.save;
+  IRET(gather_state(p, src, b.layout_field, r, tmp));
+  memcpy(field, tmp.data(), sizeof(int32_t) * (size_t)p->g.n);
+  return ISING_OK;
+}
+
+int ising_energy_trace(ising_problem* p, int64_t* out) {
+  IRET(sync_results(p));
+  if (!out) return ISING_ERR_INVALID;
+  RunBuffers& b = p->run;
+  if (!b.trace_buf) {
+    set_error("tracing was not enabled for the last anneal");
+    return ISING_ERR_STATE;
+  }
+  DeviceGuard g(p->dg.device);
+  std::vector<int32_t> tmp((size_t)b.S * b.R);
+  ICHK(hipMemcpy(tmp.data(), b.trace_buf, sizeof(int32_t) * tmp.size(), hipMemcpyDeviceToHost));
+  for (int r = 0; r < b.R; ++r)
+    for (int t = 0; t < b.S; ++t) out[(size_t)r * b.S + t] = tmp[(size_t)t * b.R + r];
+  return ISING_OK;
+}
+
+int ising_last_anneal_ms(ising_problem* p, double* ms) {
+  IRET(sync_results(p));
+  if (!ms) return ISING_ERR_INVALID;
+  float f = 0;
+  ICHK(hipEventElapsedTime(&f, p->run.ev0, p->run.ev1));
+  *ms = f;
+  return ISING_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- config
+int tune_lookup(const ising::HostGraph& g, const ising::Table& t, int R, ising::PersistentConfig& c);
+
+static int resolve_config(ising_problem* p, const Table& table, int R, const ising_tuning* t,
+                          PersistentConfig& cfg) {
+  const int path = t ? t->path : ISING_PATH_AUTO;
+  if (path == ISING_PATH_AUTO) {
+    if (tune_lookup(p->g, table, R, cfg) != ISING_OK) cfg = heuristic_config(p->g, table, R);
+    return ISING_OK;
+  }
+  cfg.path = path;
+  cfg.G = t->replicas_per_block > 0 ? t->replicas_per_block : 1;
+  cfg.block = t->block_threads > 0 ? t->block_threads : (path == ISING_PATH_MSC ? 256 : 1024);
+  if (path == ISING_PATH_PLAIN) {
+    cfg.G = 1;
+    cfg.block = 256;
+  }
+  return check_config(p->g, table, R, cfg);
+}

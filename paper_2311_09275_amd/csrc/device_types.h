@@ -1,0 +1,107 @@
+// device_types.h -- plain structs shared by the host runtime and the HIP
+// kernels (no HIP or torch types).  All device arrays use the compiled
+// problem's colour-major vertex order: each colour class occupies a run of
+// positions padded to a multiple of four, so every aligned quadruple of
+// positions is one random-number run ("group") of at most four same-colour
+// vertices.
+#pragma once
+#include <stdint.h>
+
+namespace ising {
+
+// Per-group word: bits 0..27 = original id of the group's first vertex (the
+// Philox counter word 0), bits 28..29 = number of real vertices - 1.
+constexpr int32_t kGroupLeaderMask = 0x0FFFFFFF;
+constexpr int kGroupCountShift = 28;
+
+// Philox counter word 3 ("tag") of each purpose.
+constexpr uint32_t kTagSweep = 0;
+constexpr uint32_t kTagInit = 1;
+
+// Threshold row length meaning "beta_t == 0: accept every move".
+constexpr int32_t kAcceptAll = -1;
+
+constexpr int kMaxReplicasPerBlock = 16;   // FIELD path
+constexpr int kMaxWordsPerBlock = 4;       // MSC path
+constexpr int kMaxThresholdRow = 1024;     // LDS paths stage <= this many
+constexpr int kMaxLdsDegree = 255;         // LDS paths pack degrees in 8 bits
+
+enum JobFlags : int32_t {
+  kJobTrace = 1,      // write E after every sweep to trace[t*R + r]
+  kJobInitGiven = 2,  // initial spins come from init_spins
+};
+
+// One anneal of one problem for the persistent kernels.  Units of work are
+// (job, replica block) pairs; a workgroup owns its block's replicas for all
+// sweeps [t_begin, t_end) with the whole state resident in LDS.
+struct JobDev {
+  // graph, colour-major and padded
+  const int32_t* row;    // [n_pad+1]
+  const int32_t* adj;    // [2m] neighbour position
+  const int32_t* wgt;    // [2m] MaxCut weight w (coupling J = -w)
+  const uint32_t* adjm;  // [2m] (position << 1) | (w > 0), unit weights only
+  const int2* aw;        // [2m] {neighbour position, w}
+  const int32_t* grp;    // [n_pad/4] group words
+  const int32_t* gbase;  // [n_pad/4] first adjacency entry of the group
+  const uint32_t* gdeg;  // [n_pad/4] degrees of the group's four slots, 8 bits each
+  const int32_t* cls;    // [2*C] first and end group of each class
+  int32_t n_pad, n_colours;
+  int32_t W;             // sum of weights
+  int32_t M;             // edges
+  // schedule
+  const uint32_t* tq;    // thresholds minus one, rows back to back
+  const int32_t* tq_off; // [S] row offsets into tq
+  const int32_t* tq_len; // [S] row lengths, or kAcceptAll
+  int32_t S, t_begin, t_end, flags;
+  int32_t kw;            // longest row (LDS row capacity)
+  // run
+  uint32_t seed_lo, seed_hi;
+  int32_t R;             // replicas
+  int32_t G;             // FIELD: replicas per block; MSC: words per block
+  const int8_t* init_spins;  // [R][n_pad] +-1, positions order
+  // state and outputs
+  int32_t* save;         // FIELD: [R][n_pad] packed (h<<1)|bit; MSC: [nw][n_pad] words
+  void* best;            // FIELD: int8 [R][n_pad]; MSC: uint32 [nw][n_pad]
+  int32_t* best_cut;     // [R]
+  int32_t* best_sweep;   // [R]
+  int32_t* energy;       // [R]
+  unsigned long long* accepts;  // [R]
+  int32_t* trace;        // [S][R] when kJobTrace
+  unsigned long long* argmax;   // [1] packed (best cut, replica) maximum
+};
+
+// Arguments of the per-colour-pass kernels (state in HBM, [position][R]).
+struct PlainDev {
+  const int32_t* row;
+  const int32_t* adj;
+  const int32_t* wgt;
+  const int32_t* grp;
+  int32_t n_pad, R, W, flags;
+  const uint32_t* tq;
+  const int32_t* tq_off;
+  const int32_t* tq_len;
+  uint32_t seed_lo, seed_hi;
+  const int8_t* init_spins;  // [R][n_pad] or null
+  int8_t* spins;         // [n_pad][R]
+  int32_t* field;        // [n_pad][R]
+  int8_t* best;          // [n_pad][R]
+  int32_t* energy;       // [R]
+  int32_t* eacc;         // [R] energy change of the current sweep
+  int32_t* best_cut;     // [R]
+  int32_t* best_sweep;   // [R]
+  int32_t* snap;         // [R] last improving sweep (-1 = initial state)
+  unsigned long long* accepts;  // [R]
+  int32_t* trace;        // [S][R]
+};
+
+// Layouts understood by the state gather kernel.
+enum StateLayout : int32_t {
+  kLayoutNR_I8 = 0,      // int8 [n_pad][R]
+  kLayoutRN_I8 = 1,      // int8 [R][n_pad]
+  kLayoutRN_Spin = 2,    // int32 packed [R][n_pad] -> bit 0 as +-1
+  kLayoutRN_Field = 3,   // int32 packed [R][n_pad] -> value >> 1
+  kLayoutNR_I32 = 4,     // int32 [n_pad][R]
+  kLayoutWords = 5,      // uint32 [R/32][n_pad] -> bit r%32 as +-1
+};
+
+}  // namespace ising

@@ -1,0 +1,46 @@
+// kernels.h -- host-side entry points of the HIP kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "device_types.h"
+
+namespace ising {
+
+// Colour classes of one problem for the per-pass launches.
+struct PlainPlan {
+  int S;             // sweeps
+  int C;             // colours
+  const int32_t* cls;  // host [2*C] first and end group of each class
+};
+
+// One persistent launch (FIELD or MSC) over a unit list.
+struct LaunchPersistent {
+  const JobDev* jobs;      // device [jobs]
+  const int2* units;       // device [units]: (job, replica block)
+  const int32_t* list_off; // device [9]: unit lists by XCD
+  int32_t* ctr;            // device [8]: list cursors, zero before launch
+  int grid;
+  size_t lds_bytes;        // dynamic LDS per workgroup
+  int planes;              // MSC: bit planes of the unsatisfied-bond counter
+};
+
+hipError_t launch_plain_anneal(const PlainDev& P, const PlainPlan& plan, hipStream_t s);
+hipError_t launch_field(const LaunchPersistent& L, int block, hipStream_t s);
+hipError_t launch_msc(const LaunchPersistent& L, int block, hipStream_t s);
+// Resident workgroups per CU of a persistent kernel (path 2 = FIELD, 3 = MSC).
+int persistent_occupancy(int path, int block, size_t lds_bytes);
+hipError_t set_persistent_lds_limit(int path, int block, size_t lds_bytes);
+// Per job: argmax over replicas of best_cut, packed into *argmax as
+// (best_cut + 2^31) << 32 | (2^32 - 1 - r): the lowest replica wins ties.
+hipError_t launch_argmax(const JobDev* jobs, int n_jobs, hipStream_t s);
+hipError_t launch_gather(const void* buf, int layout, int R, int n_pad, int r, const int32_t* pos,
+                         int n, int32_t* out, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t s);
+
+// Static LDS of the persistent kernels (bytes), for the LDS budget.
+constexpr size_t kFieldStaticLds = 512;
+constexpr size_t kMscStaticLds = 4096;
+
+}  // namespace ising

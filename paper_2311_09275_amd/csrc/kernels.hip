@@ -1,0 +1,1000 @@
+// kernels.hip -- gfx950 kernels of the many-replica Metropolis annealer.
+//
+// Method (one replica): visit colour classes 0..C-1; for each vertex i of
+// the class compute k = s_i h_i (flipping s_i changes E by 2k); accept when
+// k <= 0, otherwise when the u32 draw is below Tq(beta_t, k); on a flip add
+// -2 w_ij s_i(new) to every neighbour's field.  The classes come from a
+// proper colouring, so all vertices of one class are updated in parallel
+// without races on their own state; pushes into neighbour fields are
+// integer atomics and therefore order independent.  The best cut is taken
+// over end-of-sweep states (strict improvement).
+//
+// Random numbers: word j of Philox4x32-10 with key = seed and counter =
+// (leader, t, r, tag) serves the j-th vertex of a group -- four consecutive
+// same-colour vertices.  One block call therefore feeds four attempts of one
+// replica, which lets a single replica be a unit of parallel work.
+//
+// Three kernel families compute identical results:
+//   plain  state in HBM, [position][replica] so a wave's 64 lanes touch 64
+//          consecutive replicas; one launch per colour pass.
+//   field  persistent: a workgroup owns G replicas of one problem for all
+//          sweeps, the packed word (h << 1) | spin_bit of every vertex lives
+//          in LDS; only workgroup barriers separate colour passes.
+//   msc    persistent multispin: bit b of a 32-bit word is the spin of
+//          replica 32w+b; unsatisfied bonds of 32 replicas are counted with
+//          bit-sliced adders, no field array; +-1 weights only.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_types.h"
+#include "kernels.h"
+
+namespace ising {
+namespace {
+
+// ---------------------------------------------------------------- Philox
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
+// products; key advanced by the Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                          uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// Pointers fetched from a descriptor are generic; re-qualifying them as
+// global lets the compiler emit global (not flat) memory instructions.
+#define GLOBAL_AS __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const GLOBAL_AS T* gconst(const T* p) {
+  return (const GLOBAL_AS T*)p;
+}
+template <class T>
+__device__ __forceinline__ GLOBAL_AS T* gmut(T* p) {
+  return (GLOBAL_AS T*)p;
+}
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pick(const uint4& x, int j) {
+  return j == 0 ? x.x : j == 1 ? x.y : j == 2 ? x.z : x.w;
+}
+
+// ---------------------------------------------------------------- waves
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Accept test for k > 0 against a threshold row holding Tq-1 for
+// k = 1..len (len = kAcceptAll when beta = 0).
+__device__ __forceinline__ bool accept_pos(int k, int len, uint32_t draw,
+                                           const uint32_t* row) {
+  return len < 0 || (k <= len && draw <= row[k - 1]);
+}
+
+// Encode four +-1 spins (bit set = +1) as four int8 bytes.
+__device__ __forceinline__ uint32_t spins_to_bytes(uint32_t bits4) {
+  uint32_t out = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) out |= ((bits4 >> j) & 1u ? 0x01u : 0xFFu) << (8 * j);
+  return out;
+}
+
+// ================================================================ plain
+// Grid: one lane per (group, replica), replica fastest.
+
+__global__ void k_plain_init(PlainDev P) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n_grp = P.n_pad >> 2;
+  if (idx >= (int64_t)n_grp * P.R) return;
+  const int g = (int)(idx / P.R), r = (int)(idx - (int64_t)g * P.R);
+  const int gw = P.grp[g];
+  const int cnt = (gw >> kGroupCountShift) + 1;
+  uint32_t bits = 0;
+  if (P.init_spins) {
+    for (int j = 0; j < cnt; ++j)
+      bits |= (P.init_spins[(int64_t)r * P.n_pad + 4 * g + j] > 0 ? 1u : 0u) << j;
+  } else {
+    const uint4 x = philox10(gw & kGroupLeaderMask, 0, r, kTagInit, P.seed_lo, P.seed_hi);
+    bits = (x.x >> 31) | ((x.y >> 31) << 1) | ((x.z >> 31) << 2) | ((x.w >> 31) << 3);
+  }
+  for (int j = 0; j < 4; ++j)
+    P.spins[(int64_t)(4 * g + j) * P.R + r] = (j >= cnt || ((bits >> j) & 1u)) ? 1 : -1;
+}
+
+// h_p = -sum_q w_pq s_q, and the energy sum -1/2 sum_p s_p h_p per replica.
+__global__ void k_plain_fields(PlainDev P) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)P.n_pad * P.R) return;
+  const int p = (int)(idx / P.R), r = (int)(idx - (int64_t)p * P.R);
+  int h = 0;
+  for (int a = P.row[p]; a < P.row[p + 1]; ++a)
+    h -= P.wgt[a] * (int)P.spins[(int64_t)P.adj[a] * P.R + r];
+  P.field[idx] = h;
+  const int sh = (int)P.spins[idx] * h;
+  if (sh != 0) atomicAdd(&P.eacc[r], sh);
+}
+
+__global__ void k_plain_init_best(PlainDev P) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= P.R) return;
+  const int E = -P.eacc[r] / 2;
+  P.eacc[r] = 0;
+  P.energy[r] = E;
+  P.best_cut[r] = (P.W - E) / 2;
+  P.best_sweep[r] = -1;
+  P.snap[r] = -1;
+  P.accepts[r] = 0;
+}
+
+// One colour pass of sweep t over the groups [g0, g1).
+__global__ void k_plain_sweep(PlainDev P, int t, int g0, int g1) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)(g1 - g0) * P.R) return;
+  const int gl = (int)(idx / P.R), r = (int)(idx - (int64_t)gl * P.R);
+  const int g = g0 + gl;
+  const int gw = P.grp[g];
+  const int cnt = (gw >> kGroupCountShift) + 1;
+  const int len = P.tq_len[t];
+  const uint32_t* row = P.tq + P.tq_off[t];
+  const bool snap = P.snap[r] == t - 1;
+  int s[4], k[4];
+  bool need = false;
+  for (int j = 0; j < 4; ++j) {
+    if (j < cnt) {
+      const int64_t o = (int64_t)(4 * g + j) * P.R + r;
+      s[j] = P.spins[o];
+      k[j] = s[j] * P.field[o];
+      if (snap) P.best[o] = (int8_t)s[j];
+      need |= k[j] > 0 && k[j] <= len;
+    }
+  }
+  uint4 x = make_uint4(0, 0, 0, 0);
+  if (need) x = philox10(gw & kGroupLeaderMask, t, r, kTagSweep, P.seed_lo, P.seed_hi);
+  int dE = 0, nacc = 0;
+  for (int j = 0; j < cnt; ++j) {
+    if (k[j] <= 0 || accept_pos(k[j], len, pick(x, j), row)) {
+      const int p = 4 * g + j;
+      const int sn = -s[j];
+      P.spins[(int64_t)p * P.R + r] = (int8_t)sn;
+      dE += 2 * k[j];
+      ++nacc;
+      for (int a = P.row[p]; a < P.row[p + 1]; ++a)
+        atomicAdd(&P.field[(int64_t)P.adj[a] * P.R + r], -2 * P.wgt[a] * sn);
+    }
+  }
+  if (dE != 0) atomicAdd(&P.eacc[r], dE);
+  if (nacc != 0) atomicAdd(&P.accepts[r], (unsigned long long)nacc);
+}
+
+// End of sweep t: energy, cut, strict best update.
+__global__ void k_plain_eos(PlainDev P, int t, int S) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= P.R) return;
+  const int E = P.energy[r] + P.eacc[r];
+  P.eacc[r] = 0;
+  P.energy[r] = E;
+  const int cut = (P.W - E) / 2;
+  if (cut > P.best_cut[r]) {
+    P.best_cut[r] = cut;
+    P.best_sweep[r] = t;
+    P.snap[r] = t;
+  }
+  if (P.flags & kJobTrace) P.trace[(int64_t)t * P.R + r] = E;
+  (void)S;
+}
+
+// The last sweep improved: its end state is the best state.
+__global__ void k_plain_flush(PlainDev P, int last) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)P.n_pad * P.R) return;
+  const int r = (int)(idx % P.R);
+  if (P.snap[r] == last) P.best[idx] = P.spins[idx];
+}
+
+// ================================================================ field
+// Persistent kernel: workgroups pull (job, replica block) units from eight
+// lists (one per XCD, by blockIdx % 8) and steal from the others once their
+// own is empty.  Unit processing is entirely workgroup-local.
+//
+// LDS of a unit: the state words of its G replicas, two threshold rows
+// (current and next sweep), and the group descriptors: leader word,
+// adjacency base and four 8-bit slot degrees per group.
+
+struct FieldShared {
+  int32_t unit;
+  int32_t eacc[4][kMaxReplicasPerBlock];  // [sweep % 3] energy change; [3] init
+  int32_t nacc[kMaxReplicasPerBlock];
+};
+
+struct UnitLds {
+  uint32_t* tq;     // [2][kw]
+  int32_t* gword;   // [n_grp]
+  int32_t* gbase;   // [n_grp]
+  uint32_t* gdeg;   // [n_grp]
+};
+
+__device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int kw, int n_grp) {
+  UnitLds u;
+  u.tq = smem + words;
+  u.gword = reinterpret_cast<int32_t*>(u.tq + 2 * kw);
+  u.gbase = u.gword + n_grp;
+  u.gdeg = reinterpret_cast<uint32_t*>(u.gbase + n_grp);
+  return u;
+}
+
+__device__ __forceinline__ void stage_row(const JobDev& J, int t, uint32_t* buf) {
+  if (t >= J.t_end) return;
+  const int len = gconst(J.tq_len)[t];
+  const GLOBAL_AS uint32_t* src = gconst(J.tq) + gconst(J.tq_off)[t];
+  for (int i = threadIdx.x; i < len; i += blockDim.x) buf[(t & 1) * J.kw + i] = src[i];
+}
+
+__device__ __forceinline__ void stage_groups(const JobDev& J, const UnitLds& u) {
+  const int n_grp = J.n_pad >> 2;
+  const GLOBAL_AS int32_t* grp = gconst(J.grp);
+  const GLOBAL_AS int32_t* gbase = gconst(J.gbase);
+  const GLOBAL_AS uint32_t* gdeg = gconst(J.gdeg);
+  for (int i = threadIdx.x; i < n_grp; i += blockDim.x) {
+    u.gword[i] = grp[i];
+    u.gbase[i] = gbase[i];
+    u.gdeg[i] = gdeg[i];
+  }
+}
+
+__device__ __forceinline__ int next_unit(const int32_t* list_off, int32_t* ctr, int& tried) {
+  const int home = blockIdx.x & 7;
+  while (tried < 8) {
+    const int L = (home + tried) & 7;
+    const int i = atomicAdd(&ctr[L], 1);
+    if (list_off[L] + i < list_off[L + 1]) return list_off[L] + i;
+    ++tried;
+  }
+  return -1;
+}
+
+// Flip pushes of one group: slot j (flag bit j of fm) adds sgn_j * 4 * w to
+// the packed word of each neighbour.  The first four adjacency entries of
+// every flipped slot are loaded before any atomic is issued.
+__device__ __forceinline__ void push_group(int32_t* st, const GLOBAL_AS i32x2* __restrict__ aw, int base,
+                                           uint32_t dg, uint32_t fm, const int (&w)[4]) {
+  int o[4], d[4];
+  int acc = base;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    d[j] = (int)((dg >> (8 * j)) & 255u);
+    o[j] = acc;
+    acc += d[j];
+  }
+  i32x2 q[4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (((fm >> j) & 1u) && e < d[j]) q[j][e] = aw[o[j] + e];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if ((fm >> j) & 1u) {
+      const int sgn4 = (w[j] & 1) ? -4 : 4;  // (-2 w s_new) << 1 = sgn4 * w
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (e < d[j]) atomicAdd(&st[q[j][e].x], sgn4 * q[j][e].y);
+      for (int e = 4; e < d[j]; ++e) {
+        const i32x2 qq = aw[o[j] + e];
+        atomicAdd(&st[qq.x], sgn4 * qq.y);
+      }
+    }
+  }
+}
+
+template <int BLOCK>
+__device__ void field_unit(const JobDev& J, const int block, int32_t* smem, FieldShared& sh) {
+  const int G = J.G;
+  const int TPR = BLOCK / G;  // threads per replica, a multiple of 64
+  const int tid = threadIdx.x;
+  const int rl = tid / TPR, lt = tid - rl * TPR;
+  const int r = block * G + rl;
+  const bool live = r < J.R;
+  const int n_pad = J.n_pad, n_grp = n_pad >> 2;
+  int32_t* st = smem + rl * n_pad;
+  const UnitLds U = unit_lds(reinterpret_cast<uint32_t*>(smem), G * n_pad, J.kw, n_grp);
+  const uint32_t k0 = J.seed_lo, k1 = J.seed_hi;
+  const int C = J.n_colours;
+  const int W = J.W;
+  const GLOBAL_AS i32x2* __restrict__ aw = gconst(reinterpret_cast<const i32x2*>(J.aw));
+
+  if (tid < 4 * kMaxReplicasPerBlock) (&sh.eacc[0][0])[tid] = 0;
+  if (tid < kMaxReplicasPerBlock) sh.nacc[tid] = 0;
+
+  // ---- state in: initial draw, or the words saved by the previous chunk
+  const bool fresh = J.t_begin == 0;
+  if (live) {
+    for (int g = lt; g < n_grp; g += TPR) {
+      int4 w4;
+      if (fresh) {
+        const int gw = J.grp[g];
+        const int cnt = (gw >> kGroupCountShift) + 1;
+        uint32_t bits;
+        if (J.flags & kJobInitGiven) {
+          bits = 0;
+          for (int j = 0; j < cnt; ++j)
+            bits |= (J.init_spins[(int64_t)r * n_pad + 4 * g + j] > 0 ? 1u : 0u) << j;
+        } else {
+          const uint4 x = philox10(gw & kGroupLeaderMask, 0, r, kTagInit, k0, k1);
+          bits = (x.x >> 31) | ((x.y >> 31) << 1) | ((x.z >> 31) << 2) | ((x.w >> 31) << 3);
+        }
+        w4.x = (int)(bits & 1u);
+        w4.y = cnt > 1 ? (int)((bits >> 1) & 1u) : 0;
+        w4.z = cnt > 2 ? (int)((bits >> 2) & 1u) : 0;
+        w4.w = cnt > 3 ? (int)((bits >> 3) & 1u) : 0;
+      } else {
+        w4 = *reinterpret_cast<const int4*>(J.save + (int64_t)r * n_pad + 4 * g);
+      }
+      *reinterpret_cast<int4*>(st + 4 * g) = w4;
+    }
+  }
+  stage_row(J, J.t_begin, U.tq);
+  stage_groups(J, U);
+  __syncthreads();
+
+  int E, best_cut, best_sweep;
+  bool snap;
+  if (fresh) {
+    // fields from scratch: h_p = -sum_q w_pq s_q.  Only bit 0 of other
+    // words is read while fields are written, and that bit is unchanged.
+    int part = 0;
+    if (live) {
+      for (int p = lt; p < n_pad; p += TPR) {
+        const int g = p >> 2, j = p & 3;
+        const uint32_t dg = U.gdeg[g];
+        int a = U.gbase[g];
+        for (int i = 0; i < j; ++i) a += (int)((dg >> (8 * i)) & 255u);
+        const int d = (int)((dg >> (8 * j)) & 255u);
+        int h = 0;
+        for (int e = 0; e < d; ++e) {
+          const i32x2 q = aw[a + e];
+          h -= q.y * ((st[q.x] & 1) ? 1 : -1);
+        }
+        const int b = st[p] & 1;
+        st[p] = (h << 1) | b;
+        part += b ? h : -h;
+      }
+    }
+    part = wave_sum(part);
+    if ((tid & 63) == 0 && part != 0) atomicAdd(&sh.eacc[3][rl], part);
+    __syncthreads();
+    E = -sh.eacc[3][rl] / 2;
+    best_cut = (W - E) / 2;
+    best_sweep = -1;
+    snap = true;  // the initial state is written during sweep 0
+  } else {
+    E = live ? J.energy[r] : 0;
+    best_cut = live ? J.best_cut[r] : 0;
+    best_sweep = live ? J.best_sweep[r] : 0;
+    snap = false;
+  }
+
+  GLOBAL_AS int8_t* best = gmut(static_cast<int8_t*>(J.best)) + (int64_t)r * n_pad;
+  int dE = 0;
+  int nacc = 0;
+  for (int t = J.t_begin; t < J.t_end; ++t) {
+    const int len = gconst(J.tq_len)[t];
+    const uint32_t* row = U.tq + (t & 1) * J.kw;
+    for (int c = 0; c < C; ++c) {
+      if (c == C - 1) stage_row(J, t + 1, U.tq);
+      const int g0 = gconst(J.cls)[2 * c], g1 = gconst(J.cls)[2 * c + 1];
+      if (live) {
+        for (int g = g0 + lt; g < g1; g += TPR) {
+          const int gw = U.gword[g];
+          const int cnt = (gw >> kGroupCountShift) + 1;
+          const int4 w4 = *reinterpret_cast<const int4*>(st + 4 * g);
+          int w[4] = {w4.x, w4.y, w4.z, w4.w};
+          if (snap) {
+            const uint32_t bits = (w[0] & 1) | ((w[1] & 1) << 1) | ((w[2] & 1) << 2) | ((w[3] & 1) << 3);
+            *reinterpret_cast<GLOBAL_AS uint32_t*>(best + 4 * g) = spins_to_bytes(bits);
+          }
+          int k[4];
+          bool need = false;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int h = w[j] >> 1;
+            k[j] = (w[j] & 1) ? h : -h;
+            need |= j < cnt && k[j] > 0 && k[j] <= len;
+          }
+          uint4 x = make_uint4(0, 0, 0, 0);
+          if (need) x = philox10(gw & kGroupLeaderMask, t, r, kTagSweep, k0, k1);
+          uint32_t fm = 0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (j < cnt && (k[j] <= 0 || accept_pos(k[j], len, pick(x, j), row))) {
+              fm |= 1u << j;
+              w[j] ^= 1;
+              dE += 2 * k[j];
+              ++nacc;
+            }
+          }
+          if (fm) {
+            *reinterpret_cast<int4*>(st + 4 * g) = make_int4(w[0], w[1], w[2], w[3]);
+            push_group(st, aw, U.gbase[g], U.gdeg[g], fm, w);
+          }
+        }
+      }
+      if (c == C - 1) {
+        const int s = wave_sum(dE);
+        if ((tid & 63) == 0 && s != 0) atomicAdd(&sh.eacc[t % 3][rl], s);
+        dE = 0;
+      }
+      __syncthreads();
+    }
+    E += sh.eacc[t % 3][rl];
+    if (lt == 0) sh.eacc[(t + 2) % 3][rl] = 0;
+    const int cut = (W - E) / 2;
+    snap = cut > best_cut;
+    if (snap) {
+      best_cut = cut;
+      best_sweep = t;
+    }
+    if ((J.flags & kJobTrace) && lt == 0 && live) J.trace[(int64_t)t * J.R + r] = E;
+  }
+
+  // ---- state out
+  if (live) {
+    for (int g = lt; g < n_grp; g += TPR) {
+      const int4 w4 = *reinterpret_cast<const int4*>(st + 4 * g);
+      if (snap) {
+        const uint32_t bits = (w4.x & 1) | ((w4.y & 1) << 1) | ((w4.z & 1) << 2) | ((w4.w & 1) << 3);
+        *reinterpret_cast<GLOBAL_AS uint32_t*>(best + 4 * g) = spins_to_bytes(bits);
+      }
+      *reinterpret_cast<int4*>(J.save + (int64_t)r * n_pad + 4 * g) = w4;
+    }
+  }
+  const int na = wave_sum(nacc);
+  if ((tid & 63) == 0 && na != 0) atomicAdd(&sh.nacc[rl], na);
+  __syncthreads();
+  if (lt == 0 && live) {
+    const unsigned long long prev = fresh ? 0ull : J.accepts[r];
+    J.accepts[r] = prev + (unsigned long long)sh.nacc[rl];
+    J.energy[r] = E;
+    J.best_cut[r] = best_cut;
+    J.best_sweep[r] = best_sweep;
+  }
+}
+
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_field(const JobDev* __restrict__ jobs, const int2* __restrict__ units,
+        const int32_t* __restrict__ list_off, int32_t* __restrict__ ctr) {
+  extern __shared__ __align__(16) int32_t smem[];
+  __shared__ FieldShared sh;
+  int tried = 0;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) sh.unit = next_unit(list_off, ctr, tried);
+    __syncthreads();
+    const int u = sh.unit;
+    if (u < 0) break;
+    const int2 un = units[u];
+    const JobDev J = jobs[un.x];  // by value: fields stay in registers
+    field_unit<BLOCK>(J, un.y, smem, sh);
+  }
+}
+
+// ================================================================ msc
+// Unit = (job, block of G words); word w holds replicas 32w .. 32w+31.
+
+struct MscShared {
+  int32_t unit;
+  int32_t eacc[4][kMaxWordsPerBlock * 32];
+  int32_t E[kMaxWordsPerBlock * 32];
+  int32_t best_cut[kMaxWordsPerBlock * 32];
+  int32_t best_sweep[kMaxWordsPerBlock * 32];
+  uint32_t snap[kMaxWordsPerBlock];
+};
+
+constexpr int kMscPlanes = 5;  // degree <= 31
+
+// Add the 32 one-bit values of x into the bit-sliced counter U.
+__device__ __forceinline__ void slice_add(uint32_t (&U)[kMscPlanes], uint32_t x, int planes) {
+#pragma unroll
+  for (int b = 0; b < kMscPlanes; ++b) {
+    if (b < planes) {
+      const uint32_t c = U[b] & x;
+      U[b] ^= x;
+      x = c;
+    }
+  }
+}
+
+__device__ __forceinline__ int slice_get(const uint32_t (&U)[kMscPlanes], int bit, int planes) {
+  int u = 0;
+#pragma unroll
+  for (int b = 0; b < kMscPlanes; ++b)
+    if (b < planes) u |= (int)((U[b] >> bit) & 1u) << b;
+  return u;
+}
+
+// Lane layout inside a word slice: four lanes per group ("quad"), lane o of
+// the quad decides replicas 8o .. 8o+7 of the word; the four partial flip
+// masks are OR-combined with lane shuffles.
+__device__ __forceinline__ uint32_t quad_or(uint32_t v) {
+  v |= (uint32_t)__shfl_xor((int)v, 1, 64);
+  v |= (uint32_t)__shfl_xor((int)v, 2, 64);
+  return v;
+}
+
+// Sum over the lanes of a wave that share (lane & 3).
+__device__ __forceinline__ int quad_lane_sum(int v) {
+#pragma unroll
+  for (int off = 32; off >= 4; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Unsatisfied-bond counters of the four slots of a group: bit r of slice b
+// of U[j] is bit b of the number of bonds of slot j that replica r leaves
+// unsatisfied (w s_i s_j = +1).  Adjacency entries are loaded before use.
+__device__ __forceinline__ void group_unsat(const uint32_t* st, const GLOBAL_AS uint32_t* __restrict__ adjm,
+                                            int base, uint32_t dg, int cnt, const uint32_t (&S)[4],
+                                            uint32_t (&U)[4][kMscPlanes], int (&d)[4], int planes) {
+  int o[4];
+  int acc = base;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    d[j] = j < cnt ? (int)((dg >> (8 * j)) & 255u) : 0;
+    o[j] = acc;
+    acc += (int)((dg >> (8 * j)) & 255u);
+#pragma unroll
+    for (int b = 0; b < kMscPlanes; ++b) U[j][b] = 0;
+  }
+  uint32_t q[4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (e < d[j]) q[j][e] = adjm[o[j] + e];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (e < d[j]) slice_add(U[j], S[j] ^ st[q[j][e] >> 1] ^ ((q[j][e] & 1u) ? 0xFFFFFFFFu : 0u), planes);
+    for (int e = 4; e < d[j]; ++e) {
+      const uint32_t am = adjm[o[j] + e];
+      slice_add(U[j], S[j] ^ st[am >> 1] ^ ((am & 1u) ? 0xFFFFFFFFu : 0u), planes);
+    }
+  }
+}
+
+template <int BLOCK>
+__device__ void msc_unit(const JobDev& J, const int block, uint32_t* smem, MscShared& sh,
+                         const int planes) {
+  const int Gw = J.G;
+  const int TPR = BLOCK / Gw;
+  const int QPR = TPR >> 2;  // quads per word slice
+  const int tid = threadIdx.x;
+  const int wl = tid / TPR, lt = tid - wl * TPR;
+  const int o = lt & 3, gq = lt >> 2;
+  const int wi = block * Gw + wl;
+  const int r0 = 32 * wi;
+  const int rb = r0 + 8 * o;  // first replica decided by this lane
+  const bool live = r0 < J.R;
+  const int n_pad = J.n_pad, n_grp = n_pad >> 2;
+  uint32_t* st = smem + wl * n_pad;
+  const UnitLds U = unit_lds(smem, Gw * n_pad, J.kw, n_grp);
+  const uint32_t k0 = J.seed_lo, k1 = J.seed_hi;
+  const int C = J.n_colours;
+  const int W = J.W;
+  const bool fresh = J.t_begin == 0;
+  const GLOBAL_AS uint32_t* __restrict__ adjm = gconst(J.adjm);
+
+  for (int i = tid; i < 4 * kMaxWordsPerBlock * 32; i += BLOCK) (&sh.eacc[0][0])[i] = 0;
+
+  if (live) {
+    for (int g = gq; g < n_grp; g += QPR) {
+      uint32_t b[4] = {0, 0, 0, 0};
+      const int gw = J.grp[g];
+      const int cnt = (gw >> kGroupCountShift) + 1;
+      if (fresh) {
+        if (J.flags & kJobInitGiven) {
+          for (int i = 0; i < 8; ++i) {
+            const int r = rb + i;
+            if (r < J.R)
+              for (int j = 0; j < cnt; ++j)
+                b[j] |= (J.init_spins[(int64_t)r * n_pad + 4 * g + j] > 0 ? 1u : 0u) << (8 * o + i);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const uint4 x = philox10(gw & kGroupLeaderMask, 0, rb + i, kTagInit, k0, k1);
+            b[0] |= (x.x >> 31) << (8 * o + i);
+            b[1] |= (x.y >> 31) << (8 * o + i);
+            b[2] |= (x.z >> 31) << (8 * o + i);
+            b[3] |= (x.w >> 31) << (8 * o + i);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = j < cnt ? quad_or(b[j]) : 0u;
+        if (o == 0) *reinterpret_cast<uint4*>(st + 4 * g) = make_uint4(b[0], b[1], b[2], b[3]);
+      } else if (o == 0) {
+        *reinterpret_cast<uint4*>(st + 4 * g) = *reinterpret_cast<const uint4*>(
+            reinterpret_cast<const uint32_t*>(J.save) + (int64_t)wi * n_pad + 4 * g);
+      }
+    }
+  }
+  stage_row(J, J.t_begin, U.tq);
+  stage_groups(J, U);
+  __syncthreads();
+
+  GLOBAL_AS uint32_t* bestw = gmut(static_cast<uint32_t*>(J.best)) + (int64_t)wi * n_pad;
+  if (fresh) {
+    // E_r = sum_p u_{p,r} - M, with u the unsatisfied bonds at p.
+    int cnt8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (live) {
+      for (int g = gq; g < n_grp; g += QPR) {
+        const int cnt = (U.gword[g] >> kGroupCountShift) + 1;
+        const uint4 s4 = *reinterpret_cast<const uint4*>(st + 4 * g);
+        const uint32_t S[4] = {s4.x, s4.y, s4.z, s4.w};
+        uint32_t Uq[4][kMscPlanes];
+        int d[4];
+        group_unsat(st, adjm, U.gbase[g], U.gdeg[g], cnt, S, Uq, d, planes);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) cnt8[i] += slice_get(Uq[j], 8 * o + i, planes);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int s = quad_lane_sum(cnt8[i]);
+      if ((tid & 63) < 4 && s != 0) atomicAdd(&sh.eacc[3][wl * 32 + 8 * o + i], s);
+    }
+    __syncthreads();
+    if (lt < 32) {
+      const int e = sh.eacc[3][wl * 32 + lt] - J.M;
+      sh.E[wl * 32 + lt] = e;
+      sh.best_cut[wl * 32 + lt] = (W - e) / 2;
+      sh.best_sweep[wl * 32 + lt] = -1;
+    }
+    if (lt == 0) sh.snap[wl] = 0xFFFFFFFFu;
+  } else {
+    if (lt < 32) {
+      const int r = r0 + lt;
+      sh.E[wl * 32 + lt] = r < J.R ? J.energy[r] : 0;
+      sh.best_cut[wl * 32 + lt] = r < J.R ? J.best_cut[r] : 0;
+      sh.best_sweep[wl * 32 + lt] = r < J.R ? J.best_sweep[r] : 0;
+    }
+    if (lt == 0) sh.snap[wl] = 0;
+  }
+  __syncthreads();
+
+  int dE[8], nacc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    dE[i] = 0;
+    nacc[i] = 0;
+  }
+
+  for (int t = J.t_begin; t < J.t_end; ++t) {
+    const int len = gconst(J.tq_len)[t];
+    const uint32_t* row = U.tq + (t & 1) * J.kw;
+    const uint32_t snapm = sh.snap[wl];
+    const bool draw_needed = len > 0;  // otherwise no move with k > 0 can pass
+    for (int c = 0; c < C; ++c) {
+      if (c == C - 1) stage_row(J, t + 1, U.tq);
+      const int g0 = gconst(J.cls)[2 * c], g1 = gconst(J.cls)[2 * c + 1];
+      if (live) {
+        for (int g = g0 + gq; g < g1; g += QPR) {
+          const int gw = U.gword[g];
+          const int cnt = (gw >> kGroupCountShift) + 1;
+          const uint4 s4 = *reinterpret_cast<const uint4*>(st + 4 * g);
+          const uint32_t S[4] = {s4.x, s4.y, s4.z, s4.w};
+          if (snapm && o == 0) {
+            u32x4 b4 = *reinterpret_cast<const GLOBAL_AS u32x4*>(bestw + 4 * g);
+            b4.x = (b4.x & ~snapm) | (S[0] & snapm);
+            b4.y = (b4.y & ~snapm) | (S[1] & snapm);
+            b4.z = (b4.z & ~snapm) | (S[2] & snapm);
+            b4.w = (b4.w & ~snapm) | (S[3] & snapm);
+            *reinterpret_cast<GLOBAL_AS u32x4*>(bestw + 4 * g) = b4;
+          }
+          uint32_t Uq[4][kMscPlanes];
+          int d[4];
+          group_unsat(st, adjm, U.gbase[g], U.gdeg[g], cnt, S, Uq, d, planes);
+          uint32_t F[4] = {0, 0, 0, 0};
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            uint4 x = make_uint4(0, 0, 0, 0);
+            if (draw_needed) x = philox10(gw & kGroupLeaderMask, t, rb + i, kTagSweep, k0, k1);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if (j < cnt) {
+                const int k = d[j] - 2 * slice_get(Uq[j], 8 * o + i, planes);
+                const bool acc = k <= 0 || accept_pos(k, len, pick(x, j), row);
+                F[j] |= (acc ? 1u : 0u) << (8 * o + i);
+                dE[i] += acc ? 2 * k : 0;
+                nacc[i] += acc ? 1 : 0;
+              }
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) F[j] = quad_or(F[j]);
+          if (o == 0)
+            *reinterpret_cast<uint4*>(st + 4 * g) =
+                make_uint4(S[0] ^ F[0], S[1] ^ F[1], S[2] ^ F[2], S[3] ^ F[3]);
+        }
+      }
+      if (c == C - 1) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int s = quad_lane_sum(dE[i]);
+          if ((tid & 63) < 4 && s != 0) atomicAdd(&sh.eacc[t % 3][wl * 32 + 8 * o + i], s);
+          dE[i] = 0;
+        }
+      }
+      __syncthreads();
+    }
+    // end of sweep: the first 32 threads of each word slice own one replica
+    if (lt < 32) {
+      const int q = wl * 32 + lt;
+      const int r = r0 + lt;
+      const int e = sh.E[q] + sh.eacc[t % 3][q];
+      sh.eacc[(t + 2) % 3][q] = 0;
+      sh.E[q] = e;
+      const int cut = (W - e) / 2;
+      const bool imp = cut > sh.best_cut[q];
+      if (imp) {
+        sh.best_cut[q] = cut;
+        sh.best_sweep[q] = t;
+      }
+      // lanes 0..31 of the slice's first wave (TPR is a multiple of 64)
+      const unsigned long long bal = __ballot(imp);
+      if (lt == 0) sh.snap[wl] = (uint32_t)bal;
+      if ((J.flags & kJobTrace) && r < J.R) J.trace[(int64_t)t * J.R + r] = e;
+    }
+    __syncthreads();
+  }
+
+  const uint32_t snapm = sh.snap[wl];
+  if (live && o == 0) {
+    for (int g = gq; g < n_grp; g += QPR) {
+      const uint4 s4 = *reinterpret_cast<const uint4*>(st + 4 * g);
+      if (snapm) {
+        u32x4 b4 = *reinterpret_cast<const GLOBAL_AS u32x4*>(bestw + 4 * g);
+        b4.x = (b4.x & ~snapm) | (s4.x & snapm);
+        b4.y = (b4.y & ~snapm) | (s4.y & snapm);
+        b4.z = (b4.z & ~snapm) | (s4.z & snapm);
+        b4.w = (b4.w & ~snapm) | (s4.w & snapm);
+        *reinterpret_cast<GLOBAL_AS u32x4*>(bestw + 4 * g) = b4;
+      }
+      *reinterpret_cast<uint4*>(reinterpret_cast<uint32_t*>(J.save) + (int64_t)wi * n_pad + 4 * g) = s4;
+    }
+  }
+  // accepted flips per replica: reuse eacc[3] as the accumulator
+  __syncthreads();
+  if (tid < kMaxWordsPerBlock * 32) sh.eacc[3][tid] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int s = quad_lane_sum(nacc[i]);
+    if ((tid & 63) < 4 && s != 0) atomicAdd(&sh.eacc[3][wl * 32 + 8 * o + i], s);
+  }
+  __syncthreads();
+  if (lt < 32) {
+    const int q = wl * 32 + lt;
+    const int r = r0 + lt;
+    if (r < J.R) {
+      const unsigned long long prev = fresh ? 0ull : J.accepts[r];
+      J.accepts[r] = prev + (unsigned long long)(uint32_t)sh.eacc[3][q];
+      J.energy[r] = sh.E[q];
+      J.best_cut[r] = sh.best_cut[q];
+      J.best_sweep[r] = sh.best_sweep[q];
+    }
+  }
+}
+
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_msc(const JobDev* __restrict__ jobs, const int2* __restrict__ units,
+      const int32_t* __restrict__ list_off, int32_t* __restrict__ ctr, int planes) {
+  extern __shared__ __align__(16) uint32_t smem_u[];
+  __shared__ MscShared sh;
+  int tried = 0;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) sh.unit = next_unit(list_off, ctr, tried);
+    __syncthreads();
+    const int u = sh.unit;
+    if (u < 0) break;
+    const int2 un = units[u];
+    const JobDev J = jobs[un.x];  // by value: fields stay in registers
+    msc_unit<BLOCK>(J, un.y, smem_u, sh, planes);
+  }
+}
+
+// ================================================================ utils
+// Argmax over replicas of each job: key = (best_cut + 2^31 mod 2^32) << 32
+// | ~r, so the largest key is the largest cut with the lowest replica index
+// (the offset is a sign-bit flip in unsigned arithmetic).
+__global__ void k_argmax(const JobDev* jobs) {
+  const JobDev& J = jobs[blockIdx.x];
+  unsigned long long key = 0;
+  for (int r = threadIdx.x; r < J.R; r += blockDim.x) {
+    const unsigned long long k =
+        ((unsigned long long)((uint32_t)J.best_cut[r] ^ 0x80000000u) << 32) |
+        (unsigned long long)(0xFFFFFFFFu - (uint32_t)r);
+    key = k > key ? k : key;
+  }
+  key = wave_max_u64(key);
+  __shared__ unsigned long long part[16];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = key;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = part[i] > m ? part[i] : m;
+    *J.argmax = m;
+  }
+}
+
+__global__ void k_gather(const void* buf, int layout, int R, int n_pad, int r,
+                         const int32_t* pos, int n, int32_t* out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int p = pos[v];
+  int val = 0;
+  switch (layout) {
+    case kLayoutNR_I8: val = static_cast<const int8_t*>(buf)[(int64_t)p * R + r]; break;
+    case kLayoutRN_I8: val = static_cast<const int8_t*>(buf)[(int64_t)r * n_pad + p]; break;
+    case kLayoutRN_Spin:
+      val = (static_cast<const int32_t*>(buf)[(int64_t)r * n_pad + p] & 1) ? 1 : -1;
+      break;
+    case kLayoutRN_Field: val = static_cast<const int32_t*>(buf)[(int64_t)r * n_pad + p] >> 1; break;
+    case kLayoutNR_I32: val = static_cast<const int32_t*>(buf)[(int64_t)p * R + r]; break;
+    case kLayoutWords:
+      val = ((static_cast<const uint32_t*>(buf)[(int64_t)(r >> 5) * n_pad + p] >> (r & 31)) & 1u) ? 1 : -1;
+      break;
+  }
+  out[v] = val;
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t value, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = value;
+}
+
+template <int BLOCK>
+hipError_t launch_field_t(const LaunchPersistent& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_field<BLOCK>, dim3(L.grid), dim3(BLOCK), L.lds_bytes, s, L.jobs,
+                     L.units, L.list_off, L.ctr);
+  return hipGetLastError();
+}
+
+template <int BLOCK>
+hipError_t launch_msc_t(const LaunchPersistent& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_msc<BLOCK>, dim3(L.grid), dim3(BLOCK), L.lds_bytes, s, L.jobs,
+                     L.units, L.list_off, L.ctr, L.planes);
+  return hipGetLastError();
+}
+
+template <typename K>
+int occupancy_of(K kernel, int block, size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, lds) != hipSuccess) return 0;
+  return n;
+}
+
+inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+// ================================================================ launchers
+hipError_t launch_plain_anneal(const PlainDev& P, const PlainPlan& plan, hipStream_t s) {
+  const int B = 256;
+  const int n_grp = P.n_pad >> 2;
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(P.R, B)), dim3(B), 0, s, P.eacc, 0, (int64_t)P.R);
+  hipLaunchKernelGGL(k_plain_init, dim3(blocks_for((int64_t)n_grp * P.R, B)), dim3(B), 0, s, P);
+  hipLaunchKernelGGL(k_plain_fields, dim3(blocks_for((int64_t)P.n_pad * P.R, B)), dim3(B), 0, s, P);
+  hipLaunchKernelGGL(k_plain_init_best, dim3(blocks_for(P.R, B)), dim3(B), 0, s, P);
+  for (int t = 0; t < plan.S; ++t) {
+    for (int c = 0; c < plan.C; ++c) {
+      const int g0 = plan.cls[2 * c], g1 = plan.cls[2 * c + 1];
+      if (g1 > g0)
+        hipLaunchKernelGGL(k_plain_sweep, dim3(blocks_for((int64_t)(g1 - g0) * P.R, B)), dim3(B), 0,
+                           s, P, t, g0, g1);
+    }
+    hipLaunchKernelGGL(k_plain_eos, dim3(blocks_for(P.R, B)), dim3(B), 0, s, P, t, plan.S);
+  }
+  hipLaunchKernelGGL(k_plain_flush, dim3(blocks_for((int64_t)P.n_pad * P.R, B)), dim3(B), 0, s, P,
+                     plan.S - 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_field(const LaunchPersistent& L, int block, hipStream_t s) {
+  switch (block) {
+    case 256: return launch_field_t<256>(L, s);
+    case 512: return launch_field_t<512>(L, s);
+    case 1024: return launch_field_t<1024>(L, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_msc(const LaunchPersistent& L, int block, hipStream_t s) {
+  switch (block) {
+    case 256: return launch_msc_t<256>(L, s);
+    case 512: return launch_msc_t<512>(L, s);
+    case 1024: return launch_msc_t<1024>(L, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int persistent_occupancy(int path, int block, size_t lds_bytes) {
+  if (path == 2) {
+    switch (block) {
+      case 256: return occupancy_of(k_field<256>, 256, lds_bytes);
+      case 512: return occupancy_of(k_field<512>, 512, lds_bytes);
+      case 1024: return occupancy_of(k_field<1024>, 1024, lds_bytes);
+    }
+  } else {
+    switch (block) {
+      case 256: return occupancy_of(k_msc<256>, 256, lds_bytes);
+      case 512: return occupancy_of(k_msc<512>, 512, lds_bytes);
+      case 1024: return occupancy_of(k_msc<1024>, 1024, lds_bytes);
+    }
+  }
+  return 0;
+}
+
+hipError_t set_persistent_lds_limit(int path, int block, size_t lds_bytes) {
+  const void* f = nullptr;
+  if (path == 2) {
+    f = block == 256 ? (const void*)k_field<256> : block == 512 ? (const void*)k_field<512>
+                                                                : (const void*)k_field<1024>;
+  } else {
+    f = block == 256 ? (const void*)k_msc<256> : block == 512 ? (const void*)k_msc<512>
+                                                              : (const void*)k_msc<1024>;
+  }
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+}
+
+hipError_t launch_argmax(const JobDev* jobs, int n_jobs, hipStream_t s) {
+  hipLaunchKernelGGL(k_argmax, dim3(n_jobs), dim3(1024), 0, s, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const void* buf, int layout, int R, int n_pad, int r, const int32_t* pos,
+                         int n, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, 256)), dim3(256), 0, s, buf, layout, R, n_pad, r,
+                     pos, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(count, 256)), dim3(256), 0, s, p, value, count);
+  return hipGetLastError();
+}
+
+}  // namespace ising

@@ -1,0 +1,291 @@
+// problem.cpp -- problem compiler, schedules and acceptance thresholds.
+//
+// Problem (paper Sec. II.A): weighted MaxCut on n vertices, couplings
+// J = -w.  The compiled form is colour-major: colour classes in order, each
+// class's vertices in ascending id, each class padded to a multiple of four
+// positions so that aligned quadruples are the random-number groups.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <algorithm>
+
+#include "runtime.h"
+
+namespace ising {
+
+namespace {
+thread_local char g_err[512];
+}
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+const char* last_error() { return g_err; }
+
+// ---------------------------------------------------------------- graph
+int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, const int32_t* w,
+                  const int32_t* colour, HostGraph& g) {
+  if (n < 1 || n >= (1 << 28) || m < 0) {
+    set_error("n must be in [1, 2^28) and m >= 0");
+    return ISING_ERR_INVALID;
+  }
+  if (m > 0 && (!u || !v || !w)) {
+    set_error("edge arrays are NULL");
+    return ISING_ERR_INVALID;
+  }
+  if (m > (int64_t)1 << 30) {
+    set_error("too many edges");
+    return ISING_ERR_INVALID;
+  }
+  g = HostGraph();
+  g.n = n;
+  g.m = m;
+  g.u.assign(u, u + m);
+  g.v.assign(v, v + m);
+  g.w.assign(w, w + m);
+  int64_t abs_total = 0;
+  std::vector<uint64_t> keys((size_t)m);
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t a = u[e], b = v[e], we = w[e];
+    if (a < 0 || b < 0 || a >= n || b >= n) {
+      set_error("edge %lld: vertex id out of range", (long long)e);
+      return ISING_ERR_INVALID;
+    }
+    if (a == b) {
+      set_error("edge %lld: self loop", (long long)e);
+      return ISING_ERR_INVALID;
+    }
+    if (we == 0 || we > 32768 || we < -32768) {
+      set_error("edge %lld: weight must be nonzero with |w| <= 32768", (long long)e);
+      return ISING_ERR_INVALID;
+    }
+    abs_total += 2 * (int64_t)(we < 0 ? -we : we);
+    keys[(size_t)e] = ((uint64_t)(uint32_t)std::min(a, b) << 32) | (uint32_t)std::max(a, b);
+  }
+  if (abs_total >= ((int64_t)1 << 30)) {
+    set_error("sum of |w| over vertex neighbourhoods must stay below 2^30");
+    return ISING_ERR_INVALID;
+  }
+  std::sort(keys.begin(), keys.end());
+  if (std::adjacent_find(keys.begin(), keys.end()) != keys.end()) {
+    set_error("repeated undirected edge");
+    return ISING_ERR_INVALID;
+  }
+
+  // adjacency in original ids
+  std::vector<int32_t> deg((size_t)n + 1, 0);
+  for (int64_t e = 0; e < m; ++e) {
+    ++deg[(size_t)u[e] + 1];
+    ++deg[(size_t)v[e] + 1];
+  }
+  for (int32_t i = 0; i < n; ++i) deg[(size_t)i + 1] += deg[(size_t)i];
+  std::vector<int32_t> nb((size_t)(2 * m)), nw((size_t)(2 * m)), fill(deg.begin(), deg.end() - 1);
+  for (int64_t e = 0; e < m; ++e) {
+    nb[(size_t)fill[(size_t)u[e]]] = v[e];
+    nw[(size_t)fill[(size_t)u[e]]++] = w[e];
+    nb[(size_t)fill[(size_t)v[e]]] = u[e];
+    nw[(size_t)fill[(size_t)v[e]]++] = w[e];
+  }
+  g.W = 0;
+  for (int64_t e = 0; e < m; ++e) g.W += w[e];
+  g.kmax = 0;
+  g.max_deg = 0;
+  g.unit = true;
+  for (int32_t i = 0; i < n; ++i) {
+    int64_t s = 0;
+    for (int32_t a = deg[(size_t)i]; a < deg[(size_t)i + 1]; ++a) {
+      s += std::abs(nw[(size_t)a]);
+      if (std::abs(nw[(size_t)a]) != 1) g.unit = false;
+    }
+    g.kmax = std::max<int32_t>(g.kmax, (int32_t)s);
+    g.max_deg = std::max<int32_t>(g.max_deg, deg[(size_t)i + 1] - deg[(size_t)i]);
+  }
+
+  // colouring: supplied (checked proper) or greedy first fit in id order
+  g.colour.assign((size_t)n, 0);
+  if (colour) {
+    for (int32_t i = 0; i < n; ++i) {
+      if (colour[i] < 0 || colour[i] >= 1024) {
+        set_error("colour of vertex %d out of [0, 1024)", i);
+        return ISING_ERR_INVALID;
+      }
+      g.colour[(size_t)i] = colour[i];
+    }
+    for (int64_t e = 0; e < m; ++e)
+      if (colour[u[e]] == colour[v[e]]) {
+        set_error("colouring is not proper at edge %lld", (long long)e);
+        return ISING_ERR_INVALID;
+      }
+  } else {
+    std::vector<int32_t> mark((size_t)n + 2, -1);
+    for (int32_t i = 0; i < n; ++i) {
+      for (int32_t a = deg[(size_t)i]; a < deg[(size_t)i + 1]; ++a)
+        if (nb[(size_t)a] < i) mark[(size_t)g.colour[(size_t)nb[(size_t)a]]] = i;
+      int32_t c = 0;
+      while (mark[(size_t)c] == i) ++c;
+      g.colour[(size_t)i] = c;
+    }
+  }
+  g.C = 0;
+  for (int32_t i = 0; i < n; ++i) g.C = std::max(g.C, g.colour[(size_t)i] + 1);
+
+  // colour-major positions, classes padded to multiples of four
+  std::vector<int32_t> class_size((size_t)g.C, 0);
+  for (int32_t i = 0; i < n; ++i) ++class_size[(size_t)g.colour[(size_t)i]];
+  std::vector<int32_t> class_start((size_t)g.C + 1, 0);
+  for (int32_t c = 0; c < g.C; ++c)
+    class_start[(size_t)c + 1] = class_start[(size_t)c] + ((class_size[(size_t)c] + 3) & ~3);
+  g.n_pad = class_start[(size_t)g.C];
+  if ((int64_t)g.n_pad >= ((int64_t)1 << 28)) {
+    set_error("too many vertices after padding");
+    return ISING_ERR_INVALID;
+  }
+  g.pos.assign((size_t)n, 0);
+  g.orig.assign((size_t)g.n_pad, -1);
+  std::vector<int32_t> cur(class_start.begin(), class_start.end() - 1);
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t p = cur[(size_t)g.colour[(size_t)i]]++;
+    g.pos[(size_t)i] = p;
+    g.orig[(size_t)p] = i;
+  }
+  g.grp.assign((size_t)g.n_pad / 4, 0);
+  for (int32_t q = 0; q < g.n_pad / 4; ++q) {
+    int cnt = 0;
+    for (int j = 0; j < 4; ++j) cnt += g.orig[(size_t)(4 * q + j)] >= 0;
+    // padding only at class ends, so a group's first slot is always real
+    g.grp[(size_t)q] = g.orig[(size_t)(4 * q)] | ((cnt - 1) << kGroupCountShift);
+  }
+  g.cls.assign((size_t)(2 * g.C), 0);
+  for (int32_t c = 0; c < g.C; ++c) {
+    g.cls[(size_t)(2 * c)] = class_start[(size_t)c] / 4;
+    g.cls[(size_t)(2 * c + 1)] = class_start[(size_t)c + 1] / 4;
+  }
+  g.row.assign((size_t)g.n_pad + 1, 0);
+  for (int32_t p = 0; p < g.n_pad; ++p) {
+    const int32_t i = g.orig[(size_t)p];
+    g.row[(size_t)p + 1] = g.row[(size_t)p] + (i >= 0 ? deg[(size_t)i + 1] - deg[(size_t)i] : 0);
+  }
+  g.adj.assign((size_t)(2 * m), 0);
+  g.wgt.assign((size_t)(2 * m), 0);
+  g.adjm.assign((size_t)(2 * m), 0);
+  for (int32_t p = 0; p < g.n_pad; ++p) {
+    const int32_t i = g.orig[(size_t)p];
+    if (i < 0) continue;
+    int32_t o = g.row[(size_t)p];
+    for (int32_t a = deg[(size_t)i]; a < deg[(size_t)i + 1]; ++a, ++o) {
+      const int32_t q = g.pos[(size_t)nb[(size_t)a]];
+      g.adj[(size_t)o] = q;
+      g.wgt[(size_t)o] = nw[(size_t)a];
+      g.adjm[(size_t)o] = ((uint32_t)q << 1) | (nw[(size_t)a] > 0 ? 1u : 0u);
+    }
+  }
+  g.aw.assign((size_t)(4 * m), 0);
+  for (size_t a = 0; a < (size_t)(2 * m); ++a) {
+    g.aw[2 * a] = g.adj[a];
+    g.aw[2 * a + 1] = g.wgt[a];
+  }
+  g.gbase.assign((size_t)g.n_pad / 4, 0);
+  g.gdeg.assign((size_t)g.n_pad / 4, 0);
+  for (int32_t q = 0; q < g.n_pad / 4; ++q) {
+    g.gbase[(size_t)q] = g.row[(size_t)(4 * q)];
+    uint32_t packed = 0;
+    for (int j = 0; j < 4; ++j) {
+      const int32_t d = g.row[(size_t)(4 * q + j + 1)] - g.row[(size_t)(4 * q + j)];
+      packed |= (uint32_t)std::min(d, 255) << (8 * j);
+    }
+    g.gdeg[(size_t)q] = packed;
+  }
+  return ISING_OK;
+}
+
+// ---------------------------------------------------------------- schedule
+int eval_schedule(const ising_schedule* s, std::vector<double>& beta) {
+  if (!s || s->n_sweeps <= 0) {
+    set_error("schedule needs n_sweeps >= 1");
+    return ISING_ERR_INVALID;
+  }
+  const int S = s->n_sweeps;
+  beta.assign((size_t)S, 0.0);
+  if (s->kind == ISING_SCHED_EXPLICIT) {
+    if (!s->betas) {
+      set_error("explicit schedule without betas");
+      return ISING_ERR_INVALID;
+    }
+    for (int t = 0; t < S; ++t) beta[(size_t)t] = s->betas[t];
+  } else if (s->kind == ISING_SCHED_LINEAR || s->kind == ISING_SCHED_GEOMETRIC) {
+    const double b0 = s->beta0, b1 = s->beta1;
+    if (!std::isfinite(b0) || !std::isfinite(b1) || b0 < 0 || b1 < 0) {
+      set_error("beta0 and beta1 must be finite and >= 0");
+      return ISING_ERR_INVALID;
+    }
+    if (s->kind == ISING_SCHED_GEOMETRIC && (b0 <= 0 || b1 <= 0)) {
+      set_error("a geometric schedule needs beta0, beta1 > 0");
+      return ISING_ERR_INVALID;
+    }
+    for (int t = 0; t < S; ++t) {
+      if (S == 1) {
+        beta[(size_t)t] = b0;
+        continue;
+      }
+      const double frac = (double)t / (double)(S - 1);
+      beta[(size_t)t] = s->kind == ISING_SCHED_LINEAR ? b0 + (b1 - b0) * frac
+                                                      : b0 * std::pow(b1 / b0, frac);
+    }
+  } else {
+    set_error("unknown schedule kind %d", s->kind);
+    return ISING_ERR_INVALID;
+  }
+  for (int t = 0; t < S; ++t)
+    if (!std::isfinite(beta[(size_t)t]) || beta[(size_t)t] < 0) {
+      set_error("beta_%d is not finite and >= 0", t);
+      return ISING_ERR_INVALID;
+    }
+  return ISING_OK;
+}
+
+// Metropolis acceptance exp(-beta dE), dE = 2k, quantised to 32 bits:
+// a move with k > 0 is accepted iff a uniform u32 draw is below Tq.
+uint64_t threshold_q32(double beta, int64_t k) {
+  double x = -2.0 * (double)k;
+  x = x * beta;
+  const double a = std::exp(x);
+  if (a >= 1.0) return (uint64_t)1 << 32;
+  return (uint64_t)std::floor(std::ldexp(a, 32));
+}
+
+// Rows hold Tq - 1 for k = 1 .. len_t, where len_t is the last k with
+// Tq >= 1 (Tq falls with k); beta = 0 rows are marked accept-all.
+int build_table(const std::vector<double>& beta, int32_t kmax, Table& t) {
+  t = Table();
+  t.S = (int)beta.size();
+  t.off.assign((size_t)t.S, 0);
+  t.len.assign((size_t)t.S, 0);
+  for (int s = 0; s < t.S; ++s) {
+    t.off[(size_t)s] = (int32_t)t.tq.size();
+    if (beta[(size_t)s] == 0.0) {
+      t.len[(size_t)s] = kAcceptAll;
+      continue;
+    }
+    int32_t len = 0;
+    for (int64_t k = 1; k <= kmax; ++k) {
+      const uint64_t q = threshold_q32(beta[(size_t)s], k);
+      if (q == 0) break;
+      if ((int64_t)t.tq.size() >= kMaxTableEntries) {
+        set_error("threshold table exceeds 2^26 entries");
+        return ISING_ERR_INVALID;
+      }
+      t.tq.push_back((uint32_t)(q - 1));
+      ++len;
+    }
+    t.len[(size_t)s] = len;
+    t.kw = std::max(t.kw, len);
+  }
+  if (t.tq.empty()) t.tq.push_back(0);
+  return ISING_OK;
+}
+
+}  // namespace ising

@@ -1,0 +1,196 @@
+// runtime.h -- host runtime of libising (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "device_types.h"
+#include "ising.h"
+#include "kernels.h"
+
+namespace ising {
+
+// Thread-local text of the last error (for ising_status_string callers
+// that want detail, and for the Python binding's exceptions).
+void set_error(const char* fmt, ...);
+const char* last_error();
+
+#define ICHK(expr)                                                              \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      ::ising::set_error("%s failed: %s", #expr, hipGetErrorString(e_));        \
+      return ISING_ERR_DEVICE;                                                  \
+    }                                                                           \
+  } while (0)
+
+#define IRET(expr)                  \
+  do {                              \
+    int rc_ = (expr);               \
+    if (rc_ != ISING_OK) return rc_; \
+  } while (0)
+
+// Switches to a device for the scope and restores the caller's device.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (dev >= 0 && hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// One device allocation carved into 256-byte aligned pieces.
+struct DeviceArena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  int device = -1;
+  DeviceArena() = default;
+  DeviceArena(const DeviceArena&) = delete;
+  DeviceArena& operator=(const DeviceArena&) = delete;
+  ~DeviceArena();
+  int reserve(size_t bytes);  // reallocates when too small; resets used
+  void release();
+  template <class T>
+  T* take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+    if (bytes == 0) bytes = 256;
+    T* p = reinterpret_cast<T*>(base + used);
+    used += bytes;
+    return p;
+  }
+  static size_t span(size_t bytes) { return bytes == 0 ? 256 : (bytes + 255) & ~(size_t)255; }
+};
+
+// ---------------------------------------------------------------- problem
+struct HostGraph {
+  int32_t n = 0;
+  int64_t m = 0;
+  int64_t W = 0;
+  int32_t kmax = 0, max_deg = 0;
+  bool unit = true;
+  int32_t C = 0;
+  int32_t n_pad = 0;
+  std::vector<int32_t> u, v, w;        // original edge list
+  std::vector<int32_t> colour;         // [n]
+  std::vector<int32_t> pos;            // [n] original id -> position
+  std::vector<int32_t> orig;           // [n_pad] position -> id, -1 padding
+  std::vector<int32_t> grp;            // [n_pad/4]
+  std::vector<int32_t> cls;            // [2C] group ranges
+  std::vector<int32_t> row, adj, wgt;  // CSR over positions
+  std::vector<uint32_t> adjm;          // (position << 1) | (w > 0)
+  std::vector<int32_t> aw;             // [2m][2] {position, w}
+  std::vector<int32_t> gbase;          // [n_pad/4] = row[4g]
+  std::vector<uint32_t> gdeg;          // [n_pad/4] packed slot degrees
+};
+
+int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, const int32_t* w,
+                  const int32_t* colour, HostGraph& g);
+
+// ---------------------------------------------------------------- schedule
+int eval_schedule(const ising_schedule* s, std::vector<double>& beta);
+uint64_t threshold_q32(double beta, int64_t k);
+struct Table {
+  int S = 0, kw = 0;
+  std::vector<uint32_t> tq;    // Tq - 1
+  std::vector<int32_t> off, len;
+};
+constexpr int64_t kMaxTableEntries = int64_t(1) << 26;
+int build_table(const std::vector<double>& beta, int32_t kmax, Table& t);
+
+// ---------------------------------------------------------------- device
+struct DevGraph {
+  DeviceArena arena;
+  int device = -1;
+  int32_t *row = nullptr, *adj = nullptr, *wgt = nullptr, *grp = nullptr, *cls = nullptr,
+          *pos = nullptr, *gbase = nullptr;
+  uint32_t *adjm = nullptr, *gdeg = nullptr;
+  int2* aw = nullptr;
+};
+int upload_graph(const HostGraph& g, DevGraph& d);
+
+struct RunBuffers {
+  DeviceArena arena;
+  int R = 0, S = 0, path = 0, G = 0, block = 0, nw = 0;
+  bool trace = false;
+  size_t arena_key = 0;
+  // state and results
+  void* best = nullptr;
+  int32_t* save = nullptr;
+  int8_t* spins = nullptr;
+  int32_t* field = nullptr;
+  int32_t *best_cut = nullptr, *best_sweep = nullptr, *energy = nullptr, *eacc = nullptr,
+          *snap = nullptr, *trace_buf = nullptr, *gather = nullptr;
+  unsigned long long *accepts = nullptr, *argmax = nullptr;
+  uint32_t* tq = nullptr;
+  int32_t *tq_off = nullptr, *tq_len = nullptr;
+  int8_t* init_dev = nullptr;
+  JobDev* job_dev = nullptr;
+  int layout_best = 0, layout_final = 0, layout_field = -1;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool valid = false;
+  ~RunBuffers();
+};
+
+// Launch structures of the persistent kernels plus a cached hipGraph.
+struct Launcher {
+  DeviceArena arena;
+  JobDev* jobs_d = nullptr;
+  int2* units_d = nullptr;
+  int32_t* list_off_d = nullptr;
+  int32_t* ctr_d = nullptr;
+  size_t jobs_cap = 0, units_cap = 0;
+  char* staging = nullptr;  // pinned
+  size_t staging_cap = 0;
+  hipEvent_t staged = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::string graph_key;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  ~Launcher();
+};
+
+struct PersistentConfig {
+  int path = ISING_PATH_FIELD;
+  int G = 1;
+  int block = 256;
+};
+
+// A problem with its schedule, replicas and seed, ready for the kernels.
+struct JobSpec {
+  ising_problem* p;
+  const Table* table;
+  int R;
+  uint64_t seed;
+  int t_begin, t_end;
+};
+
+int run_persistent(Launcher& L, const std::vector<JobSpec>& jobs, const PersistentConfig& cfg,
+                   hipStream_t stream, bool use_graph);
+int prepare_run(ising_problem* p, const Table& table, int R, const PersistentConfig& cfg,
+                hipStream_t stream);
+int device_cu_count();
+size_t lds_budget(int path);
+int check_config(const HostGraph& g, const Table& table, int R, const PersistentConfig& cfg);
+PersistentConfig heuristic_config(const HostGraph& g, const Table& table, int R);
+JobDev make_job(ising_problem* p, const Table& table, int R, uint64_t seed, int t_begin,
+                int t_end, const PersistentConfig& cfg);
+int msc_planes(int max_deg);
+
+}  // namespace ising
+
+struct ising_problem {
+  ising::HostGraph g;
+  ising::DevGraph dg;
+  ising::RunBuffers run;
+  ising::Launcher launcher;
+  std::vector<int8_t> init;  // [init_R][n] original order
+  int32_t init_R = 0;
+  bool trace = false;
+};

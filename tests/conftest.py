@@ -19,3 +19,18 @@ def oracle_lib():
     if not os.path.exists(O.LIB):
         O.build()
     return O
+
+
+def load_binding():
+    """The ctypes binding; builds libising.so first when it is missing.
+
+    On a machine with a GPU a build or load failure is an error, never a
+    skip, so that no GPU test can pass without the HIP library."""
+    try:
+        from paper_2311_09275_amd import binding
+        return binding
+    except ImportError:
+        from paper_2311_09275_amd import build
+        build.build()
+        from paper_2311_09275_amd import binding
+        return binding

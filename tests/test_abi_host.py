@@ -1,0 +1,144 @@
+"""The C ABI library on the host: it loads, exports every declared symbol,
+and its host-side logic (validation, colouring, layout, schedules,
+thresholds, cut evaluation) agrees with the oracle.  No device compute."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2311_09275_amd import instances as I
+from tests.conftest import ROOT, load_binding
+
+B = load_binding()
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "ising.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ising_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    syms = declared_symbols()
+    assert len(syms) >= 25
+    for s in syms:
+        assert hasattr(B._L, s), s
+    assert set(syms) == set(B.EXPORTED)
+
+
+def test_status_strings():
+    for code in range(-6, 1):
+        assert B._L.ising_status_string(code)
+
+
+BAD = [
+    ("selfloop", 3, [0], [0], [1]),
+    ("dup", 3, [0, 1], [1, 0], [1, 1]),
+    ("zero", 3, [0], [1], [0]),
+    ("range", 3, [0], [3], [1]),
+    ("neg", 3, [-1], [1], [1]),
+    ("big", 3, [0], [1], [40000]),
+    ("bigsum", 40000, list(range(0, 39999)), list(range(1, 40000)), [32768] * 39999),
+]
+
+
+@pytest.mark.parametrize("case", BAD, ids=[c[0] for c in BAD])
+def test_validation_matches_oracle(case):
+    name, n, u, v, w = case
+    inst = I.Instance(name, n, np.array(u, np.int32), np.array(v, np.int32), np.array(w, np.int32))
+    assert not O.validate(inst)
+    with pytest.raises(B.IsingError) as e:
+        B.Problem.from_instance(inst)
+    assert e.value.status == B.ERR_INVALID
+
+
+def test_bad_colourings_rejected():
+    inst = I.torus(4, 4, 1)
+    for col in (np.zeros(16, np.int32), np.full(16, 2000, np.int32)):
+        assert not O.validate(inst, colour=col)
+        with pytest.raises(B.IsingError):
+            B.Problem.from_instance(inst, colour=col)
+    with pytest.raises(B.IsingError):
+        B.ising_create(0, [], [], [])
+
+
+GRAPHS = {
+    "c1": lambda: I.workload_c1(),
+    "odd": lambda: I.torus(7, 9, 5),
+    "c2": lambda: I.workload_c2(),
+    "c3": lambda: I.workload_c3(),
+    "weighted": lambda: I.random_weighted(800, 2000, 2, 50),
+    "L141": lambda: I.torus(141, 141, 3),
+}
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_colouring_and_info_match_oracle(name):
+    inst = GRAPHS[name]()
+    p = B.Problem.from_instance(inst)
+    C, col = O.colouring(inst.n, inst.u, inst.v)
+    np.testing.assert_array_equal(p.colouring(), col)
+    info = p.info()
+    assert info.n_colours == C and info.n == inst.n and info.m == inst.m
+    assert info.total_weight == int(inst.w.sum())
+    deg = np.bincount(np.concatenate([inst.u, inst.v]), minlength=inst.n)
+    assert info.max_degree == deg.max()
+    absw = np.zeros(inst.n, np.int64)
+    np.add.at(absw, inst.u, np.abs(inst.w))
+    np.add.at(absw, inst.v, np.abs(inst.w))
+    assert info.kmax == absw.max()
+    assert info.unit_weights == int(np.all(np.abs(inst.w) == 1))
+    sizes = np.bincount(col, minlength=C)
+    assert info.n_padded == int(np.sum((sizes + 3) // 4 * 4))
+    s = I.random_spins(3, 1, inst.n)[0]
+    assert p.eval_cut(s) == O.cut(inst, s)
+    p.close()
+
+
+SCHEDULES = [
+    (O.LINEAR, 1000, 0.1, 3.0, 4),        # 16x16 torus
+    (O.GEOMETRIC, 4000, 0.1, 4.0, 4),     # 100x80 torus and the batch
+    (O.LINEAR, 4000, 0.05, 3.0, 12),      # random graph
+    (O.LINEAR, 1000, 0.1, 3.0, 12),       # serving requests
+    (O.GEOMETRIC, 300, 0.001, 0.01, 200),  # long rows
+    (O.LINEAR, 1, 0.7, 3.0, 5),
+]
+
+
+@pytest.mark.parametrize("sch", SCHEDULES)
+def test_threshold_table_bitwise_equal_to_oracle(sch):
+    kind, S, b0, b1, kmax = sch
+    lib = B.ising_threshold_table(B.Schedule.make(kind, S, b0, b1), kmax)
+    betas = O.schedule(kind, S, b0, b1)
+    ref = np.array([[O.threshold(b, k) for k in range(1, kmax + 1)] for b in betas], np.uint64)
+    np.testing.assert_array_equal(lib, ref)
+
+
+def test_threshold_table_explicit_with_zero_and_infinity():
+    betas = np.array([0.0, 0.25, 1e300, 3.0])
+    lib = B.ising_threshold_table(B.Schedule.make(betas=betas), 6)
+    ref = np.array([[O.threshold(b, k) for k in range(1, 7)] for b in betas], np.uint64)
+    np.testing.assert_array_equal(lib, ref)
+    assert np.all(lib[0] == 2 ** 32) and np.all(lib[2] == 0)
+
+
+def test_bad_schedules_rejected():
+    inst = I.torus(4, 4, 1)
+    p = B.Problem.from_instance(inst)
+    for s in (B.Schedule.make(B.LINEAR, 0, 0.1, 1.0), B.Schedule.make(B.GEOMETRIC, 10, 0.0, 1.0),
+              B.Schedule.make(B.LINEAR, 10, -1.0, 1.0), B.Schedule.make(betas=np.array([0.1, np.nan]))):
+        with pytest.raises(B.IsingError) as e:
+            B.ising_threshold_table(s, 4)
+        assert e.value.status == B.ERR_INVALID
+    p.close()
+
+
+def test_initial_state_validation():
+    p = B.Problem.from_instance(I.torus(4, 4, 1))
+    with pytest.raises(B.IsingError):
+        p.set_initial_state(np.zeros((2, 16), np.int8), 2)
+    p.set_initial_state(np.ones((2, 16), np.int8), 2)
+    p.set_initial_state(None, 0)
+    p.close()

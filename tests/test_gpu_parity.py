@@ -1,0 +1,177 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Every integer the method produces is compared exactly: per-sweep energy of
+every replica, accepted-flip counts, best cut and best sweep, best and final
+states, final local fields and the argmax replica.  Runs on an MI355X."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2311_09275_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+from tests.conftest import load_binding
+
+B = load_binding()
+
+PATHS = {
+    "plain": B.Tuning(B.PATH_PLAIN, 1, 256),
+    "field_g1_b256": B.Tuning(B.PATH_FIELD, 1, 256),
+    "field_g1_b1024": B.Tuning(B.PATH_FIELD, 1, 1024),
+    "field_g2_b512": B.Tuning(B.PATH_FIELD, 2, 512),
+    "field_g4_b256": B.Tuning(B.PATH_FIELD, 4, 256),
+    "msc_g1_b256": B.Tuning(B.PATH_MSC, 1, 256),
+    "msc_g2_b512": B.Tuning(B.PATH_MSC, 2, 512),
+}
+
+
+def _sched(kind, S, b0, b1, betas=None):
+    if betas is not None:
+        return B.Schedule.make(betas=betas), dict(kind=O.EXPLICIT, betas=betas)
+    return B.Schedule.make(kind, S, b0, b1), dict(kind=kind, beta0=b0, beta1=b1)
+
+
+def compare(inst, S, R, seed, kind=O.LINEAR, b0=0.1, b1=3.0, betas=None, tuning=None,
+            init=None, replicas=None, trace=True, colour=None):
+    """Run the GPU path and check it against the oracle on `replicas`."""
+    n = inst.n
+    sched, okw = _sched(kind, S, b0, b1, betas)
+    p = B.Problem.from_instance(inst, colour)
+    if init is not None:
+        p.set_initial_state(init, R)
+    p.set_trace(trace)
+    p.anneal(sched, R, seed, tuning)
+    best, arg, per = B.ising_cut(p.handle, R)
+    bs, acc, en = p.replica_results()
+    reps = list(range(R)) if replicas is None else list(replicas)
+    full = replicas is None
+    tr = p.energy_trace() if trace else None
+    for r in reps:
+        o = O.anneal(inst, S, R, seed, init_spins=init, r_begin=r, r_end=r + 1,
+                     want_trace=trace, want_field=True, colour=colour, **okw)
+        assert per[r] == o.best_cut[0], (r, per[r], o.best_cut[0])
+        assert bs[r] == o.best_sweep[0], r
+        assert acc[r] == o.accepts[0], r
+        assert en[r] == o.final_energy[0], r
+        if trace:
+            np.testing.assert_array_equal(tr[r], o.energy_trace[0], err_msg=f"replica {r}")
+        gb, gf = p.replica_state(r)
+        np.testing.assert_array_equal(gb, o.best_state[0], err_msg=f"best state r={r}")
+        np.testing.assert_array_equal(gf, o.final_state[0], err_msg=f"final state r={r}")
+        if tuning is None or tuning.path != B.PATH_MSC:
+            np.testing.assert_array_equal(p.replica_field(r), o.final_field[0])
+    if full:
+        assert best == per.max()
+        assert arg == int(np.argmax(per))
+        bstate = p.best_state()
+        assert p.eval_cut(bstate) == best
+    p.close()
+    return per
+
+
+# ------------------------------------------------------------------ small cases
+@pytest.mark.parametrize("path", list(PATHS))
+def test_c1_torus16(path):
+    """16x16 +-1 torus, 8 replicas, 1000 sweeps, beta linear 0.1 -> 3.0."""
+    compare(I.workload_c1(), 1000, 8, 1001, tuning=PATHS[path])
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+def test_odd_torus_ragged_classes(path):
+    """7x9 torus: three colour classes whose sizes are not multiples of 4;
+    40 replicas (not a multiple of 32 or of the block size)."""
+    compare(I.torus(7, 9, 5), 150, 40, 77, kind=O.GEOMETRIC, b0=0.2, b1=4.0, tuning=PATHS[path])
+
+
+@pytest.mark.parametrize("path", [p for p in PATHS])
+def test_random_graph_with_isolated_vertices(path):
+    """G70-shaped (m = n - 1) sparse random graph: isolated vertices, varied
+    degrees, greedy colouring with several classes."""
+    compare(I.random_graph(700, 699, 11), 200, 33, 5, kind=O.LINEAR, b0=0.05, b1=3.0,
+            tuning=PATHS[path])
+
+
+@pytest.mark.parametrize("path", ["plain", "field_g1_b256", "field_g4_b256", "field_g2_b512"])
+def test_weighted_graph(path):
+    compare(I.random_weighted(500, 1400, 12, 7), 120, 20, 9, kind=O.GEOMETRIC, b0=0.05, b1=1.5,
+            tuning=PATHS[path])
+
+
+def test_msc_rejects_weighted():
+    p = B.Problem.from_instance(I.random_weighted(50, 100, 1, 3))
+    with pytest.raises(B.IsingError) as e:
+        p.anneal(B.Schedule.make(B.LINEAR, 10, 0.1, 1.0), 32, 1, PATHS["msc_g1_b256"])
+    assert e.value.status == B.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+def test_beta_zero_and_infinite(path):
+    inst = I.torus(6, 5, 3)
+    compare(inst, 9, 12, 3, betas=np.zeros(9), tuning=PATHS[path])
+    compare(inst, 30, 12, 3, betas=np.full(30, 1e300), tuning=PATHS[path])
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+def test_given_initial_state(path):
+    inst = I.torus(10, 6, 2)
+    init = I.random_spins(5, 35, inst.n)
+    compare(inst, 60, 35, 8, tuning=PATHS[path], init=init)
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+def test_degenerate_sizes(path):
+    # one vertex, no edges; a single edge; one sweep; one replica
+    compare(I.Instance("one", 1, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32)),
+            5, 3, 1, tuning=PATHS[path])
+    compare(I.Instance("edge", 2, np.array([0], np.int32), np.array([1], np.int32),
+                       np.array([1], np.int32)), 1, 1, 2, tuning=PATHS[path])
+    compare(I.torus(3, 3, 1), 1, 1, 3, tuning=PATHS[path])
+
+
+def test_supplied_colouring():
+    inst = I.torus(8, 8, 4)
+    v = np.arange(inst.n)
+    colour = ((v % 8 + v // 8) % 2 + 2 * ((v % 8) >= 4)).astype(np.int32)  # 4 classes
+    for path in ("plain", "field_g1_b256", "msc_g1_b256"):
+        compare(inst, 80, 16, 6, tuning=PATHS[path], colour=colour)
+
+
+def test_argmax_ties_lowest_replica():
+    inst = I.torus(6, 6, 1, weights="one")
+    for path in ("plain", "field_g1_b256", "msc_g1_b256"):
+        p = B.Problem.from_instance(inst)
+        p.anneal(B.Schedule.make(B.GEOMETRIC, 300, 0.5, 8.0), 6, 2, PATHS[path])
+        best, arg, per = B.ising_cut(p.handle, 6)
+        assert best == inst.m and np.all(per == inst.m) and arg == 0
+        p.close()
+
+
+def test_repeatable_and_stream():
+    import torch
+    inst = I.torus(12, 12, 7)
+    s = torch.cuda.Stream()
+    outs = []
+    for _ in range(3):
+        p = B.Problem.from_instance(inst)
+        p.set_trace(True)
+        p.anneal(B.Schedule.make(B.LINEAR, 200, 0.1, 3.0), 64, 99, PATHS["field_g1_b256"], stream=s)
+        outs.append(p.energy_trace())
+        p.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+# ------------------------------------------------------------------ full sizes
+def test_c2_full_size_sampled_replicas():
+    """100x80 torus, 256 replicas, 4000 sweeps geometric 0.1 -> 4.0 (the
+    benchmarked configuration, FIELD path as autotuned), four replicas
+    recomputed by the oracle."""
+    compare(I.workload_c2(), 4000, 256, 1002, kind=O.GEOMETRIC, b0=0.1, b1=4.0,
+            tuning=None, replicas=[0, 1, 130, 255], trace=True)
+
+
+def test_c3_full_size_sampled_replicas():
+    """Random graph n=10,000, m=9,999, 1024 replicas, 4000 sweeps linear
+    0.05 -> 3.0, three replicas recomputed by the oracle."""
+    compare(I.workload_c3(), 4000, 1024, 1003, kind=O.LINEAR, b0=0.05, b1=3.0,
+            tuning=None, replicas=[0, 513, 1023], trace=False)
