@@ -1,0 +1,214 @@
+"""Benchmark: spin-flip attempts/s and time-to-target cut on one MI355X.
+
+One step = one whole anneal of the 100x80 toroidal +-1 spin glass (the
+shape of the paper's G65, Table I): threshold table, initial draw and
+fields, 4000 colour-class sweeps of 256 replicas under a geometric beta
+schedule 0.1 -> 4.0, end-of-sweep best tracking, argmax, and the best cut
+copied back to the host.  The persistent LDS-resident kernel is timed; the
+plain one-launch-per-colour-pass form is timed beside it on the same seeds
+(identical results, so the time-to-target ratio is the wall-time ratio),
+and so is the batched form on 64 uneven tori.  The CPU oracle is timed on a
+bounded sample of the same workload on the host cores.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spin-flip attempts/s + time-to-target cut, batched vs plain, 1 MI355X"
+UNIT = "spin-flip attempts/s"
+
+# MI355X published figures used as roofline peaks.
+HBM_PEAK_GBS = 8000.0
+CUS, CLOCK_GHZ = 256, 2.4
+# 32x32->64-bit integer products (v_mad_u64_u32) issue at a quarter of the
+# full VALU rate: 64 lanes / 4 per CU per clock.
+MUL64_PEAK_PER_S = CUS * 16 * CLOCK_GHZ * 1e9
+PRODUCTS_PER_PHILOX = 20  # ten rounds, two products each
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-torus batch leg")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a 256 MiB device copy first (byte-counter calibration)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2311_09275_amd import binding as B
+    from paper_2311_09275_amd import instances as I
+    from paper_2311_09275_amd import ttt
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+
+    if args.calib_copy:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    # ------------------------------------------------------------ workload
+    L_X, L_Y, R, S, B0, B1, SEED = 100, 80, 256, 4000, 0.1, 4.0, 1002
+    inst = I.workload_c2()
+    sched = B.Schedule.make(B.GEOMETRIC, S, B0, B1)
+    attempts = inst.n * R * S
+
+    t0 = time.perf_counter()
+    prob = B.Problem.from_instance(inst)
+    create_ms = (time.perf_counter() - t0) * 1e3
+
+    def run_steps(tuning, steps, warmup, problem=prob):
+        for _ in range(warmup):
+            problem.anneal(sched, R, SEED, tuning, stream=stream)
+            problem.cut()
+        torch.cuda.synchronize()
+        walls, kern = [], []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            problem.anneal(sched, R, SEED, tuning, stream=stream)
+            res = problem.cut()  # synchronises the stream
+            walls.append(time.perf_counter() - t)
+            kern.append(problem.last_anneal_ms())
+        torch.cuda.synchronize()
+        return res, walls, kern
+
+    field = B.Tuning(B.PATH_FIELD, 1, 1024)
+    res, walls, kern = run_steps(field, args.steps, args.warmup)
+    wall_s = sum(walls)
+    ms_per_step = wall_s / args.steps * 1e3
+    value = attempts * args.steps / wall_s
+    per_rep = res.per_replica.copy()
+    best_field = res.best_cut
+    kern_ms = float(np.mean(kern))
+
+    # plain form: same seeds, so identical results
+    res_p, walls_p, kern_p = run_steps(B.Tuning(B.PATH_PLAIN, 1, 256), max(1, args.steps // 2), 1)
+    plain_ms = float(np.mean(walls_p)) * 1e3
+    assert np.array_equal(res_p.per_replica, per_rep), "plain and persistent forms disagree"
+
+    # ------------------------------------------------------------ time to target
+    # Reference best cut of this instance: a longer anneal of 1024 replicas.
+    ref = B.Problem.from_instance(inst)
+    ref.anneal(B.Schedule.make(B.GEOMETRIC, 20000, B0, B1), 1024, 7, None, stream=stream)
+    c_ref = ref.cut().best_cut
+    ref.close()
+    ttt_rows = {}
+    for q in (0.995, 0.998, 1.0):
+        target = ttt.target_cut(c_ref, q)
+        tf = ttt.replica_ttt(per_rep, target, ms_per_step / 1e3, S)
+        tp = ttt.replica_ttt(per_rep, target, plain_ms / 1e3, S)
+        ttt_rows[str(q)] = {"target": target, "ps": tf["ps"],
+                            "ttt_persistent_s": tf["ttt_s"], "ttt_plain_s": tp["ttt_s"],
+                            "sweeps_to_target": tf["sweeps_to_target"]}
+
+    # ------------------------------------------------------------ batch leg
+    batch = None
+    if not args.no_batch:
+        insts = I.workload_c4()
+        probs = [B.Problem.from_instance(x) for x in insts]
+        handles = [p.handle for p in probs]
+        seeds = np.array([2000 + i for i in range(len(insts))], np.uint64)
+        Rb = 128
+        bat_att = sum(x.n for x in insts) * Rb * S
+        tun = B.ising_autotune(handles, sched, Rb, prefix_sweeps=200, stream=stream)
+        B.ising_anneal_batch(handles, sched, Rb, seeds, tun, stream=stream)  # warm (captures)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        B.ising_anneal_batch(handles, sched, Rb, seeds, tun, stream=stream)
+        cuts_b = [B.ising_cut(h)[0] for h in handles]
+        bat_s = time.perf_counter() - t
+        t = time.perf_counter()
+        B.ising_anneal_batch(handles, sched, Rb, seeds, B.Tuning(B.PATH_PLAIN, 1, 256), stream=stream)
+        cuts_p = [B.ising_cut(h)[0] for h in handles]
+        plain_b_s = time.perf_counter() - t
+        assert cuts_b == cuts_p, "batched and plain forms disagree"
+        batch = {"workload": "64 LxL +-1 tori, L~U{32..141}, 128 replicas, 4000 sweeps geometric 0.1->4.0",
+                 "attempts": bat_att, "batched_s": bat_s, "plain_s": plain_b_s,
+                 "batched_attempts_per_s": bat_att / bat_s, "plain_attempts_per_s": bat_att / plain_b_s,
+                 "tuning": {"path": int(tun.path), "replicas_per_block": int(tun.replicas_per_block),
+                            "block_threads": int(tun.block_threads)}}
+        for p in probs:
+            p.close()
+
+    # ------------------------------------------------------------ CPU oracle
+    cpu = None
+    draws_per_attempt = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        O.build(force=False)
+        threads = max(1, min(os.cpu_count() or 1, 16))
+        sample = min(R, 8 * threads)
+        t = time.perf_counter()
+        o = O.anneal(inst, S, R, SEED, kind=O.GEOMETRIC, beta0=B0, beta1=B1, r_begin=0,
+                     r_end=sample, n_threads=threads, want_states=False)
+        cpu_s = time.perf_counter() - t
+        assert np.array_equal(o.best_cut, per_rep[:sample]), "oracle and GPU disagree"
+        cpu = {"value": inst.n * sample * S / cpu_s, "unit": UNIT, "cores": threads, "kind": "oracle",
+               "sample": f"replicas 0..{sample - 1} of 256, all {S} sweeps, {threads} threads, {cpu_s:.1f} s"}
+        draws_per_attempt = float(o.draws.sum()) / (inst.n * sample * S)
+
+    # ------------------------------------------------------------ roofline
+    # Algorithmic ALU work: the Philox blocks the method needs (counted by
+    # the oracle on its sample), 20 products each, per launch.
+    if draws_per_attempt is None:
+        draws_per_attempt = 0.24
+    products = draws_per_attempt * attempts * PRODUCTS_PER_PHILOX
+    achieved = products / (kern_ms / 1e3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": MUL64_PEAK_PER_S / 1e12,
+                "unit": "T int32x32->64 products/s", "frac": achieved / MUL64_PEAK_PER_S,
+                "traffic": None}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"torus {L_X}x{L_Y} +-1 spin glass (N=8000, M=16000), {R} replicas, "
+                               f"{S} sweeps geometric beta {B0}->{B1}",
+                   "replicas": R, "sweeps": S, "seed": SEED, "path": "field (persistent, LDS)",
+                   "block_threads": 1024, "replicas_per_block": 1},
+        "kernel_ms": kern_ms,
+        "plain_ms_per_step": plain_ms,
+        "batched_vs_plain_speedup": plain_ms / ms_per_step,
+        "create_ms": create_ms,
+        "best_cut": best_field,
+        "reference_best_cut": c_ref,
+        "ttt": ttt_rows,
+        "batch": batch,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    prob.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -144,14 +144,18 @@ enum {
 /*
  * Launch choices.  All of them compute identical results.
  *   path                 ISING_PATH_*
- *   replicas_per_block   FIELD: replicas per workgroup (1..16);
- *                        MSC: 32-replica words per workgroup (1..4)
- *   block_threads        64..1024, multiple of 64 (0 = default)
+ *   replicas_per_block   FIELD: replicas per workgroup (1, 2, 4, 8, 16);
+ *                        MSC: 32-replica words per workgroup (1, 2, 4)
+ *   block_threads        256, 512 or 1024 (MSC: 256 or 512); 0 = default
+ *   lds_adjacency        FIELD: 0 = decide, 1 = stage a 16-bit adjacency in
+ *                        LDS (unit weights, fewer than 2^15 vertices),
+ *                        2 = read the adjacency from HBM
  */
 typedef struct {
   int32_t path;
   int32_t replicas_per_block;
   int32_t block_threads;
+  int32_t lds_adjacency;
 } ising_tuning;
 
 /*

@@ -348,7 +348,8 @@ typedef struct {
 } worker_arg;
 
 static void run_replica(worker_arg* A, int32_t r, int8_t* s, int64_t* h,
-                        int64_t* hchk, uint64_t* tq, int32_t* order) {
+                        int64_t* hchk, uint64_t* tq, int32_t* order,
+                        int32_t* drawn_at) {
   const or_graph* G = A->G;
   const or_run_in* run = A->run;
   or_run_out* out = A->out;
@@ -367,7 +368,8 @@ static void run_replica(worker_arg* A, int32_t r, int8_t* s, int64_t* h,
   int64_t E = energy_from_scratch(G, s);
   int64_t best_cut = (G->W - E) / 2;
   int32_t best_sweep = -1;
-  int64_t accepts = 0;
+  int64_t accepts = 0, draws = 0, improvements = 0;
+  for (int32_t i = 0; i < n; ++i) drawn_at[i] = -1;
   if (out->best_state) memcpy(out->best_state + slot * n, s, (size_t)n);
   uint64_t shuf = run->shuffle_seed ^ ((uint64_t)r * 0x632BE59BD9B4E019ull);
 
@@ -394,6 +396,13 @@ static void run_replica(worker_arg* A, int32_t r, int8_t* s, int64_t* h,
         } else {
           uint32_t u = draw(G, run->seed, i, (uint32_t)t, (uint32_t)r, 0);
           accept = (uint64_t)u < tq[k];
+          /* bookkeeping only: one Philox block serves a whole group, so
+           * count each (leader, sweep) once; a draw whose threshold is
+           * 0 or 2^32 decides nothing and is not counted */
+          if (tq[k] != 0 && tq[k] != ((uint64_t)1 << 32) && drawn_at[G->leader[i]] != t) {
+            drawn_at[G->leader[i]] = t;
+            ++draws;
+          }
         }
         if (accept) {
           s[i] = (int8_t)-s[i];
@@ -410,6 +419,7 @@ static void run_replica(worker_arg* A, int32_t r, int8_t* s, int64_t* h,
     if (cut > best_cut) {
       best_cut = cut;
       best_sweep = t;
+      ++improvements;
       if (out->best_state) memcpy(out->best_state + slot * n, s, (size_t)n);
     }
     if (out->energy_trace) out->energy_trace[slot * S + t] = E;
@@ -424,6 +434,8 @@ static void run_replica(worker_arg* A, int32_t r, int8_t* s, int64_t* h,
   out->best_sweep[slot] = best_sweep;
   out->accepts[slot] = accepts;
   out->final_energy[slot] = E;
+  if (out->draws) out->draws[slot] = draws;
+  if (out->improvements) out->improvements[slot] = improvements;
   if (out->final_state) memcpy(out->final_state + slot * n, s, (size_t)n);
   if (out->final_field)
     for (int32_t i = 0; i < n; ++i) out->final_field[slot * n + i] = (int32_t)h[i];
@@ -437,12 +449,14 @@ static void* worker(void* p) {
   int64_t* hchk = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
   uint64_t* tq = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(A->G->kmax + 1));
   int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-  if (!s || !h || !hchk || !tq || !order) {
+  int32_t* drawn_at = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!s || !h || !hchk || !tq || !order || !drawn_at) {
     A->status = -1;
   } else {
     for (int32_t r = A->run->r_begin + A->first; r < A->run->r_end; r += A->stride)
-      run_replica(A, r, s, h, hchk, tq, order);
+      run_replica(A, r, s, h, hchk, tq, order, drawn_at);
   }
+  free(drawn_at);
   free(s);
   free(h);
   free(hchk);

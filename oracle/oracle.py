@@ -50,7 +50,8 @@ class _RunOut(C.Structure):
                 ("accepts", C.c_void_p), ("final_energy", C.c_void_p),
                 ("best_state", C.c_void_p), ("final_state", C.c_void_p),
                 ("final_field", C.c_void_p), ("energy_trace", C.c_void_p),
-                ("check_failures", C.c_int64)]
+                ("check_failures", C.c_int64), ("draws", C.c_void_p),
+                ("improvements", C.c_void_p)]
 
 
 _lib = None
@@ -144,6 +145,8 @@ class Result:
     energy_trace: np.ndarray | None
     check_failures: int
     r_begin: int
+    draws: np.ndarray         # int64 [nr] Philox blocks needed by the sweeps
+    improvements: np.ndarray  # int64 [nr] sweeps that raised the best cut
 
     def argmax(self) -> int:
         """Replica with the largest best cut, lowest index on ties."""
@@ -172,11 +175,14 @@ def anneal(inst, n_sweeps, n_replicas, seed, kind=LINEAR, beta0=0.1,
     final_state = np.zeros((nr, n), np.int8) if want_states else None
     final_field = np.zeros((nr, n), np.int32) if want_field else None
     trace = np.zeros((nr, n_sweeps), np.int64) if want_trace else None
+    draws = np.zeros(nr, np.int64)
+    impr = np.zeros(nr, np.int64)
     out = _RunOut(_p(best_cut), _p(best_sweep), _p(accepts), _p(energy),
-                  _p(best_state), _p(final_state), _p(final_field), _p(trace), 0)
+                  _p(best_state), _p(final_state), _p(final_field), _p(trace), 0,
+                  _p(draws), _p(impr))
     rc = lib().oracle_anneal(C.byref(g), C.byref(run), C.byref(out))
     if rc != 0:
         raise ValueError("oracle rejected the input")
     return Result(best_cut, best_sweep, accepts, energy, best_state,
                   final_state, final_field, trace, int(out.check_failures),
-                  r_begin)
+                  r_begin, draws, impr)

@@ -62,7 +62,7 @@ class Schedule(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("path", C.c_int32), ("replicas_per_block", C.c_int32),
-                ("block_threads", C.c_int32)]
+                ("block_threads", C.c_int32), ("lds_adjacency", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -139,6 +139,10 @@ static size_t persistent_lds(const HostGraph& g, const Table& t, const Persisten
          3 * sizeof(int32_t) * (size_t)(g.n_pad / 4);
 }
 
+// Extra LDS of the staged compact adjacency (16-bit entries).
+static size_t adjacency_lds(const HostGraph& g) { return ((size_t)(4 * g.m) + 3) & ~(size_t)3; }
+static bool adjacency_fits(const HostGraph& g) { return g.unit && g.n_pad < (1 << 15); }
+
 int check_config(const HostGraph& g, const Table& t, int R, const PersistentConfig& c) {
   (void)R;
   if (c.path == ISING_PATH_PLAIN) return ISING_OK;
@@ -154,6 +158,15 @@ int check_config(const HostGraph& g, const Table& t, int R, const PersistentConf
   if (!pow2_upto(c.G, gmax) || c.block / c.G < 64) {
     set_error("replicas_per_block %d invalid for %d threads", c.G, c.block);
     return ISING_ERR_INVALID;
+  }
+  if (c.adj < 0 || c.adj > 2) {
+    set_error("adjacency mode %d invalid", c.adj);
+    return ISING_ERR_INVALID;
+  }
+  if (c.adj == 1 && (c.path != ISING_PATH_FIELD || !adjacency_fits(g) ||
+                     persistent_lds(g, t, c) + adjacency_lds(g) > lds_budget(c.path))) {
+    set_error("the adjacency cannot be staged in LDS for this problem");
+    return ISING_ERR_UNSUPPORTED;
   }
   if (c.path == ISING_PATH_MSC) {
     if (!g.unit) {
@@ -350,12 +363,15 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
     int job, block;
   };
   std::vector<U> all;
-  size_t lds = 0;
+  size_t lds = 0, lds_adj = 0;
+  bool adj_ok = cfg.path == ISING_PATH_FIELD && cfg.adj != 2;
   int planes = 1;
   for (int j = 0; j < n_jobs; ++j) {
     const JobSpec& s = specs[(size_t)j];
     jobs[(size_t)j] = make_job(s.p, *s.table, s.R, s.seed, s.t_begin, s.t_end, cfg);
     lds = std::max(lds, persistent_lds(s.p->g, *s.table, cfg));
+    lds_adj = std::max(lds_adj, persistent_lds(s.p->g, *s.table, cfg) + adjacency_lds(s.p->g));
+    adj_ok = adj_ok && adjacency_fits(s.p->g);
     planes = std::max(planes, msc_planes(s.p->g.max_deg));
     const int per = cfg.path == ISING_PATH_MSC ? 32 * cfg.G : cfg.G;
     const int nb = (s.R + per - 1) / per;
@@ -419,6 +435,22 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
                       sizeof(list_off), hipMemcpyHostToDevice, stream));
   ICHK(hipEventRecord(L.staged, stream));
 
+  const int cus = std::max(device_cu_count(), 1);
+  adj_ok = adj_ok && lds_adj <= lds_budget(cfg.path);
+  bool use_adj = false;
+  if (cfg.adj == 1) {
+    if (!adj_ok) {
+      set_error("the adjacency cannot be staged in LDS for this batch");
+      return ISING_ERR_UNSUPPORTED;
+    }
+    use_adj = true;
+  } else if (cfg.adj == 0 && adj_ok) {
+    // stage it when that does not cost concurrency the units could use
+    const int occ_adj = persistent_occupancy(cfg.path, cfg.block, lds_adj);
+    const int occ_plain = persistent_occupancy(cfg.path, cfg.block, lds);
+    use_adj = occ_adj > 0 && (occ_adj == occ_plain || (int64_t)n_units <= (int64_t)cus * occ_adj);
+  }
+  if (use_adj) lds = lds_adj;
   // raising the dynamic LDS limit is advisory on this runtime
   if (set_persistent_lds_limit(cfg.path, cfg.block, lds) != hipSuccess) (void)hipGetLastError();
   const int occ = persistent_occupancy(cfg.path, cfg.block, lds);
@@ -426,7 +458,6 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
     set_error("persistent kernel cannot be resident with %zu bytes of LDS", lds);
     return ISING_ERR_UNSUPPORTED;
   }
-  const int cus = std::max(device_cu_count(), 1);
   LaunchPersistent lp;
   lp.jobs = L.jobs_d;
   lp.units = L.units_d;
@@ -435,6 +466,7 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   lp.grid = std::min(n_units, cus * occ);
   lp.lds_bytes = lds;
   lp.planes = planes;
+  lp.adj_lds = use_adj;
 
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     hipError_t e = launch_fill_i32(L.ctr_d, 0, 8, s);
@@ -449,8 +481,8 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   ICHK(hipEventRecord(L.ev0, stream));
   if (use_graph && stream) {
     char key[256];
-    snprintf(key, sizeof key, "%d/%d/%d/%d/%zu/%d/%d/%d/%p", cfg.path, cfg.block, cfg.G, planes,
-             lds, lp.grid, n_jobs, n_units, (void*)L.arena.base);
+    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%zu/%d/%d/%d/%p", cfg.path, cfg.block, cfg.G, planes,
+             use_adj ? 1 : 0, lds, lp.grid, n_jobs, n_units, (void*)L.arena.base);
     if (!L.exec || L.graph_key != key) {
       if (L.exec) (void)hipGraphExecDestroy(L.exec);
       if (L.graph) (void)hipGraphDestroy(L.graph);
@@ -814,6 +846,7 @@ static int resolve_config(ising_problem* p, const Table& table, int R, const isi
   cfg.path = path;
   cfg.G = t->replicas_per_block > 0 ? t->replicas_per_block : 1;
   cfg.block = t->block_threads > 0 ? t->block_threads : (path == ISING_PATH_MSC ? 256 : 1024);
+  cfg.adj = t->lds_adjacency;
   if (path == ISING_PATH_PLAIN) {
     cfg.G = 1;
     cfg.block = 256;

@@ -64,7 +64,9 @@ void load_tune_file() {
   if (!f) return;
   char key[200];
   int a, b, c;
-  while (fscanf(f, "%199s %d %d %d", key, &a, &b, &c) == 4) g_tune[key] = PersistentConfig{a, b, c};
+  int d;
+  while (fscanf(f, "%199s %d %d %d %d", key, &a, &b, &c, &d) == 5)
+    g_tune[key] = PersistentConfig{a, b, c, d};
   fclose(f);
 }
 
@@ -74,7 +76,8 @@ void save_tune_file() {
   FILE* f = fopen(path, "w");
   if (!f) return;
   for (auto& kv : g_tune)
-    fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.path, kv.second.G, kv.second.block);
+    fprintf(f, "%s %d %d %d %d\n", kv.first.c_str(), kv.second.path, kv.second.G, kv.second.block,
+            kv.second.adj);
   fclose(f);
 }
 
@@ -169,6 +172,7 @@ int ising_anneal_batch(ising_problem* const* ps, int32_t count, const ising_sche
     cfg.G = tuning->replicas_per_block > 0 ? tuning->replicas_per_block : 1;
     cfg.block = tuning->block_threads > 0 ? tuning->block_threads
                                           : (cfg.path == ISING_PATH_MSC ? 256 : 1024);
+    cfg.adj = tuning->lds_adjacency;
   } else {
     std::vector<const HostGraph*> gs;
     for (int i = 0; i < count; ++i) gs.push_back(&ps[i]->g);
@@ -203,7 +207,7 @@ int ising_anneal_batch(ising_problem* const* ps, int32_t count, const ising_sche
     if (!L.ev0) ICHK(hipEventCreate(&L.ev0));
     if (!L.ev1) ICHK(hipEventCreate(&L.ev1));
     ICHK(hipEventRecord(L.ev0, st));
-    ising_tuning t{ISING_PATH_PLAIN, 1, 256};
+    ising_tuning t{ISING_PATH_PLAIN, 1, 256, 0};
     for (int i = 0; i < count; ++i) IRET(ising_anneal_tuned(ps[i], s, n_replicas, seeds[i], &t, stream));
     ICHK(hipEventRecord(L.ev1, st));
     return ISING_OK;
@@ -244,10 +248,11 @@ int ising_autotune(ising_problem* const* ps, int32_t count, const ising_schedule
   for (int i = 0; i < count; ++i) seeds[(size_t)i] = 0x5EEDull + (uint64_t)i;
 
   std::vector<PersistentConfig> cands;
-  for (int block : {256, 512, 1024})
-    for (int G : {1, 2, 4, 8, 16}) cands.push_back(PersistentConfig{ISING_PATH_FIELD, G, block});
+  for (int adj : {1, 2})
+    for (int block : {256, 512, 1024})
+      for (int G : {1, 2, 4, 8, 16}) cands.push_back(PersistentConfig{ISING_PATH_FIELD, G, block, adj});
   for (int block : {256, 512})
-    for (int G : {1, 2, 4}) cands.push_back(PersistentConfig{ISING_PATH_MSC, G, block});
+    for (int G : {1, 2, 4}) cands.push_back(PersistentConfig{ISING_PATH_MSC, G, block, 0});
 
   Launcher L;
   double best_ms = 1e300;
@@ -275,6 +280,7 @@ int ising_autotune(ising_problem* const* ps, int32_t count, const ising_schedule
   best->path = winner.path;
   best->replicas_per_block = winner.G;
   best->block_threads = winner.block;
+  best->lds_adjacency = winner.adj;
   std::vector<const HostGraph*> gs;
   for (int i = 0; i < count; ++i) gs.push_back(&ps[i]->g);
   {

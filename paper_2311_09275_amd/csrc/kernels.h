@@ -24,6 +24,7 @@ struct LaunchPersistent {
   int grid;
   size_t lds_bytes;        // dynamic LDS per workgroup
   int planes;              // MSC: bit planes of the unsatisfied-bond counter
+  bool adj_lds;            // FIELD: compact adjacency staged in LDS
 };
 
 hipError_t launch_plain_anneal(const PlainDev& P, const PlainPlan& plan, hipStream_t s);

@@ -239,6 +239,7 @@ struct UnitLds {
   int32_t* gword;   // [n_grp]
   int32_t* gbase;   // [n_grp]
   uint32_t* gdeg;   // [n_grp]
+  uint16_t* adj16;  // [2m] (position << 1) | (w > 0), unit weights, when staged
 };
 
 __device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int kw, int n_grp) {
@@ -247,7 +248,15 @@ __device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int kw, i
   u.gword = reinterpret_cast<int32_t*>(u.tq + 2 * kw);
   u.gbase = u.gword + n_grp;
   u.gdeg = reinterpret_cast<uint32_t*>(u.gbase + n_grp);
+  u.adj16 = reinterpret_cast<uint16_t*>(u.gdeg + n_grp);
   return u;
+}
+
+// Compact adjacency of a unit-weight graph with fewer than 2^15 positions.
+__device__ __forceinline__ void stage_adjacency(const JobDev& J, const UnitLds& u) {
+  const GLOBAL_AS uint32_t* adjm = gconst(J.adjm);
+  const int n = 2 * J.M;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) u.adj16[i] = (uint16_t)adjm[i];
 }
 
 __device__ __forceinline__ void stage_row(const JobDev& J, int t, uint32_t* buf) {
@@ -280,41 +289,53 @@ __device__ __forceinline__ int next_unit(const int32_t* list_off, int32_t* ctr, 
   return -1;
 }
 
-// Flip pushes of one group: slot j (flag bit j of fm) adds sgn_j * 4 * w to
-// the packed word of each neighbour.  The first four adjacency entries of
-// every flipped slot are loaded before any atomic is issued.
-__device__ __forceinline__ void push_group(int32_t* st, const GLOBAL_AS i32x2* __restrict__ aw, int base,
-                                           uint32_t dg, uint32_t fm, const int (&w)[4]) {
-  int o[4], d[4];
-  int acc = base;
+// Flip pushes of one group: flipped slot j adds (-2 w s_new) << 1 to the
+// packed word of each neighbour.  Entries are taken four at a time; indices
+// past the slot's degree repeat its last entry and add zero, so the inner
+// body has no per-entry branch.
+__device__ __forceinline__ void push_group_global(int32_t* st, const GLOBAL_AS i32x2* __restrict__ aw,
+                                                  int base, uint32_t dg, uint32_t fm,
+                                                  const int (&w)[4]) {
+  int o = base;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    d[j] = (int)((dg >> (8 * j)) & 255u);
-    o[j] = acc;
-    acc += d[j];
-  }
-  i32x2 q[4][4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (((fm >> j) & 1u) && e < d[j]) q[j][e] = aw[o[j] + e];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
+    const int d = (int)((dg >> (8 * j)) & 255u);
     if ((fm >> j) & 1u) {
-      const int sgn4 = (w[j] & 1) ? -4 : 4;  // (-2 w s_new) << 1 = sgn4 * w
+      const int sgn4 = (w[j] & 1) ? -4 : 4;
+      for (int e0 = 0; e0 < d; e0 += 4) {
+        i32x2 q[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (e < d[j]) atomicAdd(&st[q[j][e].x], sgn4 * q[j][e].y);
-      for (int e = 4; e < d[j]; ++e) {
-        const i32x2 qq = aw[o[j] + e];
-        atomicAdd(&st[qq.x], sgn4 * qq.y);
+        for (int i = 0; i < 4; ++i) q[i] = aw[o + min(e0 + i, d - 1)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) atomicAdd(&st[q[i].x], e0 + i < d ? sgn4 * q[i].y : 0);
       }
     }
+    o += d;
   }
 }
 
-template <int BLOCK>
+__device__ __forceinline__ void push_group_lds(int32_t* st, const uint16_t* adj16, int base,
+                                               uint32_t dg, uint32_t fm, const int (&w)[4]) {
+  int o = base;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int d = (int)((dg >> (8 * j)) & 255u);
+    if ((fm >> j) & 1u) {
+      const int sgn4 = (w[j] & 1) ? -4 : 4;
+      for (int e0 = 0; e0 < d; e0 += 4) {
+        uint32_t a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = adj16[o + min(e0 + i, d - 1)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          atomicAdd(&st[a[i] >> 1], e0 + i < d ? ((a[i] & 1u) ? sgn4 : -sgn4) : 0);
+      }
+    }
+    o += d;
+  }
+}
+
+template <int BLOCK, bool ADJ_LDS>
 __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, FieldShared& sh) {
   const int G = J.G;
   const int TPR = BLOCK / G;  // threads per replica, a multiple of 64
@@ -329,6 +350,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   const int C = J.n_colours;
   const int W = J.W;
   const GLOBAL_AS i32x2* __restrict__ aw = gconst(reinterpret_cast<const i32x2*>(J.aw));
+  const int kwm1 = J.kw - 1;
 
   if (tid < 4 * kMaxReplicasPerBlock) (&sh.eacc[0][0])[tid] = 0;
   if (tid < kMaxReplicasPerBlock) sh.nacc[tid] = 0;
@@ -362,6 +384,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   }
   stage_row(J, J.t_begin, U.tq);
   stage_groups(J, U);
+  if (ADJ_LDS) stage_adjacency(J, U);
   __syncthreads();
 
   int E, best_cut, best_sweep;
@@ -420,29 +443,28 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             const uint32_t bits = (w[0] & 1) | ((w[1] & 1) << 1) | ((w[2] & 1) << 2) | ((w[3] & 1) << 3);
             *reinterpret_cast<GLOBAL_AS uint32_t*>(best + 4 * g) = spins_to_bytes(bits);
           }
-          int k[4];
-          bool need = false;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int h = w[j] >> 1;
-            k[j] = (w[j] & 1) ? h : -h;
-            need |= j < cnt && k[j] > 0 && k[j] <= len;
-          }
-          uint4 x = make_uint4(0, 0, 0, 0);
-          if (need) x = philox10(gw & kGroupLeaderMask, t, r, kTagSweep, k0, k1);
+          // Nearly every group needs its Philox block, so it is drawn
+          // unconditionally; thresholds are read at a clamped index and
+          // used only where 0 < k <= len.
+          const uint4 x = philox10(gw & kGroupLeaderMask, t, r, kTagSweep, k0, k1);
           uint32_t fm = 0;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            if (j < cnt && (k[j] <= 0 || accept_pos(k[j], len, pick(x, j), row))) {
-              fm |= 1u << j;
-              w[j] ^= 1;
-              dE += 2 * k[j];
-              ++nacc;
-            }
+            const int h = w[j] >> 1;
+            const int k = (w[j] & 1) ? h : -h;
+            const uint32_t thr = row[min(max(k - 1, 0), kwm1)];
+            const bool acc = j < cnt && (k <= 0 || len < 0 || (k <= len && pick(x, j) <= thr));
+            fm |= (acc ? 1u : 0u) << j;
+            w[j] ^= acc ? 1 : 0;
+            dE += acc ? 2 * k : 0;
           }
           if (fm) {
+            nacc += __popc(fm);
             *reinterpret_cast<int4*>(st + 4 * g) = make_int4(w[0], w[1], w[2], w[3]);
-            push_group(st, aw, U.gbase[g], U.gdeg[g], fm, w);
+            if (ADJ_LDS)
+              push_group_lds(st, U.adj16, U.gbase[g], U.gdeg[g], fm, w);
+            else
+              push_group_global(st, aw, U.gbase[g], U.gdeg[g], fm, w);
           }
         }
       }
@@ -487,7 +509,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   }
 }
 
-template <int BLOCK>
+template <int BLOCK, bool ADJ_LDS>
 __global__ void __launch_bounds__(BLOCK)
 k_field(const JobDev* __restrict__ jobs, const int2* __restrict__ units,
         const int32_t* __restrict__ list_off, int32_t* __restrict__ ctr) {
@@ -502,7 +524,7 @@ k_field(const JobDev* __restrict__ jobs, const int2* __restrict__ units,
     if (u < 0) break;
     const int2 un = units[u];
     const JobDev J = jobs[un.x];  // by value: fields stay in registers
-    field_unit<BLOCK>(J, un.y, smem, sh);
+    field_unit<BLOCK, ADJ_LDS>(J, un.y, smem, sh);
   }
 }
 
@@ -887,8 +909,12 @@ __global__ void k_fill_i32(int32_t* p, int32_t value, int64_t count) {
 
 template <int BLOCK>
 hipError_t launch_field_t(const LaunchPersistent& L, hipStream_t s) {
-  hipLaunchKernelGGL(k_field<BLOCK>, dim3(L.grid), dim3(BLOCK), L.lds_bytes, s, L.jobs,
-                     L.units, L.list_off, L.ctr);
+  if (L.adj_lds)
+    hipLaunchKernelGGL((k_field<BLOCK, true>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s, L.jobs,
+                       L.units, L.list_off, L.ctr);
+  else
+    hipLaunchKernelGGL((k_field<BLOCK, false>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s, L.jobs,
+                       L.units, L.list_off, L.ctr);
   return hipGetLastError();
 }
 
@@ -953,9 +979,9 @@ hipError_t launch_msc(const LaunchPersistent& L, int block, hipStream_t s) {
 int persistent_occupancy(int path, int block, size_t lds_bytes) {
   if (path == 2) {
     switch (block) {
-      case 256: return occupancy_of(k_field<256>, 256, lds_bytes);
-      case 512: return occupancy_of(k_field<512>, 512, lds_bytes);
-      case 1024: return occupancy_of(k_field<1024>, 1024, lds_bytes);
+      case 256: return occupancy_of(k_field<256, false>, 256, lds_bytes);
+      case 512: return occupancy_of(k_field<512, false>, 512, lds_bytes);
+      case 1024: return occupancy_of(k_field<1024, false>, 1024, lds_bytes);
     }
   } else {
     switch (block) {
@@ -970,8 +996,13 @@ int persistent_occupancy(int path, int block, size_t lds_bytes) {
 hipError_t set_persistent_lds_limit(int path, int block, size_t lds_bytes) {
   const void* f = nullptr;
   if (path == 2) {
-    f = block == 256 ? (const void*)k_field<256> : block == 512 ? (const void*)k_field<512>
-                                                                : (const void*)k_field<1024>;
+    for (const void* k : {(const void*)k_field<256, true>, (const void*)k_field<512, true>,
+                          (const void*)k_field<1024, true>}) {
+      hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+      if (e != hipSuccess) return e;
+    }
+    f = block == 256 ? (const void*)k_field<256, false>
+                     : block == 512 ? (const void*)k_field<512, false> : (const void*)k_field<1024, false>;
   } else {
     f = block == 256 ? (const void*)k_msc<256> : block == 512 ? (const void*)k_msc<512>
                                                               : (const void*)k_msc<1024>;

@@ -160,6 +160,7 @@ struct PersistentConfig {
   int path = ISING_PATH_FIELD;
   int G = 1;
   int block = 256;
+  int adj = 0;  // FIELD adjacency: 0 = decide, 1 = staged in LDS, 2 = read from HBM
 };
 
 // A problem with its schedule, replicas and seed, ready for the kernels.
