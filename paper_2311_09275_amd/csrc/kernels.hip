@@ -248,7 +248,8 @@ __device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int kw, i
   u.gword = reinterpret_cast<int32_t*>(u.tq + 2 * kw);
   u.gbase = u.gword + n_grp;
   u.gdeg = reinterpret_cast<uint32_t*>(u.gbase + n_grp);
-  u.adj16 = reinterpret_cast<uint16_t*>(u.gdeg + n_grp);
+  // 8-byte aligned so that four 16-bit entries can be read at once
+  u.adj16 = reinterpret_cast<uint16_t*>(u.gdeg + n_grp + ((words + 2 * kw + 3 * n_grp) & 1));
   return u;
 }
 
@@ -322,13 +323,23 @@ __device__ __forceinline__ void push_group_lds(int32_t* st, const uint16_t* adj1
     const int d = (int)((dg >> (8 * j)) & 255u);
     if ((fm >> j) & 1u) {
       const int sgn4 = (w[j] & 1) ? -4 : 4;
-      for (int e0 = 0; e0 < d; e0 += 4) {
-        uint32_t a[4];
+      if (d == 4 && (o & 3) == 0) {
+        // four entries in one aligned 8-byte read (every torus vertex)
+        const uint2 e4 = *reinterpret_cast<const uint2*>(adj16 + o);
+        const uint32_t a0 = e4.x & 0xFFFFu, a1 = e4.x >> 16, a2 = e4.y & 0xFFFFu, a3 = e4.y >> 16;
+        atomicAdd(&st[a0 >> 1], (a0 & 1u) ? sgn4 : -sgn4);
+        atomicAdd(&st[a1 >> 1], (a1 & 1u) ? sgn4 : -sgn4);
+        atomicAdd(&st[a2 >> 1], (a2 & 1u) ? sgn4 : -sgn4);
+        atomicAdd(&st[a3 >> 1], (a3 & 1u) ? sgn4 : -sgn4);
+      } else {
+        for (int e0 = 0; e0 < d; e0 += 4) {
+          uint32_t a[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = adj16[o + min(e0 + i, d - 1)];
+          for (int i = 0; i < 4; ++i) a[i] = adj16[o + min(e0 + i, d - 1)];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          atomicAdd(&st[a[i] >> 1], e0 + i < d ? ((a[i] & 1u) ? sgn4 : -sgn4) : 0);
+          for (int i = 0; i < 4; ++i)
+            atomicAdd(&st[a[i] >> 1], e0 + i < d ? ((a[i] & 1u) ? sgn4 : -sgn4) : 0);
+        }
       }
     }
     o += d;
@@ -429,6 +440,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   int nacc = 0;
   for (int t = J.t_begin; t < J.t_end; ++t) {
     const int len = gconst(J.tq_len)[t];
+    const bool all_pass = len < 0;
     const uint32_t* row = U.tq + (t & 1) * J.kw;
     for (int c = 0; c < C; ++c) {
       if (c == C - 1) stage_row(J, t + 1, U.tq);
@@ -444,19 +456,28 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             *reinterpret_cast<GLOBAL_AS uint32_t*>(best + 4 * g) = spins_to_bytes(bits);
           }
           // Nearly every group needs its Philox block, so it is drawn
-          // unconditionally; thresholds are read at a clamped index and
-          // used only where 0 < k <= len.
+          // unconditionally.  The four threshold reads (clamped index, used
+          // only where 0 < k <= len) are issued first so that the block's
+          // arithmetic covers their latency; the accept tests use
+          // non-short-circuit operators and compile without branches.
+          int k[4];
+          uint32_t thr[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int h = w[j] >> 1;
+            k[j] = (w[j] & 1) ? h : -h;
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) thr[j] = row[min(max(k[j] - 1, 0), kwm1)];
           const uint4 x = philox10(gw & kGroupLeaderMask, t, r, kTagSweep, k0, k1);
           uint32_t fm = 0;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const int h = w[j] >> 1;
-            const int k = (w[j] & 1) ? h : -h;
-            const uint32_t thr = row[min(max(k - 1, 0), kwm1)];
-            const bool acc = j < cnt && (k <= 0 || len < 0 || (k <= len && pick(x, j) <= thr));
+            const bool acc = (j < cnt) & ((k[j] <= 0) | all_pass |
+                                          ((k[j] <= len) & (pick(x, j) <= thr[j])));
             fm |= (acc ? 1u : 0u) << j;
             w[j] ^= acc ? 1 : 0;
-            dE += acc ? 2 * k : 0;
+            dE += acc ? 2 * k[j] : 0;
           }
           if (fm) {
             nacc += __popc(fm);

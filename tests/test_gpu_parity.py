@@ -16,13 +16,14 @@ from tests.conftest import load_binding
 B = load_binding()
 
 PATHS = {
-    "plain": B.Tuning(B.PATH_PLAIN, 1, 256),
-    "field_g1_b256": B.Tuning(B.PATH_FIELD, 1, 256),
-    "field_g1_b1024": B.Tuning(B.PATH_FIELD, 1, 1024),
-    "field_g2_b512": B.Tuning(B.PATH_FIELD, 2, 512),
-    "field_g4_b256": B.Tuning(B.PATH_FIELD, 4, 256),
-    "msc_g1_b256": B.Tuning(B.PATH_MSC, 1, 256),
-    "msc_g2_b512": B.Tuning(B.PATH_MSC, 2, 512),
+    "plain": B.Tuning(B.PATH_PLAIN, 1, 256, 0),
+    "field_g1_b256_hbmadj": B.Tuning(B.PATH_FIELD, 1, 256, 2),
+    "field_g1_b1024_ldsadj": B.Tuning(B.PATH_FIELD, 1, 1024, 1),
+    "field_g2_b512_ldsadj": B.Tuning(B.PATH_FIELD, 2, 512, 1),
+    "field_g4_b256_hbmadj": B.Tuning(B.PATH_FIELD, 4, 256, 2),
+    "field_g1_b512_auto": B.Tuning(B.PATH_FIELD, 1, 512, 0),
+    "msc_g1_b256": B.Tuning(B.PATH_MSC, 1, 256, 0),
+    "msc_g2_b512": B.Tuning(B.PATH_MSC, 2, 512, 0),
 }
 
 
@@ -92,17 +93,19 @@ def test_random_graph_with_isolated_vertices(path):
             tuning=PATHS[path])
 
 
-@pytest.mark.parametrize("path", ["plain", "field_g1_b256", "field_g4_b256", "field_g2_b512"])
+@pytest.mark.parametrize("path", ["plain", "field_g1_b256_hbmadj", "field_g4_b256_hbmadj",
+                                  "field_g1_b512_auto"])
 def test_weighted_graph(path):
     compare(I.random_weighted(500, 1400, 12, 7), 120, 20, 9, kind=O.GEOMETRIC, b0=0.05, b1=1.5,
             tuning=PATHS[path])
 
 
-def test_msc_rejects_weighted():
+def test_unit_weight_paths_reject_weighted():
     p = B.Problem.from_instance(I.random_weighted(50, 100, 1, 3))
-    with pytest.raises(B.IsingError) as e:
-        p.anneal(B.Schedule.make(B.LINEAR, 10, 0.1, 1.0), 32, 1, PATHS["msc_g1_b256"])
-    assert e.value.status == B.ERR_UNSUPPORTED
+    for path in ("msc_g1_b256", "field_g1_b1024_ldsadj"):
+        with pytest.raises(B.IsingError) as e:
+            p.anneal(B.Schedule.make(B.LINEAR, 10, 0.1, 1.0), 32, 1, PATHS[path])
+        assert e.value.status == B.ERR_UNSUPPORTED
 
 
 @pytest.mark.parametrize("path", list(PATHS))
@@ -133,13 +136,13 @@ def test_supplied_colouring():
     inst = I.torus(8, 8, 4)
     v = np.arange(inst.n)
     colour = ((v % 8 + v // 8) % 2 + 2 * ((v % 8) >= 4)).astype(np.int32)  # 4 classes
-    for path in ("plain", "field_g1_b256", "msc_g1_b256"):
+    for path in ("plain", "field_g1_b256_hbmadj", "field_g1_b1024_ldsadj", "msc_g1_b256"):
         compare(inst, 80, 16, 6, tuning=PATHS[path], colour=colour)
 
 
 def test_argmax_ties_lowest_replica():
     inst = I.torus(6, 6, 1, weights="one")
-    for path in ("plain", "field_g1_b256", "msc_g1_b256"):
+    for path in ("plain", "field_g1_b256_hbmadj", "field_g1_b1024_ldsadj", "msc_g1_b256"):
         p = B.Problem.from_instance(inst)
         p.anneal(B.Schedule.make(B.GEOMETRIC, 300, 0.5, 8.0), 6, 2, PATHS[path])
         best, arg, per = B.ising_cut(p.handle, 6)
@@ -155,7 +158,7 @@ def test_repeatable_and_stream():
     for _ in range(3):
         p = B.Problem.from_instance(inst)
         p.set_trace(True)
-        p.anneal(B.Schedule.make(B.LINEAR, 200, 0.1, 3.0), 64, 99, PATHS["field_g1_b256"], stream=s)
+        p.anneal(B.Schedule.make(B.LINEAR, 200, 0.1, 3.0), 64, 99, PATHS["field_g1_b1024_ldsadj"], stream=s)
         outs.append(p.energy_trace())
         p.close()
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
