@@ -216,6 +216,11 @@ int ising_energy_trace(ising_problem* p, int64_t* out);
 /* Device time of the last anneal in milliseconds (HIP events around the
  * enqueued work; synchronises). */
 int ising_last_anneal_ms(ising_problem* p, double* ms);
+/* Shape of the last anneal (single or batched): replicas, sweeps and the
+ * kernel path that ran.  Any pointer may be NULL.  ISING_ERR_STATE before
+ * any anneal. */
+int ising_last_run_info(const ising_problem* p, int32_t* n_replicas, int32_t* n_sweeps,
+                        int32_t* path);
 
 /* --------------------------------------------------------------- batching */
 /*

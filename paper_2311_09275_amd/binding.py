@@ -99,6 +99,7 @@ _sig = {
     "ising_replica_field": ([P, C.c_int32, P], C.c_int),
     "ising_energy_trace": ([P, P], C.c_int),
     "ising_last_anneal_ms": ([P, C.POINTER(C.c_double)], C.c_int),
+    "ising_last_run_info": ([P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "ising_anneal_batch": ([P, C.c_int32, C.POINTER(Schedule), C.c_int32, P, C.POINTER(Tuning), P], C.c_int),
     "ising_last_batch_ms": ([C.POINTER(C.c_double)], C.c_int),
     "ising_autotune": ([P, C.c_int32, C.POINTER(Schedule), C.c_int32, C.c_int32, C.POINTER(Tuning), P], C.c_int),
@@ -239,6 +240,12 @@ def ising_energy_trace(h, n_replicas, n_sweeps) -> np.ndarray:
     return out
 
 
+def ising_last_run_info(h):
+    r, s_, p = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(_L.ising_last_run_info(h, C.byref(r), C.byref(s_), C.byref(p)), "ising_last_run_info")
+    return r.value, s_.value, p.value
+
+
 def ising_last_anneal_ms(h) -> float:
     out = C.c_double()
     _check(_L.ising_last_anneal_ms(h, C.byref(out)), "ising_last_anneal_ms")
@@ -351,9 +358,15 @@ class Problem:
 
     def anneal(self, sched: Schedule, n_replicas: int, seed: int, tuning: Tuning | None = None,
                stream=None) -> None:
-        self.R = n_replicas
-        self.S = sched.n_sweeps
         ising_anneal_tuned(self.handle, sched, n_replicas, seed, tuning, stream)
+
+    @property
+    def R(self) -> int:
+        return ising_last_run_info(self.handle)[0]
+
+    @property
+    def S(self) -> int:
+        return ising_last_run_info(self.handle)[1]
 
     def cut(self) -> AnnealResult:
         b, r, per = ising_cut(self.handle, self.R)

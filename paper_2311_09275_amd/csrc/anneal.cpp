@@ -14,17 +14,18 @@ namespace ising {
 DeviceArena::~DeviceArena() { release(); }
 
 void DeviceArena::release() {
-  if (base) {
+  if (base && owned) {
     DeviceGuard g(device);
     (void)hipFree(base);
   }
   base = nullptr;
   cap = used = 0;
+  owned = true;
 }
 
 int DeviceArena::reserve(size_t bytes) {
   used = 0;
-  if (bytes <= cap && base) return ISING_OK;
+  if (bytes <= cap && base && owned) return ISING_OK;
   release();
   bytes = std::max<size_t>(bytes, 4096);
   if (hipGetDevice(&device) != hipSuccess) {
@@ -118,16 +119,18 @@ int upload_graph(const HostGraph& g, DevGraph& d) {
   return ISING_OK;
 }
 
-static int ensure_device(ising_problem* p) {
-  if (p->dg.device >= 0) return ISING_OK;
+int upload_graph_once(const HostGraph& g, DevGraph& d) {
+  if (d.device >= 0) return ISING_OK;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
     (void)hipGetLastError();
     set_error("no HIP device available");
     return ISING_ERR_DEVICE;
   }
-  return upload_graph(p->g, p->dg);
+  return upload_graph(g, d);
 }
+
+static int ensure_device(ising_problem* p) { return upload_graph_once(p->g, p->dg); }
 
 // ---------------------------------------------------------------- planning
 static bool pow2_upto(int x, int hi) { return x >= 1 && x <= hi && (x & (x - 1)) == 0; }
@@ -221,42 +224,51 @@ PersistentConfig heuristic_config(const HostGraph& g, const Table& t, int R) {
 }
 
 // ---------------------------------------------------------------- run state
-int prepare_run(ising_problem* p, const Table& table, int R, const PersistentConfig& cfg,
-                hipStream_t stream) {
-  RunBuffers& b = p->run;
-  const HostGraph& g = p->g;
+size_t run_bytes(const HostGraph& g, const Table& table, int R, const PersistentConfig& cfg,
+                 bool trace, bool init_given) {
+  const size_t np = (size_t)g.n_pad, RR = (size_t)R;
+  const size_t nw = (size_t)(R + 31) / 32;
+  const size_t S = (size_t)table.S;
+  const bool plain = cfg.path == ISING_PATH_PLAIN, msc = cfg.path == ISING_PATH_MSC;
+  const size_t best_bytes = msc ? sizeof(uint32_t) * nw * np : np * RR;
+  const size_t save_bytes = plain ? 0 : (msc ? sizeof(uint32_t) * nw * np : sizeof(int32_t) * RR * np);
+  return DeviceArena::span(best_bytes) + DeviceArena::span(save_bytes) +
+         (plain ? DeviceArena::span(np * RR) + DeviceArena::span(sizeof(int32_t) * np * RR) : 0) +
+         5 * DeviceArena::span(sizeof(int32_t) * RR) +
+         DeviceArena::span(sizeof(unsigned long long) * RR) +
+         DeviceArena::span(sizeof(unsigned long long)) +
+         (trace ? DeviceArena::span(sizeof(int32_t) * S * RR) : 0) +
+         DeviceArena::span(sizeof(int32_t) * (size_t)g.n) +
+         DeviceArena::span(sizeof(uint32_t) * table.tq.size()) +
+         2 * DeviceArena::span(sizeof(int32_t) * S) + (init_given ? DeviceArena::span(RR * np) : 0) +
+         DeviceArena::span(sizeof(JobDev));
+}
+
+int prepare_buffers(RunBuffers& b, const HostGraph& g, const Table& table, int R,
+                    const PersistentConfig& cfg, hipStream_t stream, bool trace,
+                    const int8_t* init, char* pool) {
   if (b.valid && b.stream) (void)hipStreamSynchronize(b.stream);
   b.valid = false;
   const size_t np = (size_t)g.n_pad, RR = (size_t)R;
   const int nw = (R + 31) / 32;
   const int S = table.S;
   const bool plain = cfg.path == ISING_PATH_PLAIN, msc = cfg.path == ISING_PATH_MSC;
-  const bool init_given = p->init_R > 0;
-  if (init_given && p->init_R != R) {
-    set_error("initial states were given for %d replicas, anneal asks %d", p->init_R, R);
-    return ISING_ERR_STATE;
+  const bool init_given = init != nullptr;
+  const size_t bytes = run_bytes(g, table, R, cfg, trace, init_given);
+  if (pool) {
+    int dev = -1;
+    ICHK(hipGetDevice(&dev));
+    b.arena.adopt(pool, bytes, dev);
+  } else {
+    IRET(b.arena.reserve(bytes));
   }
-  size_t best_bytes = msc ? sizeof(uint32_t) * nw * np : np * RR;
-  size_t save_bytes = plain ? 0 : (msc ? sizeof(uint32_t) * nw * np : sizeof(int32_t) * RR * np);
-  size_t bytes = DeviceArena::span(best_bytes) + DeviceArena::span(save_bytes) +
-                 (plain ? DeviceArena::span(np * RR) + DeviceArena::span(sizeof(int32_t) * np * RR)
-                        : 0) +
-                 5 * DeviceArena::span(sizeof(int32_t) * RR) +
-                 DeviceArena::span(sizeof(unsigned long long) * RR) +
-                 DeviceArena::span(sizeof(unsigned long long)) +
-                 (p->trace ? DeviceArena::span(sizeof(int32_t) * (size_t)S * RR) : 0) +
-                 DeviceArena::span(sizeof(int32_t) * (size_t)g.n) +
-                 DeviceArena::span(sizeof(uint32_t) * table.tq.size()) +
-                 2 * DeviceArena::span(sizeof(int32_t) * (size_t)S) +
-                 (init_given ? DeviceArena::span(RR * np) : 0) + DeviceArena::span(sizeof(JobDev));
-  IRET(b.arena.reserve(bytes));
   b.R = R;
   b.S = S;
   b.path = cfg.path;
   b.G = cfg.G;
   b.block = cfg.block;
   b.nw = nw;
-  b.trace = p->trace;
+  b.trace = trace;
   b.best = msc ? (void*)b.arena.take<uint32_t>(nw * np) : (void*)b.arena.take<int8_t>(np * RR);
   b.save = plain ? nullptr : b.arena.take<int32_t>(msc ? nw * np : RR * np);
   b.spins = plain ? b.arena.take<int8_t>(np * RR) : nullptr;
@@ -268,7 +280,7 @@ int prepare_run(ising_problem* p, const Table& table, int R, const PersistentCon
   b.snap = b.arena.take<int32_t>(RR);
   b.accepts = b.arena.take<unsigned long long>(RR);
   b.argmax = b.arena.take<unsigned long long>(1);
-  b.trace_buf = p->trace ? b.arena.take<int32_t>((size_t)S * RR) : nullptr;
+  b.trace_buf = trace ? b.arena.take<int32_t>((size_t)S * RR) : nullptr;
   b.gather = b.arena.take<int32_t>((size_t)g.n);
   b.tq = b.arena.take<uint32_t>(table.tq.size());
   b.tq_off = b.arena.take<int32_t>((size_t)S);
@@ -291,30 +303,38 @@ int prepare_run(ising_problem* p, const Table& table, int R, const PersistentCon
   if (!b.ev0) ICHK(hipEventCreate(&b.ev0));
   if (!b.ev1) ICHK(hipEventCreate(&b.ev1));
   b.stream = stream;
-  // host copies live in the problem until the next anneal (async uploads)
-  static_assert(sizeof(uint32_t) == 4, "");
-  ICHK(hipMemcpyAsync(b.tq, table.tq.data(), sizeof(uint32_t) * table.tq.size(),
+  // the host copy outlives the asynchronous uploads (until the next run)
+  b.table = table;
+  ICHK(hipMemcpyAsync(b.tq, b.table.tq.data(), sizeof(uint32_t) * b.table.tq.size(),
                       hipMemcpyHostToDevice, stream));
-  ICHK(hipMemcpyAsync(b.tq_off, table.off.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice,
+  ICHK(hipMemcpyAsync(b.tq_off, b.table.off.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice,
                       stream));
-  ICHK(hipMemcpyAsync(b.tq_len, table.len.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice,
+  ICHK(hipMemcpyAsync(b.tq_len, b.table.len.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice,
                       stream));
   if (init_given) {
     std::vector<int8_t> perm(RR * np, 1);
     for (size_t r = 0; r < RR; ++r)
       for (int32_t v = 0; v < g.n; ++v)
-        perm[r * np + (size_t)g.pos[(size_t)v]] = p->init[r * (size_t)g.n + (size_t)v];
+        perm[r * np + (size_t)g.pos[(size_t)v]] = init[r * (size_t)g.n + (size_t)v];
     // synchronous: the temporary buffer dies at return
     ICHK(hipMemcpy(b.init_dev, perm.data(), RR * np, hipMemcpyHostToDevice));
   }
   return ISING_OK;
 }
 
-JobDev make_job(ising_problem* p, const Table& table, int R, uint64_t seed, int t_begin,
-                int t_end, const PersistentConfig& cfg) {
-  const HostGraph& g = p->g;
-  const DevGraph& d = p->dg;
-  const RunBuffers& b = p->run;
+int prepare_run(ising_problem* p, const Table& table, int R, const PersistentConfig& cfg,
+                hipStream_t stream) {
+  if (p->init_R > 0 && p->init_R != R) {
+    set_error("initial states were given for %d replicas, anneal asks %d", p->init_R, R);
+    return ISING_ERR_STATE;
+  }
+  return prepare_buffers(p->run, p->g, table, R, cfg, stream, p->trace,
+                         p->init_R > 0 ? p->init.data() : nullptr, nullptr);
+}
+
+JobDev make_job(const HostGraph& g, const DevGraph& d, const RunBuffers& b, int R, uint64_t seed,
+                int t_begin, int t_end, const PersistentConfig& cfg) {
+  const Table& table = b.table;
   JobDev J;
   memset(&J, 0, sizeof J);
   J.row = d.row;
@@ -369,14 +389,14 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   int planes = 1;
   for (int j = 0; j < n_jobs; ++j) {
     const JobSpec& s = specs[(size_t)j];
-    jobs[(size_t)j] = make_job(s.p, *s.table, s.R, s.seed, s.t_begin, s.t_end, cfg);
-    lds = std::max(lds, persistent_lds(s.p->g, *s.table, cfg));
-    lds_adj = std::max(lds_adj, persistent_lds(s.p->g, *s.table, cfg) + adjacency_lds(s.p->g));
-    adj_ok = adj_ok && adjacency_fits(s.p->g);
-    planes = std::max(planes, msc_planes(s.p->g.max_deg));
+    jobs[(size_t)j] = make_job(*s.g, *s.dg, *s.b, s.R, s.seed, s.t_begin, s.t_end, cfg);
+    lds = std::max(lds, persistent_lds(*s.g, s.b->table, cfg));
+    lds_adj = std::max(lds_adj, persistent_lds(*s.g, s.b->table, cfg) + adjacency_lds(*s.g));
+    adj_ok = adj_ok && adjacency_fits(*s.g);
+    planes = std::max(planes, msc_planes(s.g->max_deg));
     const int per = cfg.path == ISING_PATH_MSC ? 32 * cfg.G : cfg.G;
     const int nb = (s.R + per - 1) / per;
-    const double cost = (double)s.p->g.n_pad * (s.t_end - s.t_begin) * per + 1.0;
+    const double cost = (double)s.g->n_pad * (s.t_end - s.t_begin) * per + 1.0;
     for (int k = 0; k < nb; ++k) all.push_back(U{cost, j, k});
   }
   if (lds > lds_budget(cfg.path)) {
@@ -682,7 +702,7 @@ int ising_anneal_tuned(ising_problem* p, const ising_schedule* s, int32_t n_repl
     P.accepts = b.accepts;
     P.trace = b.trace_buf;
     static thread_local JobDev hjob;
-    hjob = make_job(p, table, n_replicas, seed, 0, table.S, cfg);
+    hjob = make_job(p->g, p->dg, b, n_replicas, seed, 0, table.S, cfg);
     ICHK(hipMemcpy(b.job_dev, &hjob, sizeof(JobDev), hipMemcpyHostToDevice));
     PlainPlan plan{table.S, p->g.C, p->g.cls.data()};
     ICHK(hipEventRecord(b.ev0, st));
@@ -690,7 +710,7 @@ int ising_anneal_tuned(ising_problem* p, const ising_schedule* s, int32_t n_repl
     ICHK(launch_argmax(b.job_dev, 1, st));
     ICHK(hipEventRecord(b.ev1, st));
   } else {
-    std::vector<JobSpec> js{JobSpec{p, &table, n_replicas, seed, 0, table.S}};
+    std::vector<JobSpec> js{JobSpec{&p->g, &p->dg, &b, n_replicas, seed, 0, table.S}};
     ICHK(hipEventRecord(b.ev0, st));
     IRET(run_persistent(p->launcher, js, cfg, st, st != nullptr));
     ICHK(hipEventRecord(b.ev1, st));
@@ -820,6 +840,19 @@ int ising_energy_trace(ising_problem* p, int64_t* out) {
   ICHK(hipMemcpy(tmp.data(), b.trace_buf, sizeof(int32_t) * tmp.size(), hipMemcpyDeviceToHost));
   for (int r = 0; r < b.R; ++r)
     for (int t = 0; t < b.S; ++t) out[(size_t)r * b.S + t] = tmp[(size_t)t * b.R + r];
+  return ISING_OK;
+}
+
+int ising_last_run_info(const ising_problem* p, int32_t* n_replicas, int32_t* n_sweeps,
+                        int32_t* path) {
+  if (!p) return ISING_ERR_INVALID;
+  if (!p->run.valid) {
+    set_error("no anneal has run on this problem");
+    return ISING_ERR_STATE;
+  }
+  if (n_replicas) *n_replicas = p->run.R;
+  if (n_sweeps) *n_sweeps = p->run.S;
+  if (path) *path = p->run.path;
   return ISING_OK;
 }
 

@@ -130,7 +130,7 @@ int run_batch(ising_problem* const* ps, int count, const std::vector<Table>& tab
   for (int i = 0; i < count; ++i) IRET(prepare_run(ps[i], tables[(size_t)i], R, cfg, st));
   std::vector<JobSpec> specs;
   for (int i = 0; i < count; ++i)
-    specs.push_back(JobSpec{ps[i], &tables[(size_t)i], R, seeds[i], 0, tables[(size_t)i].S});
+    specs.push_back(JobSpec{&ps[i]->g, &ps[i]->dg, &ps[i]->run, R, seeds[i], 0, tables[(size_t)i].S});
   for (int i = 0; i < count; ++i) ICHK(hipEventRecord(ps[i]->run.ev0, st));
   IRET(run_persistent(L, specs, cfg, st, use_graph));
   for (int i = 0; i < count; ++i) {

@@ -50,6 +50,15 @@ struct DeviceArena {
   char* base = nullptr;
   size_t cap = 0, used = 0;
   int device = -1;
+  bool owned = true;  // false: memory lent by a pool, not freed here
+  void adopt(char* p, size_t bytes, int dev) {
+    release();
+    base = p;
+    cap = bytes;
+    used = 0;
+    device = dev;
+    owned = false;
+  }
   DeviceArena() = default;
   DeviceArena(const DeviceArena&) = delete;
   DeviceArena& operator=(const DeviceArena&) = delete;
@@ -132,6 +141,7 @@ struct RunBuffers {
   int8_t* init_dev = nullptr;
   JobDev* job_dev = nullptr;
   int layout_best = 0, layout_final = 0, layout_field = -1;
+  Table table;                 // host source of the uploaded thresholds
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool valid = false;
@@ -163,10 +173,11 @@ struct PersistentConfig {
   int adj = 0;  // FIELD adjacency: 0 = decide, 1 = staged in LDS, 2 = read from HBM
 };
 
-// A problem with its schedule, replicas and seed, ready for the kernels.
+// One anneal (or a chunk of sweeps of it) ready for the persistent kernels.
 struct JobSpec {
-  ising_problem* p;
-  const Table* table;
+  const HostGraph* g;
+  const DevGraph* dg;
+  const RunBuffers* b;
   int R;
   uint64_t seed;
   int t_begin, t_end;
@@ -176,12 +187,21 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& jobs, const Persiste
                    hipStream_t stream, bool use_graph);
 int prepare_run(ising_problem* p, const Table& table, int R, const PersistentConfig& cfg,
                 hipStream_t stream);
+// Device bytes of one run's buffers.
+size_t run_bytes(const HostGraph& g, const Table& table, int R, const PersistentConfig& cfg,
+                 bool trace, bool init_given);
+// Lay out a run's buffers (in its own allocation, or in pool memory of at
+// least run_bytes) and upload thresholds and initial states.
+int prepare_buffers(RunBuffers& b, const HostGraph& g, const Table& table, int R,
+                    const PersistentConfig& cfg, hipStream_t stream, bool trace,
+                    const int8_t* init, char* pool);
+int upload_graph_once(const HostGraph& g, DevGraph& d);
 int device_cu_count();
 size_t lds_budget(int path);
 int check_config(const HostGraph& g, const Table& table, int R, const PersistentConfig& cfg);
 PersistentConfig heuristic_config(const HostGraph& g, const Table& table, int R);
-JobDev make_job(ising_problem* p, const Table& table, int R, uint64_t seed, int t_begin,
-                int t_end, const PersistentConfig& cfg);
+JobDev make_job(const HostGraph& g, const DevGraph& d, const RunBuffers& b, int R, uint64_t seed,
+                int t_begin, int t_end, const PersistentConfig& cfg);
 int msc_planes(int max_deg);
 
 }  // namespace ising

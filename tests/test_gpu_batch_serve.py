@@ -1,0 +1,158 @@
+"""Batching and serving on the GPU: results must equal separate anneals
+exactly, whatever the batch composition, chunking or graph replay."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2311_09275_amd import instances as I
+from tests.conftest import load_binding
+
+pytestmark = pytest.mark.gpu
+B = load_binding()
+
+
+def _batch_instances():
+    # uneven sizes, odd and even tori (2 and 3 colours), a random graph
+    return [I.torus(33, 33, 101), I.torus(16, 20, 102), I.torus(41, 37, 103),
+            I.random_graph(900, 899, 104), I.torus(64, 64, 105), I.torus(7, 5, 106)]
+
+
+def _single(inst, sched, R, seed, tuning):
+    p = B.Problem.from_instance(inst)
+    p.anneal(sched, R, seed, tuning)
+    best, arg, per = B.ising_cut(p.handle, R)
+    bs, acc, en = p.replica_results()
+    state = p.best_state()
+    p.close()
+    return per, bs, acc, en, state
+
+
+@pytest.mark.parametrize("tun", [B.Tuning(B.PATH_FIELD, 1, 512, 0), B.Tuning(B.PATH_FIELD, 2, 1024, 2),
+                                 B.Tuning(B.PATH_MSC, 1, 256, 0), None],
+                         ids=["field_auto", "field_g2_hbm", "msc", "autotuned"])
+def test_batch_equals_separate_anneals(tun):
+    insts = _batch_instances()
+    sched = B.Schedule.make(B.GEOMETRIC, 300, 0.1, 4.0)
+    R = 40
+    seeds = np.array([7000 + i for i in range(len(insts))], np.uint64)
+    probs = [B.Problem.from_instance(x) for x in insts]
+    hs = [p.handle for p in probs]
+    if tun is None:
+        tun = B.ising_autotune(hs, sched, R, prefix_sweeps=50)
+    B.ising_anneal_batch(hs, sched, R, seeds, tun)
+    for i, (inst, p) in enumerate(zip(insts, probs)):
+        per, bs, acc, en, state = _single(inst, sched, R, int(seeds[i]), B.Tuning(B.PATH_PLAIN, 1, 256, 0))
+        best, arg, per_b = B.ising_cut(p.handle, R)
+        bs_b, acc_b, en_b = p.replica_results()
+        np.testing.assert_array_equal(per_b, per)
+        np.testing.assert_array_equal(bs_b, bs)
+        np.testing.assert_array_equal(acc_b, acc)
+        np.testing.assert_array_equal(en_b, en)
+        np.testing.assert_array_equal(p.best_state(), state)
+    # one problem also against the oracle
+    o = O.anneal(insts[1], 300, R, int(seeds[1]), kind=O.GEOMETRIC, beta0=0.1, beta1=4.0)
+    np.testing.assert_array_equal(B.ising_cut(probs[1].handle, R)[2], o.best_cut)
+    for p in probs:
+        p.close()
+
+
+def test_graph_replays_match_eager():
+    import torch
+    insts = _batch_instances()[:4]
+    sched = B.Schedule.make(B.LINEAR, 200, 0.1, 3.0)
+    R = 32
+    seeds = np.arange(4, dtype=np.uint64) + 11
+    probs = [B.Problem.from_instance(x) for x in insts]
+    hs = [p.handle for p in probs]
+    tun = B.Tuning(B.PATH_FIELD, 1, 512, 0)
+    B.ising_anneal_batch(hs, sched, R, seeds, tun, stream=None)  # eager (null stream)
+    eager = [B.ising_cut(h, R)[2].copy() for h in hs]
+    states = [p.best_state() for p in probs]
+    s = torch.cuda.Stream()
+    x = torch.ones(1 << 20, device="cuda")
+    for rep in range(4):  # first call captures, the rest replay
+        B.ising_anneal_batch(hs, sched, R, seeds, tun, stream=s)
+        for i, h in enumerate(hs):
+            np.testing.assert_array_equal(B.ising_cut(h, R)[2], eager[i])
+            np.testing.assert_array_equal(probs[i].best_state(), states[i])
+        x = x * 2 - 1  # unrelated eager work between replays
+        torch.cuda.synchronize()
+    for p in probs:
+        p.close()
+
+
+def test_batch_timing_api():
+    insts = _batch_instances()[:2]
+    probs = [B.Problem.from_instance(x) for x in insts]
+    B.ising_anneal_batch([p.handle for p in probs], B.Schedule.make(B.LINEAR, 50, 0.1, 3.0), 8,
+                         np.array([1, 2], np.uint64), B.Tuning(B.PATH_FIELD, 1, 256, 0))
+    assert B.ising_last_batch_ms() > 0
+    for p in probs:
+        p.close()
+
+
+# ------------------------------------------------------------------ serving
+def _serve(requests, chunk, budget=1 << 28, slots=8):
+    srv = B.ising_server_create(budget, slots, chunk, backend=0)
+    tickets = [B.ising_server_submit(srv, p.handle, s, R, seed, target, ce)
+               for (p, s, R, seed, target, ce) in requests]
+    out = []
+    for (p, *_), t in zip(requests, tickets):
+        r = B.ising_server_wait(srv, t, 120.0)
+        assert r.status == 0
+        out.append((r.best_cut, r.best_replica, r.sweeps_done, r.reached_target,
+                    B.ising_server_best_state(srv, t, p.n)))
+    stats = B.ising_server_stats(srv)
+    B.ising_server_destroy(srv)
+    return out, stats
+
+
+def test_serving_results_same_alone_and_in_mix():
+    insts = [I.torus(30, 30, 201), I.torus(25, 31, 202), I.random_graph(1200, 1200, 203),
+             I.torus(48, 40, 204), I.torus(15, 15, 205)]
+    probs = [B.Problem.from_instance(x) for x in insts]
+    S = 400
+    sched = B.Schedule.make(B.LINEAR, S, 0.1, 3.0)
+    reqs = []
+    for i, p in enumerate(probs):
+        R, seed = 64 + 32 * (i % 3), 300 + i
+        # even requests run the full schedule; odd ones stop at a target
+        # slightly below what their full schedule reaches
+        target = 10 ** 9
+        if i % 2 == 1:
+            p.anneal(sched, R, seed, B.Tuning(B.PATH_FIELD, 1, 256, 2))
+            target = int(0.97 * B.ising_cut(p.handle, R)[0])
+        reqs.append((p, sched, R, seed, target, 50))
+    mixed, stats = _serve(reqs, chunk=37, slots=3)
+    assert stats[2] <= 3
+    for req, res in zip(reqs, mixed):
+        alone, _ = _serve([req], chunk=64)
+        assert alone[0][:4] == res[:4]
+        np.testing.assert_array_equal(alone[0][4], res[4])
+        # and equal to a one-shot anneal of the sweeps it ran
+        p, s, R, seed, target, ce = req
+        done = res[2]
+        betas = O.schedule(O.LINEAR, S, 0.1, 3.0)[:done]
+        p.anneal(B.Schedule.make(betas=betas), R, seed, B.Tuning(B.PATH_FIELD, 1, 256, 2))
+        best, arg, per = B.ising_cut(p.handle, R)
+        assert (best, arg) == (res[0], res[1])
+        np.testing.assert_array_equal(p.best_state(), res[4])
+        if target < 10 ** 9:
+            assert res[3] == 1 and res[0] >= target and done % 50 == 0
+    for p in probs:
+        p.close()
+
+
+def test_serving_admission_under_memory_pressure():
+    insts = [I.torus(40, 40, 300 + i) for i in range(6)]
+    probs = [B.Problem.from_instance(x) for x in insts]
+    sched = B.Schedule.make(B.LINEAR, 200, 0.1, 3.0)
+    fp = B.ising_server_footprint(probs[0].handle, sched, 128)
+    reqs = [(p, sched, 128, 500 + i, 10 ** 9, 0) for i, p in enumerate(probs)]
+    out, stats = _serve(reqs, chunk=25, budget=int(2.5 * fp), slots=6)
+    assert 1 <= stats[2] <= 2
+    for (p, s, R, seed, *_), res in zip(reqs, out):
+        p.anneal(s, R, seed, B.Tuning(B.PATH_PLAIN, 1, 256, 0))
+        assert B.ising_cut(p.handle, R)[0] == res[0]
+    for p in probs:
+        p.close()
