@@ -39,6 +39,25 @@ MUL64_PEAK_PER_S = CUS * 16 * CLOCK_GHZ * 1e9
 PRODUCTS_PER_PHILOX = 20  # ten rounds, two products each
 
 
+def measured_traffic():
+    """HBM bytes per launch of the timed kernel from the committed counter
+    summary, or None when the kernel source has changed since they were
+    taken (the summary records the SHA-256 of kernels.hip)."""
+    import hashlib
+    import re
+    summary = os.path.join(ROOT, "profiles", "k_field_torus100x80_r256_counters.md")
+    src = os.path.join(ROOT, "paper_2311_09275_amd", "csrc", "kernels.hip")
+    try:
+        text = open(summary).read()
+        want = re.search(r"kernels\.hip sha256: ([0-9a-f]{64})", text).group(1)
+        have = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if want != have:
+            return None
+        return int(re.search(r"HBM bytes per launch: (\d+)", text).group(1))
+    except (OSError, AttributeError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,6 +65,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-torus batch leg")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests of the Poisson serving leg (0 = skip)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
+    ap.add_argument("--no-ttt", action="store_true", help="skip the reference run for targets")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 256 MiB device copy first (byte-counter calibration)")
     return ap.parse_args()
@@ -111,24 +134,31 @@ def main():
     kern_ms = float(np.mean(kern))
 
     # plain form: same seeds, so identical results
-    res_p, walls_p, kern_p = run_steps(B.Tuning(B.PATH_PLAIN, 1, 256), max(1, args.steps // 2), 1)
-    plain_ms = float(np.mean(walls_p)) * 1e3
-    assert np.array_equal(res_p.per_replica, per_rep), "plain and persistent forms disagree"
+    plain_ms = None
+    if not args.no_plain:
+        res_p, walls_p, kern_p = run_steps(B.Tuning(B.PATH_PLAIN, 1, 256), max(1, args.steps // 2), 1)
+        plain_ms = float(np.mean(walls_p)) * 1e3
+        assert np.array_equal(res_p.per_replica, per_rep), "plain and persistent forms disagree"
 
     # ------------------------------------------------------------ time to target
-    # Reference best cut of this instance: a longer anneal of 1024 replicas.
-    ref = B.Problem.from_instance(inst)
-    ref.anneal(B.Schedule.make(B.GEOMETRIC, 20000, B0, B1), 1024, 7, None, stream=stream)
-    c_ref = ref.cut().best_cut
-    ref.close()
-    ttt_rows = {}
-    for q in (0.995, 0.998, 1.0):
-        target = ttt.target_cut(c_ref, q)
-        tf = ttt.replica_ttt(per_rep, target, ms_per_step / 1e3, S)
-        tp = ttt.replica_ttt(per_rep, target, plain_ms / 1e3, S)
-        ttt_rows[str(q)] = {"target": target, "ps": tf["ps"],
-                            "ttt_persistent_s": tf["ttt_s"], "ttt_plain_s": tp["ttt_s"],
-                            "sweeps_to_target": tf["sweeps_to_target"]}
+    # Reference best cut of this instance: a longer anneal of 1024 replicas
+    # (512-thread blocks, so that its dispatches are told apart in profiles).
+    c_ref, ttt_rows = None, None
+    if not args.no_ttt:
+        ref = B.Problem.from_instance(inst)
+        ref.anneal(B.Schedule.make(B.GEOMETRIC, 20000, B0, B1), 1024, 7,
+                   B.Tuning(B.PATH_FIELD, 1, 512, 0), stream=stream)
+        c_ref = ref.cut().best_cut
+        ref.close()
+        ttt_rows = {}
+        for q in (0.995, 0.998, 1.0):
+            target = ttt.target_cut(c_ref, q)
+            tf = ttt.replica_ttt(per_rep, target, ms_per_step / 1e3, S)
+            row = {"target": target, "ps": tf["ps"], "ttt_persistent_s": tf["ttt_s"],
+                   "sweeps_to_target": tf["sweeps_to_target"]}
+            if plain_ms is not None:
+                row["ttt_plain_s"] = ttt.replica_ttt(per_rep, target, plain_ms / 1e3, S)["ttt_s"]
+            ttt_rows[str(q)] = row
 
     # ------------------------------------------------------------ batch leg
     batch = None
@@ -159,6 +189,12 @@ def main():
         for p in probs:
             p.close()
 
+    # ------------------------------------------------------------ serving leg
+    serving = None
+    if args.serve_requests > 0:
+        from paper_2311_09275_amd import serve_load
+        serving = serve_load.run(rate=50.0, n_requests=args.serve_requests, stream=stream)
+
     # ------------------------------------------------------------ CPU oracle
     cpu = None
     draws_per_attempt = None
@@ -166,7 +202,7 @@ def main():
         from oracle import oracle as O
         O.build(force=False)
         threads = max(1, min(os.cpu_count() or 1, 16))
-        sample = min(R, 8 * threads)
+        sample = min(R, 16 * threads)
         t = time.perf_counter()
         o = O.anneal(inst, S, R, SEED, kind=O.GEOMETRIC, beta0=B0, beta1=B1, r_begin=0,
                      r_end=sample, n_threads=threads, want_states=False)
@@ -185,7 +221,7 @@ def main():
     achieved = products / (kern_ms / 1e3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": MUL64_PEAK_PER_S / 1e12,
                 "unit": "T int32x32->64 products/s", "frac": achieved / MUL64_PEAK_PER_S,
-                "traffic": None}
+                "traffic": measured_traffic()}
 
     line = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
@@ -197,12 +233,13 @@ def main():
                    "block_threads": 1024, "replicas_per_block": 1},
         "kernel_ms": kern_ms,
         "plain_ms_per_step": plain_ms,
-        "batched_vs_plain_speedup": plain_ms / ms_per_step,
+        "batched_vs_plain_speedup": None if plain_ms is None else plain_ms / ms_per_step,
         "create_ms": create_ms,
         "best_cut": best_field,
         "reference_best_cut": c_ref,
         "ttt": ttt_rows,
         "batch": batch,
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
