@@ -8,8 +8,8 @@
  * tests, the smoke check and the CPU-baseline leg of the benchmark use it.
  *
  * Problem statement (paper Sec. II.A): weighted MaxCut on n variables with
- * integer edge weights w; the Gset tori are "formulated as weighted MaxCut"
- * and represent 2D Edwards-Anderson spin glasses.  Reading used here: the
+ * integer edge weights w; the paper poses its toroidal +-1 spin glasses
+ * (2D Edwards-Anderson) as weighted MaxCut instances.  Reading used here: the
  * Ising couplings are J = -w, so with s in {-1,+1}^n
  *     E(s)   = sum_e w_e s_u s_v,      cut(s) = sum_e w_e (1 - s_u s_v)/2
  *     cut(s) = (W - E(s)) / 2  with W = sum_e w_e.
