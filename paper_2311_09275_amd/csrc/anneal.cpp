@@ -143,9 +143,15 @@ static size_t persistent_lds(const HostGraph& g, const Table& t, const Persisten
 }
 
 // Extra LDS of the staged compact adjacency (16-bit entries).
-// (plus one word of padding that keeps the entries 8-byte aligned)
-static size_t adjacency_lds(const HostGraph& g) { return (((size_t)(4 * g.m) + 3) & ~(size_t)3) + 4; }
-static bool adjacency_fits(const HostGraph& g) { return g.unit && g.n_pad < (1 << 15); }
+// (plus one word of padding that keeps the entries 8-byte aligned, one
+// after them, and the per-wave flip lists: 256 entries per wave of the
+// largest block).
+static size_t adjacency_lds(const HostGraph& g) {
+  return (((size_t)(4 * g.m) + 3) & ~(size_t)3) + 8 + (size_t)(1024 / 64) * 256 * 4;
+}
+static bool adjacency_fits(const HostGraph& g) {
+  return g.unit && g.n_pad < (1 << 15) && 2 * g.m < (1 << 17) && g.max_deg <= 255;
+}
 
 int check_config(const HostGraph& g, const Table& t, int R, const PersistentConfig& c) {
   (void)R;

@@ -240,6 +240,7 @@ struct UnitLds {
   int32_t* gbase;   // [n_grp]
   uint32_t* gdeg;   // [n_grp]
   uint16_t* adj16;  // [2m] (position << 1) | (w > 0), unit weights, when staged
+  uint32_t* flips;  // [BLOCK/64][256] per-wave lists of flipped vertices (with adj16)
 };
 
 __device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int kw, int n_grp) {
@@ -250,7 +251,13 @@ __device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int kw, i
   u.gdeg = reinterpret_cast<uint32_t*>(u.gbase + n_grp);
   // 8-byte aligned so that four 16-bit entries can be read at once
   u.adj16 = reinterpret_cast<uint16_t*>(u.gdeg + n_grp + ((words + 2 * kw + 3 * n_grp) & 1));
+  u.flips = nullptr;
   return u;
+}
+
+// Flip lists follow the staged adjacency (m entries of 2 x 16 bits).
+__device__ __forceinline__ void place_flip_lists(UnitLds& u, int m) {
+  u.flips = reinterpret_cast<uint32_t*>(u.adj16) + m + 1;
 }
 
 // Compact adjacency of a unit-weight graph with fewer than 2^15 positions.
@@ -315,34 +322,55 @@ __device__ __forceinline__ void push_group_global(int32_t* st, const GLOBAL_AS i
   }
 }
 
-__device__ __forceinline__ void push_group_lds(int32_t* st, const uint16_t* adj16, int base,
-                                               uint32_t dg, uint32_t fm, const int (&w)[4]) {
+// Pushes of one flipped vertex described by a flip-list entry:
+// bits 0..16 = first adjacency entry, 17..24 = degree, 25 = new spin is +1.
+__device__ __forceinline__ void push_entry(int32_t* st, const uint16_t* adj16, uint32_t e) {
+  const int o = (int)(e & 0x1FFFFu);
+  const int d = (int)((e >> 17) & 255u);
+  const int sgn4 = ((e >> 25) & 1u) ? -4 : 4;
+  if (d == 4 && (o & 3) == 0) {
+    const uint2 e4 = *reinterpret_cast<const uint2*>(adj16 + o);
+    const uint32_t a0 = e4.x & 0xFFFFu, a1 = e4.x >> 16, a2 = e4.y & 0xFFFFu, a3 = e4.y >> 16;
+    atomicAdd(&st[a0 >> 1], (a0 & 1u) ? sgn4 : -sgn4);
+    atomicAdd(&st[a1 >> 1], (a1 & 1u) ? sgn4 : -sgn4);
+    atomicAdd(&st[a2 >> 1], (a2 & 1u) ? sgn4 : -sgn4);
+    atomicAdd(&st[a3 >> 1], (a3 & 1u) ? sgn4 : -sgn4);
+  } else {
+    for (int i = 0; i < d; ++i) {
+      const uint32_t a = adj16[o + i];
+      atomicAdd(&st[a >> 1], (a & 1u) ? sgn4 : -sgn4);
+    }
+  }
+}
+
+// The flipped vertices of a wave's groups are appended to the wave's list
+// (ballot + rank among set lanes) and then pushed with every active lane
+// taking one entry per round, instead of four mostly-masked slot passes.
+__device__ __forceinline__ void push_wave_compacted(int32_t* st, const uint16_t* adj16,
+                                                    uint32_t* list, int base, uint32_t dg,
+                                                    uint32_t fm, const int (&w)[4]) {
+  const uint64_t active = __ballot(1);
+  const uint32_t lo = (uint32_t)active, hi = (uint32_t)(active >> 32);
+  const int arank = (int)__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+  const int nact = __popcll(active);
+  int n = 0;
   int o = base;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int d = (int)((dg >> (8 * j)) & 255u);
-    if ((fm >> j) & 1u) {
-      const int sgn4 = (w[j] & 1) ? -4 : 4;
-      if (d == 4 && (o & 3) == 0) {
-        // four entries in one aligned 8-byte read (every torus vertex)
-        const uint2 e4 = *reinterpret_cast<const uint2*>(adj16 + o);
-        const uint32_t a0 = e4.x & 0xFFFFu, a1 = e4.x >> 16, a2 = e4.y & 0xFFFFu, a3 = e4.y >> 16;
-        atomicAdd(&st[a0 >> 1], (a0 & 1u) ? sgn4 : -sgn4);
-        atomicAdd(&st[a1 >> 1], (a1 & 1u) ? sgn4 : -sgn4);
-        atomicAdd(&st[a2 >> 1], (a2 & 1u) ? sgn4 : -sgn4);
-        atomicAdd(&st[a3 >> 1], (a3 & 1u) ? sgn4 : -sgn4);
-      } else {
-        for (int e0 = 0; e0 < d; e0 += 4) {
-          uint32_t a[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) a[i] = adj16[o + min(e0 + i, d - 1)];
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            atomicAdd(&st[a[i] >> 1], e0 + i < d ? ((a[i] & 1u) ? sgn4 : -sgn4) : 0);
-        }
-      }
+    const bool f = (fm >> j) & 1u;
+    const uint64_t m = __ballot(f);
+    if (f) {
+      const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      list[n + rank] = (uint32_t)o | ((uint32_t)d << 17) | ((uint32_t)(w[j] & 1) << 25);
     }
+    n += __popcll(m);
     o += d;
+  }
+  for (int b = 0; b < n; b += nact) {
+    const int i = b + arank;
+    if (i < n) push_entry(st, adj16, list[i]);
   }
 }
 
@@ -356,7 +384,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   const bool live = r < J.R;
   const int n_pad = J.n_pad, n_grp = n_pad >> 2;
   int32_t* st = smem + rl * n_pad;
-  const UnitLds U = unit_lds(reinterpret_cast<uint32_t*>(smem), G * n_pad, J.kw, n_grp);
+  UnitLds U = unit_lds(reinterpret_cast<uint32_t*>(smem), G * n_pad, J.kw, n_grp);
   const uint32_t k0 = J.seed_lo, k1 = J.seed_hi;
   const int C = J.n_colours;
   const int W = J.W;
@@ -395,7 +423,11 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   }
   stage_row(J, J.t_begin, U.tq);
   stage_groups(J, U);
-  if (ADJ_LDS) stage_adjacency(J, U);
+  if (ADJ_LDS) {
+    stage_adjacency(J, U);
+    place_flip_lists(U, J.M);
+  }
+  uint32_t* flist = ADJ_LDS ? U.flips + (threadIdx.x >> 6) * 256 : nullptr;
   __syncthreads();
 
   int E, best_cut, best_sweep;
@@ -479,13 +511,16 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             w[j] ^= acc ? 1 : 0;
             dE += acc ? 2 * k[j] : 0;
           }
-          if (fm) {
+          if (ADJ_LDS) {
+            if (fm) {
+              nacc += __popc(fm);
+              *reinterpret_cast<int4*>(st + 4 * g) = make_int4(w[0], w[1], w[2], w[3]);
+            }
+            push_wave_compacted(st, U.adj16, flist, U.gbase[g], U.gdeg[g], fm, w);
+          } else if (fm) {
             nacc += __popc(fm);
             *reinterpret_cast<int4*>(st + 4 * g) = make_int4(w[0], w[1], w[2], w[3]);
-            if (ADJ_LDS)
-              push_group_lds(st, U.adj16, U.gbase[g], U.gdeg[g], fm, w);
-            else
-              push_group_global(st, aw, U.gbase[g], U.gdeg[g], fm, w);
+            push_group_global(st, aw, U.gbase[g], U.gdeg[g], fm, w);
           }
         }
       }
