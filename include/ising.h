@@ -148,8 +148,11 @@ enum {
  *                        MSC: 32-replica words per workgroup (1, 2, 4)
  *   block_threads        256, 512 or 1024 (MSC: 256 or 512); 0 = default
  *   lds_adjacency        FIELD: 0 = decide, 1 = stage a 16-bit adjacency in
- *                        LDS (unit weights, fewer than 2^15 vertices),
- *                        2 = read the adjacency from HBM
+ *                        LDS (unit weights, fewer than 2^15 vertices; a
+ *                        fixed 32-byte-per-group form when every vertex has
+ *                        degree 4, else CSR order), 2 = read the adjacency
+ *                        from HBM, 3 = stage it in CSR order even when the
+ *                        degree-4 form applies
  */
 typedef struct {
   int32_t path;

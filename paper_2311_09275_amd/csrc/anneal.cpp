@@ -142,15 +142,31 @@ static size_t persistent_lds(const HostGraph& g, const Table& t, const Persisten
          3 * sizeof(int32_t) * (size_t)(g.n_pad / 4);
 }
 
-// Extra LDS of the staged compact adjacency (16-bit entries).
-// (plus one word of padding that keeps the entries 8-byte aligned, one
-// after them, and the per-wave flip lists: 256 entries per wave of the
-// largest block).
-static size_t adjacency_lds(const HostGraph& g) {
-  return (((size_t)(4 * g.m) + 3) & ~(size_t)3) + 8 + (size_t)(1024 / 64) * 256 * 4;
+// Staged adjacency forms of the FIELD kernel (16-bit entries).
+constexpr int kFormHbm = 0, kFormCsr = 1, kFormDeg4 = 2;
+
+// Extra LDS of a staged form: up to 12 bytes that align the entries to 16
+// bytes, then the CSR form's 2m entries, a gap word and the per-wave flip
+// lists (256 entries per wave of the largest block), or the degree-4 form's
+// 32 bytes of positions and 4 bytes of weight signs per group.
+static size_t adjacency_lds(const HostGraph& g, int form) {
+  if (form == kFormDeg4) return 12 + 36 * (size_t)(g.n_pad / 4);
+  return 12 + 4 * (size_t)g.m + 4 + (size_t)(1024 / 64) * 256 * 4;
 }
-static bool adjacency_fits(const HostGraph& g) {
+static bool adjacency_fits(const HostGraph& g, int form) {
+  if (form == kFormDeg4) return g.unit && g.deg4 && g.n_pad < (1 << 15);
   return g.unit && g.n_pad < (1 << 15) && 2 * g.m < (1 << 17) && g.max_deg <= 255;
+}
+// The form that tuning value `adj` (0 decide, 1 LDS, 2 HBM, 3 LDS in CSR
+// form) stages for g, if it fits the LDS budget; kFormHbm when none does.
+static int staged_form(const HostGraph& g, const Table& t, const PersistentConfig& c) {
+  if (c.path != ISING_PATH_FIELD || c.adj == 2) return kFormHbm;
+  const size_t base = persistent_lds(g, t, c);
+  for (int form : {kFormDeg4, kFormCsr}) {
+    if (form == kFormDeg4 && c.adj == 3) continue;
+    if (adjacency_fits(g, form) && base + adjacency_lds(g, form) <= lds_budget(c.path)) return form;
+  }
+  return kFormHbm;
 }
 
 int check_config(const HostGraph& g, const Table& t, int R, const PersistentConfig& c) {
@@ -169,12 +185,11 @@ int check_config(const HostGraph& g, const Table& t, int R, const PersistentConf
     set_error("replicas_per_block %d invalid for %d threads", c.G, c.block);
     return ISING_ERR_INVALID;
   }
-  if (c.adj < 0 || c.adj > 2) {
+  if (c.adj < 0 || c.adj > 3) {
     set_error("adjacency mode %d invalid", c.adj);
     return ISING_ERR_INVALID;
   }
-  if (c.adj == 1 && (c.path != ISING_PATH_FIELD || !adjacency_fits(g) ||
-                     persistent_lds(g, t, c) + adjacency_lds(g) > lds_budget(c.path))) {
+  if ((c.adj == 1 || c.adj == 3) && staged_form(g, t, c) == kFormHbm) {
     set_error("the adjacency cannot be staged in LDS for this problem");
     return ISING_ERR_UNSUPPORTED;
   }
@@ -390,15 +405,20 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
     int job, block;
   };
   std::vector<U> all;
-  size_t lds = 0, lds_adj = 0;
-  bool adj_ok = cfg.path == ISING_PATH_FIELD && cfg.adj != 2;
+  size_t lds = 0, lds_deg4 = 0, lds_csr = 0;
+  // a staged form is used only when every job of the launch fits it
+  bool deg4_ok = cfg.path == ISING_PATH_FIELD && (cfg.adj == 0 || cfg.adj == 1);
+  bool csr_ok = cfg.path == ISING_PATH_FIELD && cfg.adj != 2;
   int planes = 1;
   for (int j = 0; j < n_jobs; ++j) {
     const JobSpec& s = specs[(size_t)j];
     jobs[(size_t)j] = make_job(*s.g, *s.dg, *s.b, s.R, s.seed, s.t_begin, s.t_end, cfg);
     lds = std::max(lds, persistent_lds(*s.g, s.b->table, cfg));
-    lds_adj = std::max(lds_adj, persistent_lds(*s.g, s.b->table, cfg) + adjacency_lds(*s.g));
-    adj_ok = adj_ok && adjacency_fits(*s.g);
+    const size_t own = persistent_lds(*s.g, s.b->table, cfg);
+    lds_deg4 = std::max(lds_deg4, own + adjacency_lds(*s.g, kFormDeg4));
+    lds_csr = std::max(lds_csr, own + adjacency_lds(*s.g, kFormCsr));
+    deg4_ok = deg4_ok && adjacency_fits(*s.g, kFormDeg4);
+    csr_ok = csr_ok && adjacency_fits(*s.g, kFormCsr);
     planes = std::max(planes, msc_planes(s.g->max_deg));
     const int per = cfg.path == ISING_PATH_MSC ? 32 * cfg.G : cfg.G;
     const int nb = (s.R + per - 1) / per;
@@ -463,24 +483,31 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   ICHK(hipEventRecord(L.staged, stream));
 
   const int cus = std::max(device_cu_count(), 1);
-  adj_ok = adj_ok && lds_adj <= lds_budget(cfg.path);
-  bool use_adj = false;
-  if (cfg.adj == 1) {
-    if (!adj_ok) {
+  int form = kFormHbm;
+  size_t lds_adj = lds;
+  if (deg4_ok && lds_deg4 <= lds_budget(cfg.path)) {
+    form = kFormDeg4;
+    lds_adj = lds_deg4;
+  } else if (csr_ok && lds_csr <= lds_budget(cfg.path)) {
+    form = kFormCsr;
+    lds_adj = lds_csr;
+  }
+  if (cfg.adj == 1 || cfg.adj == 3) {
+    if (form == kFormHbm) {
       set_error("the adjacency cannot be staged in LDS for this batch");
       return ISING_ERR_UNSUPPORTED;
     }
-    use_adj = true;
-  } else if (cfg.adj == 0 && adj_ok) {
+  } else if (cfg.adj == 0 && form != kFormHbm) {
     // stage it when that does not cost concurrency the units could use
-    const int occ_adj = persistent_occupancy(cfg.path, cfg.block, lds_adj);
-    const int occ_plain = persistent_occupancy(cfg.path, cfg.block, lds);
-    use_adj = occ_adj > 0 && (occ_adj == occ_plain || (int64_t)n_units <= (int64_t)cus * occ_adj);
+    const int occ_adj = persistent_occupancy(cfg.path, cfg.block, form, lds_adj);
+    const int occ_plain = persistent_occupancy(cfg.path, cfg.block, kFormHbm, lds);
+    if (!(occ_adj > 0 && (occ_adj == occ_plain || (int64_t)n_units <= (int64_t)cus * occ_adj)))
+      form = kFormHbm;
   }
-  if (use_adj) lds = lds_adj;
+  if (form != kFormHbm) lds = lds_adj;
   // raising the dynamic LDS limit is advisory on this runtime
   if (set_persistent_lds_limit(cfg.path, cfg.block, lds) != hipSuccess) (void)hipGetLastError();
-  const int occ = persistent_occupancy(cfg.path, cfg.block, lds);
+  const int occ = persistent_occupancy(cfg.path, cfg.block, form, lds);
   if (occ <= 0) {
     set_error("persistent kernel cannot be resident with %zu bytes of LDS", lds);
     return ISING_ERR_UNSUPPORTED;
@@ -493,7 +520,7 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   lp.grid = std::min(n_units, cus * occ);
   lp.lds_bytes = lds;
   lp.planes = planes;
-  lp.adj_lds = use_adj;
+  lp.adj = form;
 
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     hipError_t e = launch_fill_i32(L.ctr_d, 0, 8, s);
@@ -509,7 +536,7 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   if (use_graph && stream) {
     char key[256];
     snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%zu/%d/%d/%d/%p", cfg.path, cfg.block, cfg.G, planes,
-             use_adj ? 1 : 0, lds, lp.grid, n_jobs, n_units, (void*)L.arena.base);
+             form, lds, lp.grid, n_jobs, n_units, (void*)L.arena.base);
     if (!L.exec || L.graph_key != key) {
       if (L.exec) (void)hipGraphExecDestroy(L.exec);
       if (L.graph) (void)hipGraphDestroy(L.graph);

@@ -24,14 +24,16 @@ struct LaunchPersistent {
   int grid;
   size_t lds_bytes;        // dynamic LDS per workgroup
   int planes;              // MSC: bit planes of the unsatisfied-bond counter
-  bool adj_lds;            // FIELD: compact adjacency staged in LDS
+  int adj;                 // FIELD: 0 = adjacency in HBM, 1 = staged 16-bit CSR,
+                           // 2 = staged degree-4 form (every vertex of degree 4)
 };
 
 hipError_t launch_plain_anneal(const PlainDev& P, const PlainPlan& plan, hipStream_t s);
 hipError_t launch_field(const LaunchPersistent& L, int block, hipStream_t s);
 hipError_t launch_msc(const LaunchPersistent& L, int block, hipStream_t s);
-// Resident workgroups per CU of a persistent kernel (path 2 = FIELD, 3 = MSC).
-int persistent_occupancy(int path, int block, size_t lds_bytes);
+// Resident workgroups per CU of a persistent kernel (path 2 = FIELD, 3 = MSC;
+// adj = the FIELD adjacency form, as in LaunchPersistent).
+int persistent_occupancy(int path, int block, int adj, size_t lds_bytes);
 hipError_t set_persistent_lds_limit(int path, int block, size_t lds_bytes);
 // Per job: argmax over replicas of best_cut, packed into *argmax as
 // (best_cut + 2^31) << 32 | (2^32 - 1 - r): the lowest replica wins ties.

@@ -77,10 +77,16 @@ __device__ __forceinline__ uint32_t pick(const uint4& x, int j) {
 }
 
 // ---------------------------------------------------------------- waves
+// Sum over the wave, returned in every lane.  DPP steps reduce each row of
+// 16 lanes (quad swaps, half-row and row mirrors) without an LDS round
+// trip; the four row sums are then read out as scalars.
 __device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+         __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
 }
 
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
@@ -239,9 +245,17 @@ struct UnitLds {
   int32_t* gword;   // [n_grp]
   int32_t* gbase;   // [n_grp]
   uint32_t* gdeg;   // [n_grp]
-  uint16_t* adj16;  // [2m] (position << 1) | (w > 0), unit weights, when staged
-  uint32_t* flips;  // [BLOCK/64][256] per-wave lists of flipped vertices (with adj16)
+  uint16_t* adj16;  // staged adjacency.  CSR form: [2m] entries
+                    // (position << 1) | (w > 0).  Degree-4 form: [16 n_grp]
+                    // positions, slot j of group g at 16 g + 4 j, then
+  uint32_t* gneg;   // [n_grp] bit 4 j + e set when entry e of slot j has w < 0
+  uint32_t* flips;  // [BLOCK/64][256] per-wave lists of flipped vertices (CSR form)
 };
+
+// Staged adjacency forms (the kernel's ADJ parameter).
+constexpr int kAdjHbm = 0;      // {position, w} pairs read from HBM
+constexpr int kAdjLds = 1;      // 16-bit CSR entries in LDS, wave-compacted pushes
+constexpr int kAdjLdsDeg4 = 2;  // every vertex of degree 4: 32 bytes per group
 
 __device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int kw, int n_grp) {
   UnitLds u;
@@ -249,8 +263,10 @@ __device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int kw, i
   u.gword = reinterpret_cast<int32_t*>(u.tq + 2 * kw);
   u.gbase = u.gword + n_grp;
   u.gdeg = reinterpret_cast<uint32_t*>(u.gbase + n_grp);
-  // 8-byte aligned so that four 16-bit entries can be read at once
-  u.adj16 = reinterpret_cast<uint16_t*>(u.gdeg + n_grp + ((words + 2 * kw + 3 * n_grp) & 1));
+  // 16-byte aligned so that a group's sixteen degree-4 entries are two
+  // 128-bit reads (and four general entries one 64-bit read)
+  u.adj16 = reinterpret_cast<uint16_t*>(u.gdeg + n_grp + ((4 - ((words + 2 * kw + 3 * n_grp) & 3)) & 3));
+  u.gneg = nullptr;
   u.flips = nullptr;
   return u;
 }
@@ -265,6 +281,38 @@ __device__ __forceinline__ void stage_adjacency(const JobDev& J, const UnitLds& 
   const GLOBAL_AS uint32_t* adjm = gconst(J.adjm);
   const int n = 2 * J.M;
   for (int i = threadIdx.x; i < n; i += blockDim.x) u.adj16[i] = (uint16_t)adjm[i];
+}
+
+// Degree-4 form: positions and negative-weight bits of the four entries of
+// each real slot; zeros for padding slots (never pushed: padding never flips).
+__device__ __forceinline__ void stage_adjacency_deg4(const JobDev& J, UnitLds& u) {
+  const GLOBAL_AS uint32_t* adjm = gconst(J.adjm);
+  const GLOBAL_AS int32_t* grp = gconst(J.grp);
+  const GLOBAL_AS int32_t* gbase = gconst(J.gbase);
+  const int n_grp = J.n_pad >> 2;
+  u.gneg = reinterpret_cast<uint32_t*>(u.adj16) + 8 * n_grp;
+  for (int g = threadIdx.x; g < n_grp; g += blockDim.x) {
+    const int cnt = (grp[g] >> kGroupCountShift) + 1;
+    uint32_t pos[8], neg = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) pos[i] = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j < cnt) {
+        const int o = gbase[g] + 4 * j;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t a = adjm[o + e];
+          pos[2 * j + (e >> 1)] |= (a >> 1) << (16 * (e & 1));
+          neg |= ((a & 1u) ^ 1u) << (4 * j + e);
+        }
+      }
+    }
+    uint4* dst = reinterpret_cast<uint4*>(u.adj16) + 2 * g;
+    dst[0] = make_uint4(pos[0], pos[1], pos[2], pos[3]);
+    dst[1] = make_uint4(pos[4], pos[5], pos[6], pos[7]);
+    u.gneg[g] = neg;
+  }
 }
 
 __device__ __forceinline__ void stage_row(const JobDev& J, int t, uint32_t* buf) {
@@ -374,7 +422,43 @@ __device__ __forceinline__ void push_wave_compacted(int32_t* st, const uint16_t*
   }
 }
 
-template <int BLOCK, bool ADJ_LDS>
+// Degree-4 pushes.  The packed word of a neighbour changes by -4 w s_new:
+// +4 when the entry's negative-weight bit equals the new spin's bit (1 for
+// +1), -4 otherwise.  With q = negative-weight bits XOR the new spin bit,
+// entry e adds 4 when bit e of q is clear and -4 when it is set.  Each entry is decoded in three VALU operations, written out
+// because the compiler folds the field extracts into longer sequences:
+// the LDS byte address is one 16 x 16 + 32 multiply-add of the 16-bit
+// position (low or high half of the word), the value a sign-extended bit
+// field shifted and or-ed with 4.
+typedef __attribute__((address_space(3))) int32_t lds_i32;
+
+template <int HI>
+__device__ __forceinline__ uint32_t lds_byte_addr(uint32_t two, uint32_t base) {
+  uint32_t a;
+  if (HI)
+    asm("v_mad_u32_u16 %0, %1, 4, %2 op_sel:[1,0,0,0]" : "=v"(a) : "v"(two), "v"(base));
+  else
+    asm("v_mad_u32_u16 %0, %1, 4, %2" : "=v"(a) : "v"(two), "v"(base));
+  return a;
+}
+
+template <int E>
+__device__ __forceinline__ int plus_minus4(int q) {
+  int m, v;
+  asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(m) : "v"(q), "i"(E));
+  asm("v_lshl_or_b32 %0, %1, 3, 4" : "=v"(v) : "v"(m));
+  return v;
+}
+
+template <int E>
+__device__ __forceinline__ void push_deg4_pair(uint32_t base, uint32_t two, int q) {
+  __hip_atomic_fetch_add((lds_i32*)(uintptr_t)lds_byte_addr<0>(two, base), plus_minus4<E>(q),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_fetch_add((lds_i32*)(uintptr_t)lds_byte_addr<1>(two, base), plus_minus4<E + 1>(q),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int BLOCK, int ADJ>
 __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, FieldShared& sh) {
   const int G = J.G;
   const int TPR = BLOCK / G;  // threads per replica, a multiple of 64
@@ -423,11 +507,15 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   }
   stage_row(J, J.t_begin, U.tq);
   stage_groups(J, U);
-  if (ADJ_LDS) {
+  if (ADJ == kAdjLds) {
     stage_adjacency(J, U);
     place_flip_lists(U, J.M);
+  } else if (ADJ == kAdjLdsDeg4) {
+    stage_adjacency_deg4(J, U);
   }
-  uint32_t* flist = ADJ_LDS ? U.flips + (threadIdx.x >> 6) * 256 : nullptr;
+  uint32_t* flist = ADJ == kAdjLds ? U.flips + (threadIdx.x >> 6) * 256 : nullptr;
+  // LDS byte address of this replica's words (degree-4 pushes)
+  const uint32_t st_base = (uint32_t)(uintptr_t)(lds_i32*)st;
   __syncthreads();
 
   int E, best_cut, best_sweep;
@@ -482,6 +570,15 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           const int gw = U.gword[g];
           const int cnt = (gw >> kGroupCountShift) + 1;
           const int4 w4 = *reinterpret_cast<const int4*>(st + 4 * g);
+          // degree-4 form: the group's entries are fetched with its state,
+          // so their latency is covered by the Philox block
+          uint4 a01 = make_uint4(0u, 0u, 0u, 0u), a23 = a01;
+          uint32_t neg = 0;
+          if (ADJ == kAdjLdsDeg4) {
+            a01 = reinterpret_cast<const uint4*>(U.adj16)[2 * g];
+            a23 = reinterpret_cast<const uint4*>(U.adj16)[2 * g + 1];
+            neg = U.gneg[g];
+          }
           int w[4] = {w4.x, w4.y, w4.z, w4.w};
           if (snap) {
             const uint32_t bits = (w[0] & 1) | ((w[1] & 1) << 1) | ((w[2] & 1) << 2) | ((w[3] & 1) << 3);
@@ -511,7 +608,21 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             w[j] ^= acc ? 1 : 0;
             dE += acc ? 2 * k[j] : 0;
           }
-          if (ADJ_LDS) {
+          if (ADJ == kAdjLdsDeg4) {
+            if (fm) {
+              nacc += __popc(fm);
+              *reinterpret_cast<int4*>(st + 4 * g) = make_int4(w[0], w[1], w[2], w[3]);
+            }
+            const uint32_t e[8] = {a01.x, a01.y, a01.z, a01.w, a23.x, a23.y, a23.z, a23.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              if ((fm >> j) & 1u) {
+                const int q = (int)(neg >> (4 * j)) ^ -(w[j] & 1);
+                push_deg4_pair<0>(st_base, e[2 * j], q);
+                push_deg4_pair<2>(st_base, e[2 * j + 1], q);
+              }
+            }
+          } else if (ADJ == kAdjLds) {
             if (fm) {
               nacc += __popc(fm);
               *reinterpret_cast<int4*>(st + 4 * g) = make_int4(w[0], w[1], w[2], w[3]);
@@ -565,7 +676,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   }
 }
 
-template <int BLOCK, bool ADJ_LDS>
+template <int BLOCK, int ADJ>
 __global__ void __launch_bounds__(BLOCK)
 k_field(const JobDev* __restrict__ jobs, const int2* __restrict__ units,
         const int32_t* __restrict__ list_off, int32_t* __restrict__ ctr) {
@@ -580,7 +691,7 @@ k_field(const JobDev* __restrict__ jobs, const int2* __restrict__ units,
     if (u < 0) break;
     const int2 un = units[u];
     const JobDev J = jobs[un.x];  // by value: fields stay in registers
-    field_unit<BLOCK, ADJ_LDS>(J, un.y, smem, sh);
+    field_unit<BLOCK, ADJ>(J, un.y, smem, sh);
   }
 }
 
@@ -965,13 +1076,30 @@ __global__ void k_fill_i32(int32_t* p, int32_t value, int64_t count) {
 
 template <int BLOCK>
 hipError_t launch_field_t(const LaunchPersistent& L, hipStream_t s) {
-  if (L.adj_lds)
-    hipLaunchKernelGGL((k_field<BLOCK, true>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s, L.jobs,
-                       L.units, L.list_off, L.ctr);
-  else
-    hipLaunchKernelGGL((k_field<BLOCK, false>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s, L.jobs,
-                       L.units, L.list_off, L.ctr);
+  switch (L.adj) {
+    case kAdjHbm:
+      hipLaunchKernelGGL((k_field<BLOCK, kAdjHbm>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s,
+                         L.jobs, L.units, L.list_off, L.ctr);
+      break;
+    case kAdjLds:
+      hipLaunchKernelGGL((k_field<BLOCK, kAdjLds>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s,
+                         L.jobs, L.units, L.list_off, L.ctr);
+      break;
+    case kAdjLdsDeg4:
+      hipLaunchKernelGGL((k_field<BLOCK, kAdjLdsDeg4>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s,
+                         L.jobs, L.units, L.list_off, L.ctr);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+
+template <int BLOCK>
+const void* field_kernel(int adj) {
+  return adj == kAdjLds ? (const void*)k_field<BLOCK, kAdjLds>
+                        : adj == kAdjLdsDeg4 ? (const void*)k_field<BLOCK, kAdjLdsDeg4>
+                                             : (const void*)k_field<BLOCK, kAdjHbm>;
 }
 
 template <int BLOCK>
@@ -1032,12 +1160,12 @@ hipError_t launch_msc(const LaunchPersistent& L, int block, hipStream_t s) {
   }
 }
 
-int persistent_occupancy(int path, int block, size_t lds_bytes) {
+int persistent_occupancy(int path, int block, int adj, size_t lds_bytes) {
   if (path == 2) {
     switch (block) {
-      case 256: return occupancy_of(k_field<256, false>, 256, lds_bytes);
-      case 512: return occupancy_of(k_field<512, false>, 512, lds_bytes);
-      case 1024: return occupancy_of(k_field<1024, false>, 1024, lds_bytes);
+      case 256: return occupancy_of(field_kernel<256>(adj), 256, lds_bytes);
+      case 512: return occupancy_of(field_kernel<512>(adj), 512, lds_bytes);
+      case 1024: return occupancy_of(field_kernel<1024>(adj), 1024, lds_bytes);
     }
   } else {
     switch (block) {
@@ -1052,13 +1180,14 @@ int persistent_occupancy(int path, int block, size_t lds_bytes) {
 hipError_t set_persistent_lds_limit(int path, int block, size_t lds_bytes) {
   const void* f = nullptr;
   if (path == 2) {
-    for (const void* k : {(const void*)k_field<256, true>, (const void*)k_field<512, true>,
-                          (const void*)k_field<1024, true>}) {
+    for (int adj : {kAdjLds, kAdjLdsDeg4}) {
+      const void* k = block == 256 ? field_kernel<256>(adj)
+                                   : block == 512 ? field_kernel<512>(adj) : field_kernel<1024>(adj);
       hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
       if (e != hipSuccess) return e;
     }
-    f = block == 256 ? (const void*)k_field<256, false>
-                     : block == 512 ? (const void*)k_field<512, false> : (const void*)k_field<1024, false>;
+    f = block == 256 ? field_kernel<256>(kAdjHbm)
+                     : block == 512 ? field_kernel<512>(kAdjHbm) : field_kernel<1024>(kAdjHbm);
   } else {
     f = block == 256 ? (const void*)k_msc<256> : block == 512 ? (const void*)k_msc<512>
                                                               : (const void*)k_msc<1024>;

@@ -199,6 +199,8 @@ int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, cons
     }
     g.gdeg[(size_t)q] = packed;
   }
+  g.deg4 = n > 0;
+  for (int32_t i = 0; i < n && g.deg4; ++i) g.deg4 = deg[(size_t)i + 1] - deg[(size_t)i] == 4;
   return ISING_OK;
 }
 

@@ -83,6 +83,7 @@ struct HostGraph {
   int64_t W = 0;
   int32_t kmax = 0, max_deg = 0;
   bool unit = true;
+  bool deg4 = false;                   // every vertex has degree 4 (tori)
   int32_t C = 0;
   int32_t n_pad = 0;
   std::vector<int32_t> u, v, w;        // original edge list

@@ -19,6 +19,8 @@ PATHS = {
     "plain": B.Tuning(B.PATH_PLAIN, 1, 256, 0),
     "field_g1_b256_hbmadj": B.Tuning(B.PATH_FIELD, 1, 256, 2),
     "field_g1_b1024_ldsadj": B.Tuning(B.PATH_FIELD, 1, 1024, 1),
+    "field_g1_b1024_csradj": B.Tuning(B.PATH_FIELD, 1, 1024, 3),
+    "field_g4_b256_csradj": B.Tuning(B.PATH_FIELD, 4, 256, 3),
     "field_g2_b512_ldsadj": B.Tuning(B.PATH_FIELD, 2, 512, 1),
     "field_g4_b256_hbmadj": B.Tuning(B.PATH_FIELD, 4, 256, 2),
     "field_g1_b512_auto": B.Tuning(B.PATH_FIELD, 1, 512, 0),
@@ -93,6 +95,24 @@ def test_random_graph_with_isolated_vertices(path):
             tuning=PATHS[path])
 
 
+def circulant4(n, a, b, seed):
+    """4-regular circulant graph, i ~ i+a and i ~ i+b (mod n), +-1 weights:
+    every vertex of degree 4 but, unlike a torus, not 2-colourable."""
+    i = np.arange(n, dtype=np.int32)
+    u = np.concatenate([i, i])
+    v = np.concatenate([(i + a) % n, (i + b) % n]).astype(np.int32)
+    w = (np.random.Generator(np.random.PCG64(seed)).integers(0, 2, 2 * n) * 2 - 1).astype(np.int32)
+    return I.Instance(f"circulant{n}_{a}_{b}", n, u, v, w)
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+def test_degree4_non_bipartite(path):
+    """Degree-4 graph with several colour classes of ragged sizes, so the
+    degree-4 adjacency form meets padding slots in many groups."""
+    compare(circulant4(331, 1, 17, 4), 150, 20, 12, kind=O.GEOMETRIC, b0=0.1, b1=3.0,
+            tuning=PATHS[path])
+
+
 @pytest.mark.parametrize("path", ["plain", "field_g1_b256_hbmadj", "field_g4_b256_hbmadj",
                                   "field_g1_b512_auto"])
 def test_weighted_graph(path):
@@ -102,7 +122,7 @@ def test_weighted_graph(path):
 
 def test_unit_weight_paths_reject_weighted():
     p = B.Problem.from_instance(I.random_weighted(50, 100, 1, 3))
-    for path in ("msc_g1_b256", "field_g1_b1024_ldsadj"):
+    for path in ("msc_g1_b256", "field_g1_b1024_ldsadj", "field_g1_b1024_csradj"):
         with pytest.raises(B.IsingError) as e:
             p.anneal(B.Schedule.make(B.LINEAR, 10, 0.1, 1.0), 32, 1, PATHS[path])
         assert e.value.status == B.ERR_UNSUPPORTED
@@ -167,10 +187,16 @@ def test_repeatable_and_stream():
 # ------------------------------------------------------------------ full sizes
 def test_c2_full_size_sampled_replicas():
     """100x80 torus, 256 replicas, 4000 sweeps geometric 0.1 -> 4.0 (the
-    benchmarked configuration, FIELD path as autotuned), four replicas
-    recomputed by the oracle."""
+    benchmarked configuration, in the launch configuration the benchmark
+    times), four replicas recomputed by the oracle."""
     compare(I.workload_c2(), 4000, 256, 1002, kind=O.GEOMETRIC, b0=0.1, b1=4.0,
-            tuning=None, replicas=[0, 1, 130, 255], trace=True)
+            tuning=B.Tuning(B.PATH_FIELD, 1, 1024), replicas=[0, 1, 130, 255], trace=True)
+
+
+def test_c2_full_size_automatic_configuration():
+    """The same workload with the library choosing the configuration."""
+    compare(I.workload_c2(), 4000, 256, 1002, kind=O.GEOMETRIC, b0=0.1, b1=4.0,
+            tuning=None, replicas=[7, 200], trace=False)
 
 
 def test_c3_full_size_sampled_replicas():
