@@ -135,11 +135,43 @@ static int ensure_device(ising_problem* p) { return upload_graph_once(p->g, p->d
 // ---------------------------------------------------------------- planning
 static bool pow2_upto(int x, int hi) { return x >= 1 && x <= hi && (x & (x - 1)) == 0; }
 
-// LDS of one unit: state words, two threshold rows, and the group
-// descriptors (leader word, adjacency base, packed degrees).
+// FIELD rows are staged in chunks of up to 256 sweeps and about 8 KB.
+static int row_chunk(const Table& t) {
+  const int rw = std::max(t.kw, 1) + 2;
+  return std::max(1, std::min(256, 2048 / rw));
+}
+
+// LDS of one unit: state words, a chunk of threshold rows, the class
+// bounds and the group descriptors (leader word, adjacency base, packed
+// degrees).  The multispin kernel needs less (two rows, no class bounds).
+
 static size_t persistent_lds(const HostGraph& g, const Table& t, const PersistentConfig& c) {
-  return sizeof(int32_t) * ((size_t)c.G * g.n_pad + 2 * (size_t)std::max(t.kw, 1)) +
+  const size_t rows = (size_t)row_chunk(t) * (size_t)(std::max(t.kw, 1) + 2);
+  return sizeof(int32_t) * ((size_t)c.G * g.n_pad + rows + 2 * (size_t)g.C) +
          3 * sizeof(int32_t) * (size_t)(g.n_pad / 4);
+}
+
+// Rows of the FIELD kernel (JobDev::tqp): fixed stride kw + 2 so that a
+// sweep's row is fetched without first reading its offset.
+static size_t padded_rows(const Table& t) {
+  return (size_t)t.S * (size_t)(std::max(t.kw, 1) + 2);
+}
+
+static void build_padded_rows(const Table& t, std::vector<uint32_t>& out) {
+  const int kw = std::max(t.kw, 1), rw = kw + 2;
+  out.assign(padded_rows(t), 0u);
+  for (int s = 0; s < t.S; ++s) {
+    uint32_t* row = out.data() + (size_t)s * rw;
+    const int len = t.len[(size_t)s];
+    row[0] = 0xFFFFFFFFu;
+    if (len == kAcceptAll) {
+      for (int k = 1; k <= kw; ++k) row[k] = 0xFFFFFFFFu;
+      row[kw + 1] = (uint32_t)t.kmax;
+    } else {
+      for (int k = 1; k <= len; ++k) row[k] = t.tq[(size_t)(t.off[(size_t)s] + k - 1)];
+      row[kw + 1] = (uint32_t)len;
+    }
+  }
 }
 
 // Staged adjacency forms of the FIELD kernel (16-bit entries).
@@ -215,6 +247,10 @@ int check_config(const HostGraph& g, const Table& t, int R, const PersistentConf
     set_error("threshold rows longer than %d need the plain path", kMaxThresholdRow);
     return ISING_ERR_UNSUPPORTED;
   }
+  if (c.path == ISING_PATH_FIELD && (int64_t)padded_rows(t) > kMaxTableEntries) {
+    set_error("sweeps x (row length + 2) above 2^26 need the plain path");
+    return ISING_ERR_UNSUPPORTED;
+  }
   if (persistent_lds(g, t, c) > lds_budget(c.path)) {
     set_error("problem does not fit the %zu-byte LDS budget with %d replica(s) per block",
               lds_budget(c.path), c.G);
@@ -262,6 +298,7 @@ size_t run_bytes(const HostGraph& g, const Table& table, int R, const Persistent
          DeviceArena::span(sizeof(int32_t) * (size_t)g.n) +
          DeviceArena::span(sizeof(uint32_t) * table.tq.size()) +
          2 * DeviceArena::span(sizeof(int32_t) * S) + (init_given ? DeviceArena::span(RR * np) : 0) +
+         (cfg.path == ISING_PATH_FIELD ? DeviceArena::span(sizeof(uint32_t) * padded_rows(table)) : 0) +
          DeviceArena::span(sizeof(JobDev));
 }
 
@@ -306,6 +343,7 @@ int prepare_buffers(RunBuffers& b, const HostGraph& g, const Table& table, int R
   b.tq = b.arena.take<uint32_t>(table.tq.size());
   b.tq_off = b.arena.take<int32_t>((size_t)S);
   b.tq_len = b.arena.take<int32_t>((size_t)S);
+  b.tqp = cfg.path == ISING_PATH_FIELD ? b.arena.take<uint32_t>(padded_rows(table)) : nullptr;
   b.init_dev = init_given ? b.arena.take<int8_t>(RR * np) : nullptr;
   b.job_dev = b.arena.take<JobDev>(1);
   if (plain) {
@@ -332,6 +370,11 @@ int prepare_buffers(RunBuffers& b, const HostGraph& g, const Table& table, int R
                       stream));
   ICHK(hipMemcpyAsync(b.tq_len, b.table.len.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice,
                       stream));
+  if (b.tqp) {
+    build_padded_rows(b.table, b.tqp_host);
+    ICHK(hipMemcpyAsync(b.tqp, b.tqp_host.data(), sizeof(uint32_t) * b.tqp_host.size(),
+                        hipMemcpyHostToDevice, stream));
+  }
   if (init_given) {
     std::vector<int8_t> perm(RR * np, 1);
     for (size_t r = 0; r < RR; ++r)
@@ -374,6 +417,8 @@ JobDev make_job(const HostGraph& g, const DevGraph& d, const RunBuffers& b, int 
   J.tq = b.tq;
   J.tq_off = b.tq_off;
   J.tq_len = b.tq_len;
+  J.tqp = b.tqp;
+  J.row_chunk = row_chunk(table);
   J.S = table.S;
   J.t_begin = t_begin;
   J.t_end = t_end;

@@ -21,6 +21,11 @@ constexpr uint32_t kTagInit = 1;
 // Threshold row length meaning "beta_t == 0: accept every move".
 constexpr int32_t kAcceptAll = -1;
 
+// FIELD path: packed word of a padding slot.  Its k = s h = 2^30 - 1 is
+// above every row's acceptable length (k never exceeds the problem's
+// kmax < 2^29), so padding is never flipped.
+constexpr int32_t kPadWord = 0x7FFFFFFF;
+
 constexpr int kMaxReplicasPerBlock = 16;   // FIELD path
 constexpr int kMaxWordsPerBlock = 4;       // MSC path
 constexpr int kMaxThresholdRow = 1024;     // LDS paths stage <= this many
@@ -52,6 +57,11 @@ struct JobDev {
   const uint32_t* tq;    // thresholds minus one, rows back to back
   const int32_t* tq_off; // [S] row offsets into tq
   const int32_t* tq_len; // [S] row lengths, or kAcceptAll
+  // FIELD: rows of kw + 2 words: [0] = 0xFFFFFFFF (k <= 0 always accepts),
+  // [1..kw] = Tq - 1 for k = 1..len and 0 beyond, [kw + 1] = the largest
+  // acceptable k (len, or kmax when beta = 0 and the row is all 0xFFFFFFFF)
+  const uint32_t* tqp;   // [S][kw + 2]
+  int32_t row_chunk;     // FIELD: sweeps whose rows are staged in LDS at once
   int32_t S, t_begin, t_end, flags;
   int32_t kw;            // longest row (LDS row capacity)
   // run

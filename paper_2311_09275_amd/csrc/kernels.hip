@@ -241,7 +241,8 @@ struct FieldShared {
 };
 
 struct UnitLds {
-  uint32_t* tq;     // [2][kw]
+  uint32_t* tq;     // FIELD: [row_chunk][kw + 2] rows; MSC: [2][kw] (t even, odd)
+  int32_t* cls;     // [2C] first and end group of each class (FIELD)
   int32_t* gword;   // [n_grp]
   int32_t* gbase;   // [n_grp]
   uint32_t* gdeg;   // [n_grp]
@@ -257,15 +258,18 @@ constexpr int kAdjHbm = 0;      // {position, w} pairs read from HBM
 constexpr int kAdjLds = 1;      // 16-bit CSR entries in LDS, wave-compacted pushes
 constexpr int kAdjLdsDeg4 = 2;  // every vertex of degree 4: 32 bytes per group
 
-__device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int kw, int n_grp) {
+__device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int tq_words,
+                                            int cls_words, int n_grp) {
   UnitLds u;
   u.tq = smem + words;
-  u.gword = reinterpret_cast<int32_t*>(u.tq + 2 * kw);
+  u.cls = reinterpret_cast<int32_t*>(u.tq + tq_words);
+  u.gword = u.cls + cls_words;
   u.gbase = u.gword + n_grp;
   u.gdeg = reinterpret_cast<uint32_t*>(u.gbase + n_grp);
   // 16-byte aligned so that a group's sixteen degree-4 entries are two
   // 128-bit reads (and four general entries one 64-bit read)
-  u.adj16 = reinterpret_cast<uint16_t*>(u.gdeg + n_grp + ((4 - ((words + 2 * kw + 3 * n_grp) & 3)) & 3));
+  const int used = words + tq_words + cls_words + 3 * n_grp;
+  u.adj16 = reinterpret_cast<uint16_t*>(u.gdeg + n_grp + ((4 - (used & 3)) & 3));
   u.gneg = nullptr;
   u.flips = nullptr;
   return u;
@@ -320,6 +324,14 @@ __device__ __forceinline__ void stage_row(const JobDev& J, int t, uint32_t* buf)
   const int len = gconst(J.tq_len)[t];
   const GLOBAL_AS uint32_t* src = gconst(J.tq) + gconst(J.tq_off)[t];
   for (int i = threadIdx.x; i < len; i += blockDim.x) buf[(t & 1) * J.kw + i] = src[i];
+}
+
+// FIELD rows (kw + 2 words each, see JobDev::tqp) of sweeps t .. t+n-1,
+// one contiguous copy.
+__device__ __forceinline__ void stage_row_chunk(const JobDev& J, int t, int n, uint32_t* buf,
+                                                int rw) {
+  const GLOBAL_AS uint32_t* src = gconst(J.tqp) + (int64_t)t * rw;
+  for (int i = threadIdx.x; i < n * rw; i += blockDim.x) buf[i] = src[i];
 }
 
 __device__ __forceinline__ void stage_groups(const JobDev& J, const UnitLds& u) {
@@ -458,6 +470,25 @@ __device__ __forceinline__ void push_deg4_pair(uint32_t base, uint32_t two, int 
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// k = s h for a packed word (h << 1) | b, s = 2 b - 1: with m = -b,
+// k = (h XNOR m) + m + 1.  Written out (four operations where the compiler
+// emits five), like the threshold index: k clamped to [0, kw] by one
+// median-of-three.
+__device__ __forceinline__ int spin_times_field(int w) {
+  const int h = w >> 1;
+  int m, x, k;
+  asm("v_bfe_i32 %0, %1, 0, 1" : "=v"(m) : "v"(w));
+  asm("v_xnor_b32 %0, %1, %2" : "=v"(x) : "v"(h), "v"(m));
+  asm("v_add3_u32 %0, %1, %2, 1" : "=v"(k) : "v"(x), "v"(m));
+  return k;
+}
+
+__device__ __forceinline__ int clamp_row_index(int k, int kw) {
+  int i;
+  asm("v_med3_i32 %0, %1, 0, %2" : "=v"(i) : "v"(k), "s"(kw));
+  return i;
+}
+
 template <int BLOCK, int ADJ>
 __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, FieldShared& sh) {
   const int G = J.G;
@@ -468,12 +499,12 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   const bool live = r < J.R;
   const int n_pad = J.n_pad, n_grp = n_pad >> 2;
   int32_t* st = smem + rl * n_pad;
-  UnitLds U = unit_lds(reinterpret_cast<uint32_t*>(smem), G * n_pad, J.kw, n_grp);
-  const uint32_t k0 = J.seed_lo, k1 = J.seed_hi;
   const int C = J.n_colours;
+  const int RW = J.kw + 2;  // row words
+  UnitLds U = unit_lds(reinterpret_cast<uint32_t*>(smem), G * n_pad, J.row_chunk * RW, 2 * C, n_grp);
+  const uint32_t k0 = J.seed_lo, k1 = J.seed_hi;
   const int W = J.W;
   const GLOBAL_AS i32x2* __restrict__ aw = gconst(reinterpret_cast<const i32x2*>(J.aw));
-  const int kwm1 = J.kw - 1;
 
   if (tid < 4 * kMaxReplicasPerBlock) (&sh.eacc[0][0])[tid] = 0;
   if (tid < kMaxReplicasPerBlock) sh.nacc[tid] = 0;
@@ -496,16 +527,18 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           bits = (x.x >> 31) | ((x.y >> 31) << 1) | ((x.z >> 31) << 2) | ((x.w >> 31) << 3);
         }
         w4.x = (int)(bits & 1u);
-        w4.y = cnt > 1 ? (int)((bits >> 1) & 1u) : 0;
-        w4.z = cnt > 2 ? (int)((bits >> 2) & 1u) : 0;
-        w4.w = cnt > 3 ? (int)((bits >> 3) & 1u) : 0;
+        w4.y = cnt > 1 ? (int)((bits >> 1) & 1u) : kPadWord;
+        w4.z = cnt > 2 ? (int)((bits >> 2) & 1u) : kPadWord;
+        w4.w = cnt > 3 ? (int)((bits >> 3) & 1u) : kPadWord;
       } else {
         w4 = *reinterpret_cast<const int4*>(J.save + (int64_t)r * n_pad + 4 * g);
       }
       *reinterpret_cast<int4*>(st + 4 * g) = w4;
     }
   }
-  stage_row(J, J.t_begin, U.tq);
+  const int CH = J.row_chunk;
+  stage_row_chunk(J, J.t_begin, min(CH, J.t_end - J.t_begin), U.tq, RW);
+  for (int i = tid; i < 2 * C; i += BLOCK) U.cls[i] = gconst(J.cls)[i];
   stage_groups(J, U);
   if (ADJ == kAdjLds) {
     stage_adjacency(J, U);
@@ -527,6 +560,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
     if (live) {
       for (int p = lt; p < n_pad; p += TPR) {
         const int g = p >> 2, j = p & 3;
+        if (j > (U.gword[g] >> kGroupCountShift)) continue;  // padding keeps kPadWord
         const uint32_t dg = U.gdeg[g];
         int a = U.gbase[g];
         for (int i = 0; i < j; ++i) a += (int)((dg >> (8 * i)) & 255u);
@@ -553,22 +587,40 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
     best_cut = live ? J.best_cut[r] : 0;
     best_sweep = live ? J.best_sweep[r] : 0;
     snap = false;
+    // drain these loads here: left pending, their wait would sit inside the
+    // sweep loop and also wait for the snapshot stores of every sweep
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   }
 
   GLOBAL_AS int8_t* best = gmut(static_cast<int8_t*>(J.best)) + (int64_t)r * n_pad;
+  const int kw = J.kw;
   int dE = 0;
-  int nacc = 0;
+  int nacc = 0;  // accepted flips of this wave (wave-uniform)
+  // class bounds of the next pass, read one pass ahead
+  int nb0 = U.cls[0], nb1 = U.cls[1];
+  // Rows come in chunks of CH sweeps, one HBM copy and barrier per chunk,
+  // so that the passes themselves issue no HBM loads: a wait for one would
+  // also wait for the snapshot stores still in flight.
+  int tc = 0;  // sweep within the staged chunk
   for (int t = J.t_begin; t < J.t_end; ++t) {
-    const int len = gconst(J.tq_len)[t];
-    const bool all_pass = len < 0;
-    const uint32_t* row = U.tq + (t & 1) * J.kw;
+    if (tc == CH) {
+      stage_row_chunk(J, t, min(CH, J.t_end - t), U.tq, RW);
+      tc = 0;
+      __syncthreads();
+    }
+    const uint32_t* row = U.tq + tc * RW;
+    const int len = (int)row[RW - 1];
+    ++tc;
     for (int c = 0; c < C; ++c) {
-      if (c == C - 1) stage_row(J, t + 1, U.tq);
-      const int g0 = gconst(J.cls)[2 * c], g1 = gconst(J.cls)[2 * c + 1];
+      const int g0 = nb0, g1 = nb1;
+      {
+        const int cn = c + 1 < C ? c + 1 : 0;
+        nb0 = U.cls[2 * cn];
+        nb1 = U.cls[2 * cn + 1];
+      }
       if (live) {
         for (int g = g0 + lt; g < g1; g += TPR) {
           const int gw = U.gword[g];
-          const int cnt = (gw >> kGroupCountShift) + 1;
           const int4 w4 = *reinterpret_cast<const int4*>(st + 4 * g);
           // degree-4 form: the group's entries are fetched with its state,
           // so their latency is covered by the Philox block
@@ -585,52 +637,43 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             *reinterpret_cast<GLOBAL_AS uint32_t*>(best + 4 * g) = spins_to_bytes(bits);
           }
           // Nearly every group needs its Philox block, so it is drawn
-          // unconditionally.  The four threshold reads (clamped index, used
-          // only where 0 < k <= len) are issued first so that the block's
-          // arithmetic covers their latency; the accept tests use
-          // non-short-circuit operators and compile without branches.
+          // unconditionally.  The four threshold reads are issued first so
+          // that the block's arithmetic covers their latency.  Row entry 0
+          // accepts k <= 0 and k above the row's length is refused by the
+          // length test (padding slots have k = 2^30 - 1), so each slot's
+          // test is two comparisons.
           int k[4];
           uint32_t thr[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int h = w[j] >> 1;
-            k[j] = (w[j] & 1) ? h : -h;
-          }
+          for (int j = 0; j < 4; ++j) k[j] = spin_times_field(w[j]);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) thr[j] = row[min(max(k[j] - 1, 0), kwm1)];
+          for (int j = 0; j < 4; ++j) thr[j] = row[clamp_row_index(k[j], kw)];
           const uint4 x = philox10(gw & kGroupLeaderMask, t, r, kTagSweep, k0, k1);
+          bool acc[4];
           uint32_t fm = 0;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const bool acc = (j < cnt) & ((k[j] <= 0) | all_pass |
-                                          ((k[j] <= len) & (pick(x, j) <= thr[j])));
-            fm |= (acc ? 1u : 0u) << j;
-            w[j] ^= acc ? 1 : 0;
-            dE += acc ? 2 * k[j] : 0;
+            acc[j] = (k[j] <= len) & (pick(x, j) <= thr[j]);
+            nacc += __popcll(__ballot(acc[j]));
+            fm |= (acc[j] ? 1u : 0u) << j;
+            w[j] ^= acc[j] ? 1 : 0;
+            dE += acc[j] ? 2 * k[j] : 0;
           }
+          const bool any = acc[0] | acc[1] | acc[2] | acc[3];
+          if (any) *reinterpret_cast<int4*>(st + 4 * g) = make_int4(w[0], w[1], w[2], w[3]);
           if (ADJ == kAdjLdsDeg4) {
-            if (fm) {
-              nacc += __popc(fm);
-              *reinterpret_cast<int4*>(st + 4 * g) = make_int4(w[0], w[1], w[2], w[3]);
-            }
             const uint32_t e[8] = {a01.x, a01.y, a01.z, a01.w, a23.x, a23.y, a23.z, a23.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-              if ((fm >> j) & 1u) {
+              if (acc[j]) {
                 const int q = (int)(neg >> (4 * j)) ^ -(w[j] & 1);
                 push_deg4_pair<0>(st_base, e[2 * j], q);
                 push_deg4_pair<2>(st_base, e[2 * j + 1], q);
               }
             }
           } else if (ADJ == kAdjLds) {
-            if (fm) {
-              nacc += __popc(fm);
-              *reinterpret_cast<int4*>(st + 4 * g) = make_int4(w[0], w[1], w[2], w[3]);
-            }
             push_wave_compacted(st, U.adj16, flist, U.gbase[g], U.gdeg[g], fm, w);
-          } else if (fm) {
-            nacc += __popc(fm);
-            *reinterpret_cast<int4*>(st + 4 * g) = make_int4(w[0], w[1], w[2], w[3]);
+          } else if (any) {
             push_group_global(st, aw, U.gbase[g], U.gdeg[g], fm, w);
           }
         }
@@ -664,8 +707,9 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
       *reinterpret_cast<int4*>(J.save + (int64_t)r * n_pad + 4 * g) = w4;
     }
   }
-  const int na = wave_sum(nacc);
-  if ((tid & 63) == 0 && na != 0) atomicAdd(&sh.nacc[rl], na);
+  // lane 0 takes part in every group iteration of its wave, so its count
+  // is the wave's
+  if ((tid & 63) == 0 && nacc != 0) atomicAdd(&sh.nacc[rl], nacc);
   __syncthreads();
   if (lt == 0 && live) {
     const unsigned long long prev = fresh ? 0ull : J.accepts[r];
@@ -794,7 +838,7 @@ __device__ void msc_unit(const JobDev& J, const int block, uint32_t* smem, MscSh
   const bool live = r0 < J.R;
   const int n_pad = J.n_pad, n_grp = n_pad >> 2;
   uint32_t* st = smem + wl * n_pad;
-  const UnitLds U = unit_lds(smem, Gw * n_pad, J.kw, n_grp);
+  const UnitLds U = unit_lds(smem, Gw * n_pad, 2 * J.kw, 0, n_grp);
   const uint32_t k0 = J.seed_lo, k1 = J.seed_hi;
   const int C = J.n_colours;
   const int W = J.W;

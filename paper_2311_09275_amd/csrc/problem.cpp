@@ -264,6 +264,7 @@ uint64_t threshold_q32(double beta, int64_t k) {
 int build_table(const std::vector<double>& beta, int32_t kmax, Table& t) {
   t = Table();
   t.S = (int)beta.size();
+  t.kmax = kmax;
   t.off.assign((size_t)t.S, 0);
   t.len.assign((size_t)t.S, 0);
   for (int s = 0; s < t.S; ++s) {

@@ -107,6 +107,7 @@ int eval_schedule(const ising_schedule* s, std::vector<double>& beta);
 uint64_t threshold_q32(double beta, int64_t k);
 struct Table {
   int S = 0, kw = 0;
+  int32_t kmax = 0;            // the problem's kmax the rows were built for
   std::vector<uint32_t> tq;    // Tq - 1
   std::vector<int32_t> off, len;
 };
@@ -139,6 +140,8 @@ struct RunBuffers {
   unsigned long long *accepts = nullptr, *argmax = nullptr;
   uint32_t* tq = nullptr;
   int32_t *tq_off = nullptr, *tq_len = nullptr;
+  uint32_t* tqp = nullptr;     // FIELD: padded rows [S][kw + 2]
+  std::vector<uint32_t> tqp_host;
   int8_t* init_dev = nullptr;
   JobDev* job_dev = nullptr;
   int layout_best = 0, layout_final = 0, layout_field = -1;
