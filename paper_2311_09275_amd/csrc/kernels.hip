@@ -39,15 +39,23 @@ constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
-// products; key advanced by the Weyl constants between rounds.
+// products; key advanced by the Weyl constants between rounds.  From the
+// third round on every word differs per lane, and each new word's two
+// XORs are one three-input bitwise operation (truth table 0x96); the first
+// two rounds keep plain XORs, which the compiler folds where counter words
+// are the same for the whole wave.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
                                           uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
     const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
     const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = i < 2 ? (uint32_t)(p1 >> 32) ^ c1 ^ k0 : xor3((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = i < 2 ? (uint32_t)(p0 >> 32) ^ c3 ^ k1 : xor3((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -474,9 +482,9 @@ __device__ __forceinline__ void push_deg4_pair(uint32_t base, uint32_t two, int 
 // k = (h XNOR m) + m + 1.  Written out (four operations where the compiler
 // emits five), like the threshold index: k clamped to [0, kw] by one
 // median-of-three.
-__device__ __forceinline__ int spin_times_field(int w) {
+__device__ __forceinline__ int spin_times_field(int w, int& m) {
   const int h = w >> 1;
-  int m, x, k;
+  int x, k;
   asm("v_bfe_i32 %0, %1, 0, 1" : "=v"(m) : "v"(w));
   asm("v_xnor_b32 %0, %1, %2" : "=v"(x) : "v"(h), "v"(m));
   asm("v_add3_u32 %0, %1, %2, 1" : "=v"(k) : "v"(x), "v"(m));
@@ -594,7 +602,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
 
   GLOBAL_AS int8_t* best = gmut(static_cast<int8_t*>(J.best)) + (int64_t)r * n_pad;
   const int kw = J.kw;
-  int dE = 0;
+  int dk = 0;    // sum of k over this lane's accepted flips (the energy moves by 2 k)
   int nacc = 0;  // accepted flips of this wave (wave-uniform)
   // class bounds of the next pass, read one pass ahead
   int nb0 = U.cls[0], nb1 = U.cls[1];
@@ -642,46 +650,60 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           // accepts k <= 0 and k above the row's length is refused by the
           // length test (padding slots have k = 2^30 - 1), so each slot's
           // test is two comparisons.
-          int k[4];
+          int k[4], m[4];  // m = -(spin bit)
           uint32_t thr[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) k[j] = spin_times_field(w[j]);
+          for (int j = 0; j < 4; ++j) k[j] = spin_times_field(w[j], m[j]);
 #pragma unroll
           for (int j = 0; j < 4; ++j) thr[j] = row[clamp_row_index(k[j], kw)];
+          // keep the reads ahead of the Philox arithmetic
+          __builtin_amdgcn_sched_barrier(0);
           const uint4 x = philox10(gw & kGroupLeaderMask, t, r, kTagSweep, k0, k1);
           bool acc[4];
-          uint32_t fm = 0;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             acc[j] = (k[j] <= len) & (pick(x, j) <= thr[j]);
             nacc += __popcll(__ballot(acc[j]));
-            fm |= (acc[j] ? 1u : 0u) << j;
-            w[j] ^= acc[j] ? 1 : 0;
-            dE += acc[j] ? 2 * k[j] : 0;
           }
-          const bool any = acc[0] | acc[1] | acc[2] | acc[3];
-          if (any) *reinterpret_cast<int4*>(st + 4 * g) = make_int4(w[0], w[1], w[2], w[3]);
           if (ADJ == kAdjLdsDeg4) {
+            // Within a pass only the owning lane touches a group's words
+            // (neighbours are in other classes), so a flip is an LDS XOR of
+            // the spin bit under the accept mask: no per-slot selects.
             const uint32_t e[8] = {a01.x, a01.y, a01.z, a01.w, a23.x, a23.y, a23.z, a23.w};
+            const uint32_t gaddr = st_base + 16u * (uint32_t)g;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               if (acc[j]) {
-                const int q = (int)(neg >> (4 * j)) ^ -(w[j] & 1);
+                __hip_atomic_fetch_xor((lds_i32*)(uintptr_t)(gaddr + 4 * j), 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                dk += k[j];
+                // new spin bit = old ^ 1, so q = neg ^ ~m
+                const int q = ~((int)(neg >> (4 * j)) ^ m[j]);
                 push_deg4_pair<0>(st_base, e[2 * j], q);
                 push_deg4_pair<2>(st_base, e[2 * j + 1], q);
               }
             }
-          } else if (ADJ == kAdjLds) {
-            push_wave_compacted(st, U.adj16, flist, U.gbase[g], U.gdeg[g], fm, w);
-          } else if (any) {
-            push_group_global(st, aw, U.gbase[g], U.gdeg[g], fm, w);
+          } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              w[j] = acc[j] ? w[j] ^ 1 : w[j];
+              dk += acc[j] ? k[j] : 0;
+            }
+            const bool any = acc[0] | acc[1] | acc[2] | acc[3];
+            if (any) *reinterpret_cast<int4*>(st + 4 * g) = make_int4(w[0], w[1], w[2], w[3]);
+            const uint32_t fm =
+                (acc[0] ? 1u : 0u) | (acc[1] ? 2u : 0u) | (acc[2] ? 4u : 0u) | (acc[3] ? 8u : 0u);
+            if (ADJ == kAdjLds)
+              push_wave_compacted(st, U.adj16, flist, U.gbase[g], U.gdeg[g], fm, w);
+            else if (any)
+              push_group_global(st, aw, U.gbase[g], U.gdeg[g], fm, w);
           }
         }
       }
       if (c == C - 1) {
-        const int s = wave_sum(dE);
+        const int s = 2 * wave_sum(dk);
         if ((tid & 63) == 0 && s != 0) atomicAdd(&sh.eacc[t % 3][rl], s);
-        dE = 0;
+        dk = 0;
       }
       __syncthreads();
     }
