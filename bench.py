@@ -58,6 +58,16 @@ def measured_traffic():
         return None
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,7 +195,8 @@ def main():
                  "attempts": bat_att, "batched_s": bat_s, "plain_s": plain_b_s,
                  "batched_attempts_per_s": bat_att / bat_s, "plain_attempts_per_s": bat_att / plain_b_s,
                  "tuning": {"path": int(tun.path), "replicas_per_block": int(tun.replicas_per_block),
-                            "block_threads": int(tun.block_threads)}}
+                            "block_threads": int(tun.block_threads),
+                            "lds_adjacency": int(tun.lds_adjacency)}}
         for p in probs:
             p.close()
 
@@ -208,9 +219,20 @@ def main():
                      r_end=sample, n_threads=threads, want_states=False)
         cpu_s = time.perf_counter() - t
         assert np.array_equal(o.best_cut, per_rep[:sample]), "oracle and GPU disagree"
+        # one thread on two replicas, for the per-core rate
+        t = time.perf_counter()
+        O.anneal(inst, S, R, SEED, kind=O.GEOMETRIC, beta0=B0, beta1=B1, r_begin=0, r_end=2,
+                 n_threads=1, want_states=False)
+        one_s = time.perf_counter() - t
         cpu = {"value": inst.n * sample * S / cpu_s, "unit": UNIT, "cores": threads, "kind": "oracle",
-               "sample": f"replicas 0..{sample - 1} of 256, all {S} sweeps, {threads} threads, {cpu_s:.1f} s"}
+               "sample": f"replicas 0..{sample - 1} of 256, all {S} sweeps, {threads} threads, {cpu_s:.1f} s",
+               "one_thread_value": inst.n * 2 * S / one_s, "cpu_model": cpu_model()}
         draws_per_attempt = float(o.draws.sum()) / (inst.n * sample * S)
+        if ttt_rows is not None:
+            # the oracle's wall time for all R replicas at its measured rate
+            oracle_wall = attempts / cpu["value"]
+            for row in ttt_rows.values():
+                row["ttt_oracle_s"] = ttt.replica_ttt(per_rep, row["target"], oracle_wall, S)["ttt_s"]
 
     # ------------------------------------------------------------ roofline
     # Algorithmic ALU work: the Philox blocks the method needs (counted by
@@ -235,6 +257,7 @@ def main():
         "plain_ms_per_step": plain_ms,
         "batched_vs_plain_speedup": None if plain_ms is None else plain_ms / ms_per_step,
         "create_ms": create_ms,
+        "value_incl_create": attempts / (ms_per_step / 1e3 + create_ms / 1e3),
         "best_cut": best_field,
         "reference_best_cut": c_ref,
         "ttt": ttt_rows,

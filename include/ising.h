@@ -242,10 +242,12 @@ int ising_anneal_batch(ising_problem* const* ps, int32_t count,
 int ising_last_batch_ms(double* ms);
 
 /*
- * Autotuner: time each launch candidate on a short prefix of sweeps of the
- * given batch and return the fastest in *best (also cached in memory and in
+ * Autotuner: time each launch candidate on a short trial anneal of the given
+ * batch -- prefix_sweeps sweeps whose betas are taken evenly spaced from the
+ * schedule -- and return the fastest in *best (also cached in memory and in
  * the file named by $ISING_TUNE_CACHE when set).  prefix_sweeps <= 0 picks
- * a default.
+ * 200 (or S when smaller).  The trial's results are discarded: each problem
+ * needs a new anneal before its results can be read.
  */
 int ising_autotune(ising_problem* const* ps, int32_t count,
                    const ising_schedule* s, int32_t n_replicas,

@@ -176,6 +176,7 @@ static void build_padded_rows(const Table& t, std::vector<uint32_t>& out) {
 
 // Staged adjacency forms of the FIELD kernel (16-bit entries).
 constexpr int kFormHbm = 0, kFormCsr = 1, kFormDeg4 = 2;
+constexpr int kFormPerJob = 3;  // a launch whose jobs use different forms
 
 // Extra LDS of a staged form: up to 12 bytes that align the entries to 16
 // bytes, then the CSR form's 2m entries, a gap word and the per-wave flip
@@ -450,20 +451,24 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
     int job, block;
   };
   std::vector<U> all;
-  size_t lds = 0, lds_deg4 = 0, lds_csr = 0;
-  // a staged form is used only when every job of the launch fits it
-  bool deg4_ok = cfg.path == ISING_PATH_FIELD && (cfg.adj == 0 || cfg.adj == 1);
-  bool csr_ok = cfg.path == ISING_PATH_FIELD && cfg.adj != 2;
+  // Each FIELD job stages the best adjacency form that fits it (degree-4,
+  // then CSR), else reads HBM; a launch whose jobs differ runs the kernel
+  // that picks the form per job.
+  std::vector<int> forms((size_t)n_jobs, kFormHbm);
+  size_t lds = 0, lds_staged = 0;
   int planes = 1;
   for (int j = 0; j < n_jobs; ++j) {
     const JobSpec& s = specs[(size_t)j];
     jobs[(size_t)j] = make_job(*s.g, *s.dg, *s.b, s.R, s.seed, s.t_begin, s.t_end, cfg);
-    lds = std::max(lds, persistent_lds(*s.g, s.b->table, cfg));
     const size_t own = persistent_lds(*s.g, s.b->table, cfg);
-    lds_deg4 = std::max(lds_deg4, own + adjacency_lds(*s.g, kFormDeg4));
-    lds_csr = std::max(lds_csr, own + adjacency_lds(*s.g, kFormCsr));
-    deg4_ok = deg4_ok && adjacency_fits(*s.g, kFormDeg4);
-    csr_ok = csr_ok && adjacency_fits(*s.g, kFormCsr);
+    lds = std::max(lds, own);
+    const int f = staged_form(*s.g, s.b->table, cfg);
+    if ((cfg.adj == 1 || cfg.adj == 3) && f == kFormHbm) {
+      set_error("the adjacency of problem %d cannot be staged in LDS", j);
+      return ISING_ERR_UNSUPPORTED;
+    }
+    forms[(size_t)j] = f;
+    lds_staged = std::max(lds_staged, own + (f != kFormHbm ? adjacency_lds(*s.g, f) : 0));
     planes = std::max(planes, msc_planes(s.g->max_deg));
     const int per = cfg.path == ISING_PATH_MSC ? 32 * cfg.G : cfg.G;
     const int nb = (s.R + per - 1) / per;
@@ -494,6 +499,26 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   }
   const int n_units = (int)units.size();
   if (n_units == 0) return ISING_OK;
+
+  const int cus = std::max(device_cu_count(), 1);
+  int form = forms.empty() ? kFormHbm : forms[0];
+  bool staged = false;
+  for (int f : forms) {
+    if (f != form) form = kFormPerJob;
+    staged = staged || f != kFormHbm;
+  }
+  if (cfg.adj == 0 && staged) {
+    // stage only when that does not cost concurrency the units could use
+    const int occ_adj = persistent_occupancy(cfg.path, cfg.block, form, lds_staged);
+    const int occ_plain = persistent_occupancy(cfg.path, cfg.block, kFormHbm, lds);
+    if (!(occ_adj > 0 && (occ_adj == occ_plain || (int64_t)n_units <= (int64_t)cus * occ_adj))) {
+      staged = false;
+      form = kFormHbm;
+      std::fill(forms.begin(), forms.end(), kFormHbm);
+    }
+  }
+  if (staged) lds = lds_staged;
+  for (int j = 0; j < n_jobs; ++j) jobs[(size_t)j].adj_form = forms[(size_t)j];
 
   // device and pinned staging buffers
   if (L.jobs_cap < (size_t)n_jobs || L.units_cap < (size_t)n_units || !L.arena.base) {
@@ -527,29 +552,6 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
                       sizeof(list_off), hipMemcpyHostToDevice, stream));
   ICHK(hipEventRecord(L.staged, stream));
 
-  const int cus = std::max(device_cu_count(), 1);
-  int form = kFormHbm;
-  size_t lds_adj = lds;
-  if (deg4_ok && lds_deg4 <= lds_budget(cfg.path)) {
-    form = kFormDeg4;
-    lds_adj = lds_deg4;
-  } else if (csr_ok && lds_csr <= lds_budget(cfg.path)) {
-    form = kFormCsr;
-    lds_adj = lds_csr;
-  }
-  if (cfg.adj == 1 || cfg.adj == 3) {
-    if (form == kFormHbm) {
-      set_error("the adjacency cannot be staged in LDS for this batch");
-      return ISING_ERR_UNSUPPORTED;
-    }
-  } else if (cfg.adj == 0 && form != kFormHbm) {
-    // stage it when that does not cost concurrency the units could use
-    const int occ_adj = persistent_occupancy(cfg.path, cfg.block, form, lds_adj);
-    const int occ_plain = persistent_occupancy(cfg.path, cfg.block, kFormHbm, lds);
-    if (!(occ_adj > 0 && (occ_adj == occ_plain || (int64_t)n_units <= (int64_t)cus * occ_adj)))
-      form = kFormHbm;
-  }
-  if (form != kFormHbm) lds = lds_adj;
   // raising the dynamic LDS limit is advisory on this runtime
   if (set_persistent_lds_limit(cfg.path, cfg.block, lds) != hipSuccess) (void)hipGetLastError();
   const int occ = persistent_occupancy(cfg.path, cfg.block, form, lds);

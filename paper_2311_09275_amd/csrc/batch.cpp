@@ -236,8 +236,11 @@ int ising_autotune(ising_problem* const* ps, int32_t count, const ising_schedule
   IRET(eval_schedule(s, beta));
   const int S = (int)beta.size();
   const int prefix = prefix_sweeps > 0 ? std::min(prefix_sweeps, S) : std::min(S, 200);
-  // the prefix anneals the first sweeps of the real schedule
-  std::vector<double> pre(beta.begin(), beta.begin() + prefix);
+  // The trial anneal takes sweeps spread evenly over the real schedule, so
+  // that it meets each temperature for the same share of its sweeps: the
+  // paths' costs depend on how many moves are accepted.
+  std::vector<double> pre((size_t)prefix);
+  for (int i = 0; i < prefix; ++i) pre[(size_t)i] = beta[(size_t)((int64_t)i * S / prefix)];
   ising_schedule ps_sched{ISING_SCHED_EXPLICIT, prefix, 0, 0, pre.data()};
   std::vector<Table> tables;
   IRET(batch_tables(ps, count, &ps_sched, tables));
@@ -248,7 +251,9 @@ int ising_autotune(ising_problem* const* ps, int32_t count, const ising_schedule
   for (int i = 0; i < count; ++i) seeds[(size_t)i] = 0x5EEDull + (uint64_t)i;
 
   std::vector<PersistentConfig> cands;
-  for (int adj : {1, 2})
+  // adjacency: 0 = each problem's staged form unless that costs occupancy
+  // (mixed forms in one launch), 1 = staged for every problem, 2 = HBM
+  for (int adj : {0, 1, 2})
     for (int block : {256, 512, 1024})
       for (int G : {1, 2, 4, 8, 16}) cands.push_back(PersistentConfig{ISING_PATH_FIELD, G, block, adj});
   for (int block : {256, 512})

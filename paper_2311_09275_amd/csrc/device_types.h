@@ -68,6 +68,7 @@ struct JobDev {
   uint32_t seed_lo, seed_hi;
   int32_t R;             // replicas
   int32_t G;             // FIELD: replicas per block; MSC: words per block
+  int32_t adj_form;      // FIELD: this job's staged adjacency form (mixed launches)
   const int8_t* init_spins;  // [R][n_pad] +-1, positions order
   // state and outputs
   int32_t* save;         // FIELD: [R][n_pad] packed (h<<1)|bit; MSC: [nw][n_pad] words

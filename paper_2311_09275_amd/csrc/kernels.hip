@@ -265,6 +265,7 @@ struct UnitLds {
 constexpr int kAdjHbm = 0;      // {position, w} pairs read from HBM
 constexpr int kAdjLds = 1;      // 16-bit CSR entries in LDS, wave-compacted pushes
 constexpr int kAdjLdsDeg4 = 2;  // every vertex of degree 4: 32 bytes per group
+constexpr int kAdjPerJob = 3;   // each job's own form (JobDev::adj_form), for mixed batches
 
 __device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int tq_words,
                                             int cls_words, int n_grp) {
@@ -757,7 +758,15 @@ k_field(const JobDev* __restrict__ jobs, const int2* __restrict__ units,
     if (u < 0) break;
     const int2 un = units[u];
     const JobDev J = jobs[un.x];  // by value: fields stay in registers
-    field_unit<BLOCK, ADJ>(J, un.y, smem, sh);
+    if (ADJ != kAdjPerJob) {
+      field_unit<BLOCK, ADJ>(J, un.y, smem, sh);
+    } else if (J.adj_form == kAdjLdsDeg4) {
+      field_unit<BLOCK, kAdjLdsDeg4>(J, un.y, smem, sh);
+    } else if (J.adj_form == kAdjLds) {
+      field_unit<BLOCK, kAdjLds>(J, un.y, smem, sh);
+    } else {
+      field_unit<BLOCK, kAdjHbm>(J, un.y, smem, sh);
+    }
   }
 }
 
@@ -1155,6 +1164,10 @@ hipError_t launch_field_t(const LaunchPersistent& L, hipStream_t s) {
       hipLaunchKernelGGL((k_field<BLOCK, kAdjLdsDeg4>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s,
                          L.jobs, L.units, L.list_off, L.ctr);
       break;
+    case kAdjPerJob:
+      hipLaunchKernelGGL((k_field<BLOCK, kAdjPerJob>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s,
+                         L.jobs, L.units, L.list_off, L.ctr);
+      break;
     default:
       return hipErrorInvalidValue;
   }
@@ -1163,9 +1176,10 @@ hipError_t launch_field_t(const LaunchPersistent& L, hipStream_t s) {
 
 template <int BLOCK>
 const void* field_kernel(int adj) {
-  return adj == kAdjLds ? (const void*)k_field<BLOCK, kAdjLds>
-                        : adj == kAdjLdsDeg4 ? (const void*)k_field<BLOCK, kAdjLdsDeg4>
-                                             : (const void*)k_field<BLOCK, kAdjHbm>;
+  return adj == kAdjLds       ? (const void*)k_field<BLOCK, kAdjLds>
+         : adj == kAdjLdsDeg4 ? (const void*)k_field<BLOCK, kAdjLdsDeg4>
+         : adj == kAdjPerJob  ? (const void*)k_field<BLOCK, kAdjPerJob>
+                              : (const void*)k_field<BLOCK, kAdjHbm>;
 }
 
 template <int BLOCK>
@@ -1246,7 +1260,7 @@ int persistent_occupancy(int path, int block, int adj, size_t lds_bytes) {
 hipError_t set_persistent_lds_limit(int path, int block, size_t lds_bytes) {
   const void* f = nullptr;
   if (path == 2) {
-    for (int adj : {kAdjLds, kAdjLdsDeg4}) {
+    for (int adj : {kAdjLds, kAdjLdsDeg4, kAdjPerJob}) {
       const void* k = block == 256 ? field_kernel<256>(adj)
                                    : block == 512 ? field_kernel<512>(adj) : field_kernel<1024>(adj);
       hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);

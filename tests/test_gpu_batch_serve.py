@@ -56,6 +56,32 @@ def test_batch_equals_separate_anneals(tun):
         p.close()
 
 
+@pytest.mark.parametrize("tun", [B.Tuning(B.PATH_FIELD, 1, 1024, 0), B.Tuning(B.PATH_FIELD, 2, 512, 0)],
+                         ids=["g1_b1024", "g2_b512"])
+def test_batch_mixed_adjacency_forms(tun):
+    """One launch whose problems stage different adjacency forms: a small
+    torus (degree-4 form), a random graph (CSR form) and a torus too large
+    to stage (adjacency read from HBM)."""
+    insts = [I.torus(24, 24, 111), I.random_graph(700, 699, 112), I.torus(110, 110, 113),
+             I.torus(9, 11, 114)]
+    sched = B.Schedule.make(B.GEOMETRIC, 120, 0.1, 4.0)
+    R = 40
+    seeds = np.array([7100 + i for i in range(len(insts))], np.uint64)
+    probs = [B.Problem.from_instance(x) for x in insts]
+    B.ising_anneal_batch([p.handle for p in probs], sched, R, seeds, tun)
+    for i, (inst, p) in enumerate(zip(insts, probs)):
+        per, bs, acc, en, state = _single(inst, sched, R, int(seeds[i]), B.Tuning(B.PATH_PLAIN, 1, 256, 0))
+        best, arg, per_b = B.ising_cut(p.handle, R)
+        bs_b, acc_b, en_b = p.replica_results()
+        np.testing.assert_array_equal(per_b, per, err_msg=inst.name)
+        np.testing.assert_array_equal(bs_b, bs, err_msg=inst.name)
+        np.testing.assert_array_equal(acc_b, acc, err_msg=inst.name)
+        np.testing.assert_array_equal(en_b, en, err_msg=inst.name)
+        np.testing.assert_array_equal(p.best_state(), state, err_msg=inst.name)
+    for p in probs:
+        p.close()
+
+
 def test_graph_replays_match_eager():
     import torch
     insts = _batch_instances()[:4]
