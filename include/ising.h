@@ -152,7 +152,10 @@ enum {
  *                        fixed 32-byte-per-group form when every vertex has
  *                        degree 4, else CSR order), 2 = read the adjacency
  *                        from HBM, 3 = stage it in CSR order even when the
- *                        degree-4 form applies
+ *                        degree-4 form applies, 4 = read the degree-4 form
+ *                        from HBM (unit weights, every vertex of degree 4,
+ *                        at most 2^16 vertices).  With 0 a graph whose
+ *                        degree-4 form does not fit LDS reads it from HBM.
  */
 typedef struct {
   int32_t path;

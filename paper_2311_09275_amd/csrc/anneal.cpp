@@ -91,7 +91,9 @@ int upload_graph(const HostGraph& g, DevGraph& d) {
                  DeviceArena::span(sizeof(int2) * e2) +
                  3 * DeviceArena::span(sizeof(int32_t) * g.grp.size()) +
                  DeviceArena::span(sizeof(int32_t) * g.cls.size()) +
-                 DeviceArena::span(sizeof(int32_t) * g.n);
+                 DeviceArena::span(sizeof(int32_t) * g.n) +
+                 DeviceArena::span(sizeof(uint32_t) * g.adj4.size()) +
+                 DeviceArena::span(sizeof(uint32_t) * g.neg4.size());
   IRET(d.arena.reserve(bytes));
   d.device = d.arena.device;
   d.row = d.arena.take<int32_t>(g.n_pad + 1);
@@ -104,6 +106,12 @@ int upload_graph(const HostGraph& g, DevGraph& d) {
   d.gdeg = d.arena.take<uint32_t>(g.grp.size());
   d.cls = d.arena.take<int32_t>(g.cls.size());
   d.pos = d.arena.take<int32_t>(g.n);
+  d.adj4 = g.adj4.empty() ? nullptr : d.arena.take<uint32_t>(g.adj4.size());
+  d.neg4 = g.neg4.empty() ? nullptr : d.arena.take<uint32_t>(g.neg4.size());
+  if (d.adj4) {
+    ICHK(hipMemcpy(d.adj4, g.adj4.data(), sizeof(uint32_t) * g.adj4.size(), hipMemcpyHostToDevice));
+    ICHK(hipMemcpy(d.neg4, g.neg4.data(), sizeof(uint32_t) * g.neg4.size(), hipMemcpyHostToDevice));
+  }
   ICHK(hipMemcpy(d.row, g.row.data(), sizeof(int32_t) * g.row.size(), hipMemcpyHostToDevice));
   if (e2) {
     ICHK(hipMemcpy(d.adj, g.adj.data(), sizeof(int32_t) * e2, hipMemcpyHostToDevice));
@@ -176,31 +184,42 @@ static void build_padded_rows(const Table& t, std::vector<uint32_t>& out) {
 
 // Staged adjacency forms of the FIELD kernel (16-bit entries).
 constexpr int kFormHbm = 0, kFormCsr = 1, kFormDeg4 = 2;
-constexpr int kFormPerJob = 3;  // a launch whose jobs use different forms
+constexpr int kFormPerJob = 3;   // a launch whose jobs use different forms
+constexpr int kFormHbmDeg4 = 4;  // degree-4 blocks read from HBM (too large for LDS)
 
 // Extra LDS of a staged form: up to 12 bytes that align the entries to 16
 // bytes, then the CSR form's 2m entries, a gap word and the per-wave flip
 // lists (256 entries per wave of the largest block), or the degree-4 form's
 // 32 bytes of positions and 4 bytes of weight signs per group.
 static size_t adjacency_lds(const HostGraph& g, int form) {
+  if (form == kFormHbmDeg4) return 0;
   if (form == kFormDeg4) return 12 + 36 * (size_t)(g.n_pad / 4);
   return 12 + 4 * (size_t)g.m + 4 + (size_t)(1024 / 64) * 256 * 4;
 }
 static bool adjacency_fits(const HostGraph& g, int form) {
+  if (form == kFormHbmDeg4) return !g.adj4.empty();
   if (form == kFormDeg4) return g.unit && g.deg4 && g.n_pad < (1 << 15);
   return g.unit && g.n_pad < (1 << 15) && 2 * g.m < (1 << 17) && g.max_deg <= 255;
 }
-// The form that tuning value `adj` (0 decide, 1 LDS, 2 HBM, 3 LDS in CSR
-// form) stages for g, if it fits the LDS budget; kFormHbm when none does.
+// The adjacency form that tuning value `adj` (0 decide, 1 LDS, 2 HBM
+// pairs, 3 LDS in CSR form, 4 degree-4 blocks from HBM) gives g: the
+// degree-4 form staged in LDS when it fits, else its blocks read from HBM,
+// else the CSR form staged; kFormHbm ({position, w} pairs) otherwise.  For
+// adj = 1 and 3 the caller refuses a result that is not staged.
 static int staged_form(const HostGraph& g, const Table& t, const PersistentConfig& c) {
   if (c.path != ISING_PATH_FIELD || c.adj == 2) return kFormHbm;
+  if (c.adj == 4) return adjacency_fits(g, kFormHbmDeg4) ? kFormHbmDeg4 : kFormHbm;
   const size_t base = persistent_lds(g, t, c);
-  for (int form : {kFormDeg4, kFormCsr}) {
-    if (form == kFormDeg4 && c.adj == 3) continue;
-    if (adjacency_fits(g, form) && base + adjacency_lds(g, form) <= lds_budget(c.path)) return form;
-  }
-  return kFormHbm;
+  const bool fits_deg4 = adjacency_fits(g, kFormDeg4) &&
+                         base + adjacency_lds(g, kFormDeg4) <= lds_budget(c.path);
+  const bool fits_csr = adjacency_fits(g, kFormCsr) &&
+                        base + adjacency_lds(g, kFormCsr) <= lds_budget(c.path);
+  if (c.adj == 3) return fits_csr ? kFormCsr : kFormHbm;
+  if (fits_deg4) return kFormDeg4;
+  if (c.adj == 0 && adjacency_fits(g, kFormHbmDeg4)) return kFormHbmDeg4;
+  return fits_csr ? kFormCsr : kFormHbm;
 }
+static bool form_in_lds(int form) { return form == kFormCsr || form == kFormDeg4; }
 
 int check_config(const HostGraph& g, const Table& t, int R, const PersistentConfig& c) {
   (void)R;
@@ -218,11 +237,16 @@ int check_config(const HostGraph& g, const Table& t, int R, const PersistentConf
     set_error("replicas_per_block %d invalid for %d threads", c.G, c.block);
     return ISING_ERR_INVALID;
   }
-  if (c.adj < 0 || c.adj > 3) {
+  if (c.adj < 0 || c.adj > 4) {
     set_error("adjacency mode %d invalid", c.adj);
     return ISING_ERR_INVALID;
   }
-  if ((c.adj == 1 || c.adj == 3) && staged_form(g, t, c) == kFormHbm) {
+  if (c.adj == 4 && (c.path != ISING_PATH_FIELD || !adjacency_fits(g, kFormHbmDeg4))) {
+    set_error("the degree-4 adjacency form needs unit weights, every vertex of degree 4 "
+              "and at most 2^16 positions");
+    return ISING_ERR_UNSUPPORTED;
+  }
+  if ((c.adj == 1 || c.adj == 3) && !form_in_lds(staged_form(g, t, c))) {
     set_error("the adjacency cannot be staged in LDS for this problem");
     return ISING_ERR_UNSUPPORTED;
   }
@@ -406,6 +430,8 @@ JobDev make_job(const HostGraph& g, const DevGraph& d, const RunBuffers& b, int 
   J.adj = d.adj;
   J.wgt = d.wgt;
   J.adjm = d.adjm;
+  J.adj4 = reinterpret_cast<const uint4*>(d.adj4);
+  J.neg4 = d.neg4;
   J.aw = d.aw;
   J.grp = d.grp;
   J.gbase = d.gbase;
@@ -463,12 +489,12 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
     const size_t own = persistent_lds(*s.g, s.b->table, cfg);
     lds = std::max(lds, own);
     const int f = staged_form(*s.g, s.b->table, cfg);
-    if ((cfg.adj == 1 || cfg.adj == 3) && f == kFormHbm) {
+    if ((cfg.adj == 1 || cfg.adj == 3) && !form_in_lds(f)) {
       set_error("the adjacency of problem %d cannot be staged in LDS", j);
       return ISING_ERR_UNSUPPORTED;
     }
     forms[(size_t)j] = f;
-    lds_staged = std::max(lds_staged, own + (f != kFormHbm ? adjacency_lds(*s.g, f) : 0));
+    lds_staged = std::max(lds_staged, own + (form_in_lds(f) ? adjacency_lds(*s.g, f) : 0));
     planes = std::max(planes, msc_planes(s.g->max_deg));
     const int per = cfg.path == ISING_PATH_MSC ? 32 * cfg.G : cfg.G;
     const int nb = (s.R + per - 1) / per;
@@ -505,16 +531,22 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   bool staged = false;
   for (int f : forms) {
     if (f != form) form = kFormPerJob;
-    staged = staged || f != kFormHbm;
+    staged = staged || form_in_lds(f);
   }
   if (cfg.adj == 0 && staged) {
     // stage only when that does not cost concurrency the units could use
     const int occ_adj = persistent_occupancy(cfg.path, cfg.block, form, lds_staged);
     const int occ_plain = persistent_occupancy(cfg.path, cfg.block, kFormHbm, lds);
     if (!(occ_adj > 0 && (occ_adj == occ_plain || (int64_t)n_units <= (int64_t)cus * occ_adj))) {
+      // keep the forms that need no LDS
       staged = false;
-      form = kFormHbm;
-      std::fill(forms.begin(), forms.end(), kFormHbm);
+      form = -1;
+      for (size_t j = 0; j < forms.size(); ++j) {
+        const JobSpec& s = specs[j];
+        if (form_in_lds(forms[j]))
+          forms[j] = adjacency_fits(*s.g, kFormHbmDeg4) ? kFormHbmDeg4 : kFormHbm;
+        form = form < 0 || form == forms[j] ? forms[j] : kFormPerJob;
+      }
     }
   }
   if (staged) lds = lds_staged;

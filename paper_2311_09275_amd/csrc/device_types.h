@@ -46,6 +46,8 @@ struct JobDev {
   const int32_t* wgt;    // [2m] MaxCut weight w (coupling J = -w)
   const uint32_t* adjm;  // [2m] (position << 1) | (w > 0), unit weights only
   const int2* aw;        // [2m] {neighbour position, w}
+  const uint4* adj4;     // degree-4 graphs: [n_pad/4][2] 16-bit neighbour positions
+  const uint32_t* neg4;  // degree-4 graphs: [n_pad/4] negative-weight bits (4 j + e)
   const int32_t* grp;    // [n_pad/4] group words
   const int32_t* gbase;  // [n_pad/4] first adjacency entry of the group
   const uint32_t* gdeg;  // [n_pad/4] degrees of the group's four slots, 8 bits each

@@ -26,7 +26,8 @@ struct LaunchPersistent {
   int planes;              // MSC: bit planes of the unsatisfied-bond counter
   int adj;                 // FIELD: 0 = adjacency in HBM, 1 = staged 16-bit CSR,
                            // 2 = staged degree-4 form (every vertex of degree 4),
-                           // 3 = each job's own form (JobDev::adj_form)
+                           // 3 = each job's own form (JobDev::adj_form),
+                           // 4 = degree-4 blocks read from HBM
 };
 
 hipError_t launch_plain_anneal(const PlainDev& P, const PlainPlan& plan, hipStream_t s);

@@ -266,6 +266,7 @@ constexpr int kAdjHbm = 0;      // {position, w} pairs read from HBM
 constexpr int kAdjLds = 1;      // 16-bit CSR entries in LDS, wave-compacted pushes
 constexpr int kAdjLdsDeg4 = 2;  // every vertex of degree 4: 32 bytes per group
 constexpr int kAdjPerJob = 3;   // each job's own form (JobDev::adj_form), for mixed batches
+constexpr int kAdjHbmDeg4 = 4;  // the degree-4 blocks read from HBM (graphs too large for LDS)
 
 __device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int tq_words,
                                             int cls_words, int n_grp) {
@@ -639,6 +640,12 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             a01 = reinterpret_cast<const uint4*>(U.adj16)[2 * g];
             a23 = reinterpret_cast<const uint4*>(U.adj16)[2 * g + 1];
             neg = U.gneg[g];
+          } else if (ADJ == kAdjHbmDeg4) {
+            const GLOBAL_AS u32x4* a4 = gconst(reinterpret_cast<const u32x4*>(J.adj4)) + 2 * g;
+            const u32x4 b01 = a4[0], b23 = a4[1];
+            a01 = make_uint4(b01.x, b01.y, b01.z, b01.w);
+            a23 = make_uint4(b23.x, b23.y, b23.z, b23.w);
+            neg = gconst(J.neg4)[g];
           }
           int w[4] = {w4.x, w4.y, w4.z, w4.w};
           if (snap) {
@@ -666,7 +673,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             acc[j] = (k[j] <= len) & (pick(x, j) <= thr[j]);
             nacc += __popcll(__ballot(acc[j]));
           }
-          if (ADJ == kAdjLdsDeg4) {
+          if (ADJ == kAdjLdsDeg4 || ADJ == kAdjHbmDeg4) {
             // Within a pass only the owning lane touches a group's words
             // (neighbours are in other classes), so a flip is an LDS XOR of
             // the spin bit under the accept mask: no per-slot selects.
@@ -764,6 +771,8 @@ k_field(const JobDev* __restrict__ jobs, const int2* __restrict__ units,
       field_unit<BLOCK, kAdjLdsDeg4>(J, un.y, smem, sh);
     } else if (J.adj_form == kAdjLds) {
       field_unit<BLOCK, kAdjLds>(J, un.y, smem, sh);
+    } else if (J.adj_form == kAdjHbmDeg4) {
+      field_unit<BLOCK, kAdjHbmDeg4>(J, un.y, smem, sh);
     } else {
       field_unit<BLOCK, kAdjHbm>(J, un.y, smem, sh);
     }
@@ -1168,6 +1177,10 @@ hipError_t launch_field_t(const LaunchPersistent& L, hipStream_t s) {
       hipLaunchKernelGGL((k_field<BLOCK, kAdjPerJob>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s,
                          L.jobs, L.units, L.list_off, L.ctr);
       break;
+    case kAdjHbmDeg4:
+      hipLaunchKernelGGL((k_field<BLOCK, kAdjHbmDeg4>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s,
+                         L.jobs, L.units, L.list_off, L.ctr);
+      break;
     default:
       return hipErrorInvalidValue;
   }
@@ -1179,6 +1192,7 @@ const void* field_kernel(int adj) {
   return adj == kAdjLds       ? (const void*)k_field<BLOCK, kAdjLds>
          : adj == kAdjLdsDeg4 ? (const void*)k_field<BLOCK, kAdjLdsDeg4>
          : adj == kAdjPerJob  ? (const void*)k_field<BLOCK, kAdjPerJob>
+         : adj == kAdjHbmDeg4 ? (const void*)k_field<BLOCK, kAdjHbmDeg4>
                               : (const void*)k_field<BLOCK, kAdjHbm>;
 }
 
@@ -1260,7 +1274,7 @@ int persistent_occupancy(int path, int block, int adj, size_t lds_bytes) {
 hipError_t set_persistent_lds_limit(int path, int block, size_t lds_bytes) {
   const void* f = nullptr;
   if (path == 2) {
-    for (int adj : {kAdjLds, kAdjLdsDeg4, kAdjPerJob}) {
+    for (int adj : {kAdjLds, kAdjLdsDeg4, kAdjPerJob, kAdjHbmDeg4}) {
       const void* k = block == 256 ? field_kernel<256>(adj)
                                    : block == 512 ? field_kernel<512>(adj) : field_kernel<1024>(adj);
       hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);

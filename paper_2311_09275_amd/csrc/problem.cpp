@@ -201,6 +201,21 @@ int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, cons
   }
   g.deg4 = n > 0;
   for (int32_t i = 0; i < n && g.deg4; ++i) g.deg4 = deg[(size_t)i + 1] - deg[(size_t)i] == 4;
+  if (g.deg4 && g.unit && g.n_pad <= (1 << 16)) {
+    const size_t ng = (size_t)g.n_pad / 4;
+    g.adj4.assign(8 * ng, 0u);
+    g.neg4.assign(ng, 0u);
+    for (size_t q = 0; q < ng; ++q)
+      for (int j = 0; j < 4; ++j) {
+        if (g.orig[4 * q + (size_t)j] < 0) continue;  // padding slot: never pushed
+        const int32_t o = g.row[4 * q + (size_t)j];
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t pos = (uint32_t)g.adj[(size_t)(o + e)];
+          g.adj4[8 * q + (size_t)(2 * j + e / 2)] |= pos << (16 * (e & 1));
+          if (g.wgt[(size_t)(o + e)] < 0) g.neg4[q] |= 1u << (4 * j + e);
+        }
+      }
+  }
   return ISING_OK;
 }
 

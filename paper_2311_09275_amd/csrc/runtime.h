@@ -97,6 +97,10 @@ struct HostGraph {
   std::vector<int32_t> aw;             // [2m][2] {position, w}
   std::vector<int32_t> gbase;          // [n_pad/4] = row[4g]
   std::vector<uint32_t> gdeg;          // [n_pad/4] packed slot degrees
+  // degree-4 graphs with fewer than 2^16 positions: per group eight words
+  // of 16-bit neighbour positions (slot j's four at 16-bit index 4j..4j+3)
+  // and a word whose bit 4j+e is set when entry e of slot j has w < 0
+  std::vector<uint32_t> adj4, neg4;
 };
 
 int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, const int32_t* w,
@@ -121,6 +125,7 @@ struct DevGraph {
   int32_t *row = nullptr, *adj = nullptr, *wgt = nullptr, *grp = nullptr, *cls = nullptr,
           *pos = nullptr, *gbase = nullptr;
   uint32_t *adjm = nullptr, *gdeg = nullptr;
+  uint32_t *adj4 = nullptr, *neg4 = nullptr;
   int2* aw = nullptr;
 };
 int upload_graph(const HostGraph& g, DevGraph& d);

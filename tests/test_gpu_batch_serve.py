@@ -59,11 +59,12 @@ def test_batch_equals_separate_anneals(tun):
 @pytest.mark.parametrize("tun", [B.Tuning(B.PATH_FIELD, 1, 1024, 0), B.Tuning(B.PATH_FIELD, 2, 512, 0)],
                          ids=["g1_b1024", "g2_b512"])
 def test_batch_mixed_adjacency_forms(tun):
-    """One launch whose problems stage different adjacency forms: a small
-    torus (degree-4 form), a random graph (CSR form) and a torus too large
-    to stage (adjacency read from HBM)."""
+    """One launch whose problems use different adjacency forms: a small
+    torus (degree-4 form in LDS), a random graph (CSR form in LDS), a torus
+    too large to stage (degree-4 form read from HBM) and a weighted graph
+    ({position, w} pairs from HBM)."""
     insts = [I.torus(24, 24, 111), I.random_graph(700, 699, 112), I.torus(110, 110, 113),
-             I.torus(9, 11, 114)]
+             I.torus(9, 11, 114), I.random_weighted(300, 800, 115, 5)]
     sched = B.Schedule.make(B.GEOMETRIC, 120, 0.1, 4.0)
     R = 40
     seeds = np.array([7100 + i for i in range(len(insts))], np.uint64)

@@ -21,6 +21,7 @@ PATHS = {
     "field_g1_b1024_ldsadj": B.Tuning(B.PATH_FIELD, 1, 1024, 1),
     "field_g1_b1024_csradj": B.Tuning(B.PATH_FIELD, 1, 1024, 3),
     "field_g4_b256_csradj": B.Tuning(B.PATH_FIELD, 4, 256, 3),
+    "field_g1_b512_hbmdeg4": B.Tuning(B.PATH_FIELD, 1, 512, 4),
     "field_g2_b512_ldsadj": B.Tuning(B.PATH_FIELD, 2, 512, 1),
     "field_g4_b256_hbmadj": B.Tuning(B.PATH_FIELD, 4, 256, 2),
     "field_g1_b512_auto": B.Tuning(B.PATH_FIELD, 1, 512, 0),
@@ -39,6 +40,10 @@ def compare(inst, S, R, seed, kind=O.LINEAR, b0=0.1, b1=3.0, betas=None, tuning=
             init=None, replicas=None, trace=True, colour=None):
     """Run the GPU path and check it against the oracle on `replicas`."""
     n = inst.n
+    if tuning is not None and tuning.lds_adjacency == 4:
+        deg = np.bincount(np.concatenate([inst.u, inst.v]), minlength=n)
+        if n == 0 or not (deg == 4).all() or not (np.abs(inst.w) == 1).all():
+            pytest.skip("the degree-4 form needs a 4-regular unit-weight graph")
     sched, okw = _sched(kind, S, b0, b1, betas)
     p = B.Problem.from_instance(inst, colour)
     if init is not None:
@@ -122,7 +127,8 @@ def test_weighted_graph(path):
 
 def test_unit_weight_paths_reject_weighted():
     p = B.Problem.from_instance(I.random_weighted(50, 100, 1, 3))
-    for path in ("msc_g1_b256", "field_g1_b1024_ldsadj", "field_g1_b1024_csradj"):
+    for path in ("msc_g1_b256", "field_g1_b1024_ldsadj", "field_g1_b1024_csradj",
+                 "field_g1_b512_hbmdeg4"):
         with pytest.raises(B.IsingError) as e:
             p.anneal(B.Schedule.make(B.LINEAR, 10, 0.1, 1.0), 32, 1, PATHS[path])
         assert e.value.status == B.ERR_UNSUPPORTED
