@@ -41,6 +41,7 @@ int DeviceArena::reserve(size_t bytes) {
   }
   base = static_cast<char*>(p);
   cap = bytes;
+  ++generation;
   return ISING_OK;
 }
 
@@ -387,18 +388,28 @@ int prepare_buffers(RunBuffers& b, const HostGraph& g, const Table& table, int R
   if (!b.ev0) ICHK(hipEventCreate(&b.ev0));
   if (!b.ev1) ICHK(hipEventCreate(&b.ev1));
   b.stream = stream;
-  // the host copy outlives the asynchronous uploads (until the next run)
-  b.table = table;
-  ICHK(hipMemcpyAsync(b.tq, b.table.tq.data(), sizeof(uint32_t) * b.table.tq.size(),
-                      hipMemcpyHostToDevice, stream));
-  ICHK(hipMemcpyAsync(b.tq_off, b.table.off.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice,
-                      stream));
-  ICHK(hipMemcpyAsync(b.tq_len, b.table.len.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice,
-                      stream));
-  if (b.tqp) {
-    build_padded_rows(b.table, b.tqp_host);
-    ICHK(hipMemcpyAsync(b.tqp, b.tqp_host.data(), sizeof(uint32_t) * b.tqp_host.size(),
+  // The tables are uploaded unless this same table already sits at these
+  // addresses of this same arena (a pool's memory is always rewritten).
+  const void* at = b.tqp ? (const void*)b.tqp : (const void*)b.tq;
+  const bool resident = !pool && table.id != 0 && b.up_table == table.id &&
+                        b.up_generation == b.arena.generation && b.up_at == at;
+  if (!resident) {
+    // the host copy outlives the asynchronous uploads (until the next run)
+    b.table = table;
+    ICHK(hipMemcpyAsync(b.tq, b.table.tq.data(), sizeof(uint32_t) * b.table.tq.size(),
                         hipMemcpyHostToDevice, stream));
+    ICHK(hipMemcpyAsync(b.tq_off, b.table.off.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice,
+                        stream));
+    ICHK(hipMemcpyAsync(b.tq_len, b.table.len.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice,
+                        stream));
+    if (b.tqp) {
+      build_padded_rows(b.table, b.tqp_host);
+      ICHK(hipMemcpyAsync(b.tqp, b.tqp_host.data(), sizeof(uint32_t) * b.tqp_host.size(),
+                          hipMemcpyHostToDevice, stream));
+    }
+    b.up_table = table.id;
+    b.up_generation = b.arena.generation;
+    b.up_at = at;
   }
   if (init_given) {
     std::vector<int8_t> perm(RR * np, 1);
@@ -772,13 +783,35 @@ int ising_set_trace(ising_problem* p, int32_t enable) {
 static int resolve_config(ising_problem* p, const Table& table, int R, const ising_tuning* t,
                           PersistentConfig& cfg);
 
-int ising_anneal_tuned(ising_problem* p, const ising_schedule* s, int32_t n_replicas,
-                       uint64_t seed, const ising_tuning* tuning, void* stream) {
-  if (!p || !s || n_replicas < 1) return ISING_ERR_INVALID;
+// Thresholds of schedule s for p, rebuilt only when s differs from the last
+// schedule p annealed with (the table costs S * kmax exponentials).
+static int schedule_table(ising_problem* p, const ising_schedule* s) {
+  auto& c = p->sched;
+  const bool expl = s->kind == ISING_SCHED_EXPLICIT;
+  if (c.table.id != 0 && c.kind == s->kind && c.n_sweeps == s->n_sweeps && s->n_sweeps > 0) {
+    const bool same = expl ? (s->betas && c.betas.size() == (size_t)s->n_sweeps &&
+                              memcmp(c.betas.data(), s->betas, sizeof(double) * c.betas.size()) == 0)
+                           : (c.beta0 == s->beta0 && c.beta1 == s->beta1);
+    if (same) return ISING_OK;
+  }
   std::vector<double> beta;
   IRET(eval_schedule(s, beta));
   Table table;
   IRET(build_table(beta, p->g.kmax, table));
+  c.table = std::move(table);
+  c.kind = s->kind;
+  c.n_sweeps = s->n_sweeps;
+  c.beta0 = s->beta0;
+  c.beta1 = s->beta1;
+  c.betas.assign(expl ? s->betas : nullptr, expl ? s->betas + s->n_sweeps : nullptr);
+  return ISING_OK;
+}
+
+int ising_anneal_tuned(ising_problem* p, const ising_schedule* s, int32_t n_replicas,
+                       uint64_t seed, const ising_tuning* tuning, void* stream) {
+  if (!p || !s || n_replicas < 1) return ISING_ERR_INVALID;
+  IRET(schedule_table(p, s));
+  const Table& table = p->sched.table;
   IRET(ensure_device(p));
   DeviceGuard dg(p->dg.device);
   PersistentConfig cfg;

@@ -9,6 +9,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "runtime.h"
 
@@ -277,7 +278,9 @@ uint64_t threshold_q32(double beta, int64_t k) {
 // Rows hold Tq - 1 for k = 1 .. len_t, where len_t is the last k with
 // Tq >= 1 (Tq falls with k); beta = 0 rows are marked accept-all.
 int build_table(const std::vector<double>& beta, int32_t kmax, Table& t) {
+  static std::atomic<uint64_t> next_id{1};
   t = Table();
+  t.id = next_id.fetch_add(1);
   t.S = (int)beta.size();
   t.kmax = kmax;
   t.off.assign((size_t)t.S, 0);

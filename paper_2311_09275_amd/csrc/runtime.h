@@ -51,6 +51,7 @@ struct DeviceArena {
   size_t cap = 0, used = 0;
   int device = -1;
   bool owned = true;  // false: memory lent by a pool, not freed here
+  uint64_t generation = 0;  // bumped whenever the memory behind base changes
   void adopt(char* p, size_t bytes, int dev) {
     release();
     base = p;
@@ -58,6 +59,7 @@ struct DeviceArena {
     used = 0;
     device = dev;
     owned = false;
+    ++generation;
   }
   DeviceArena() = default;
   DeviceArena(const DeviceArena&) = delete;
@@ -112,6 +114,7 @@ uint64_t threshold_q32(double beta, int64_t k);
 struct Table {
   int S = 0, kw = 0;
   int32_t kmax = 0;            // the problem's kmax the rows were built for
+  uint64_t id = 0;             // distinct for every table built
   std::vector<uint32_t> tq;    // Tq - 1
   std::vector<int32_t> off, len;
 };
@@ -147,6 +150,10 @@ struct RunBuffers {
   int32_t *tq_off = nullptr, *tq_len = nullptr;
   uint32_t* tqp = nullptr;     // FIELD: padded rows [S][kw + 2]
   std::vector<uint32_t> tqp_host;
+  // what the last table upload wrote, so that an unchanged table on an
+  // unchanged arena is not uploaded again
+  uint64_t up_table = 0, up_generation = 0;
+  const void* up_at = nullptr;
   int8_t* init_dev = nullptr;
   JobDev* job_dev = nullptr;
   int layout_best = 0, layout_final = 0, layout_field = -1;
@@ -223,4 +230,11 @@ struct ising_problem {
   std::vector<int8_t> init;  // [init_R][n] original order
   int32_t init_R = 0;
   bool trace = false;
+  // the thresholds of the last schedule annealed, reused while it repeats
+  struct {
+    int32_t kind = -1, n_sweeps = 0;
+    double beta0 = 0, beta1 = 0;
+    std::vector<double> betas;
+    ising::Table table;
+  } sched;
 };

@@ -210,3 +210,23 @@ def test_c3_full_size_sampled_replicas():
     0.05 -> 3.0, three replicas recomputed by the oracle."""
     compare(I.workload_c3(), 4000, 1024, 1003, kind=O.LINEAR, b0=0.05, b1=3.0,
             tuning=None, replicas=[0, 513, 1023], trace=False)
+
+
+def test_schedule_and_table_reuse_across_anneals():
+    """One problem annealed with alternating schedules and replica counts:
+    cached threshold tables and skipped uploads must never leave a stale
+    table behind (each result equals a fresh problem's)."""
+    inst = I.torus(20, 18, 21)
+    a = B.Schedule.make(B.GEOMETRIC, 300, 0.1, 4.0)
+    b = B.Schedule.make(B.LINEAR, 300, 0.2, 2.0)
+    c = B.Schedule.make(betas=np.linspace(0.3, 3.3, 300))
+    p = B.Problem.from_instance(inst)
+    for sched, R, tun in [(a, 24, None), (b, 24, None), (a, 24, None), (a, 40, None),
+                          (c, 40, None), (c, 40, B.Tuning(B.PATH_PLAIN, 1, 256, 0)), (a, 24, None)]:
+        p.anneal(sched, R, 5, tun)
+        got = B.ising_cut(p.handle, R)[2]
+        q = B.Problem.from_instance(inst)
+        q.anneal(sched, R, 5, B.Tuning(B.PATH_PLAIN, 1, 256, 0))
+        np.testing.assert_array_equal(got, B.ising_cut(q.handle, R)[2])
+        q.close()
+    p.close()
