@@ -39,13 +39,13 @@ MUL64_PEAK_PER_S = CUS * 16 * CLOCK_GHZ * 1e9
 PRODUCTS_PER_PHILOX = 20  # ten rounds, two products each
 
 
-def measured_traffic():
-    """HBM bytes per launch of the timed kernel from the committed counter
-    summary, or None when the kernel source has changed since they were
-    taken (the summary records the SHA-256 of kernels.hip)."""
+def _profile_figure(name, pattern, cast):
+    """A figure from a committed counter summary, or None when the kernel
+    source has changed since the counters were taken (each summary records
+    the SHA-256 of kernels.hip)."""
     import hashlib
     import re
-    summary = os.path.join(ROOT, "profiles", "k_field_torus100x80_r256_counters.md")
+    summary = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_2311_09275_amd", "csrc", "kernels.hip")
     try:
         text = open(summary).read()
@@ -53,9 +53,19 @@ def measured_traffic():
         have = hashlib.sha256(open(src, "rb").read()).hexdigest()
         if want != have:
             return None
-        return int(re.search(r"HBM bytes per launch: (\d+)", text).group(1))
+        return cast(re.search(pattern, text).group(1))
     except (OSError, AttributeError):
         return None
+
+
+def measured_traffic():
+    """HBM bytes per launch of the timed kernel (FETCH_SIZE + WRITE_SIZE)."""
+    return _profile_figure("k_field_torus100x80_r256_counters.md", r"HBM bytes per launch: (\d+)", int)
+
+
+def measured_valu_issue():
+    """Fraction of the SIMDs' cycles spent issuing VALU instructions."""
+    return _profile_figure("k_field_torus100x80_r256_valu.md", r"VALU issue fraction: [^=]*= ([0-9]+\.[0-9]+)", float)
 
 
 def cpu_model():
@@ -243,7 +253,7 @@ def main():
     achieved = products / (kern_ms / 1e3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": MUL64_PEAK_PER_S / 1e12,
                 "unit": "T int32x32->64 products/s", "frac": achieved / MUL64_PEAK_PER_S,
-                "traffic": measured_traffic()}
+                "traffic": measured_traffic(), "valu_issue_frac": measured_valu_issue()}
 
     line = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
