@@ -191,10 +191,10 @@ constexpr int kFormHbmDeg4 = 4;  // degree-4 blocks read from HBM (too large for
 // Extra LDS of a staged form: up to 12 bytes that align the entries to 16
 // bytes, then the CSR form's 2m entries, a gap word and the per-wave flip
 // lists (256 entries per wave of the largest block), or the degree-4 form's
-// 32 bytes of positions and 4 bytes of weight signs per group.
+// 32 bytes of positions and 8 bytes of {leader, weight signs} per group.
 static size_t adjacency_lds(const HostGraph& g, int form) {
   if (form == kFormHbmDeg4) return 0;
-  if (form == kFormDeg4) return 12 + 36 * (size_t)(g.n_pad / 4);
+  if (form == kFormDeg4) return 12 + 40 * (size_t)(g.n_pad / 4);
   return 12 + 4 * (size_t)g.m + 4 + (size_t)(1024 / 64) * 256 * 4;
 }
 static bool adjacency_fits(const HostGraph& g, int form) {

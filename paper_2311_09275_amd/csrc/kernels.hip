@@ -257,7 +257,8 @@ struct UnitLds {
   uint16_t* adj16;  // staged adjacency.  CSR form: [2m] entries
                     // (position << 1) | (w > 0).  Degree-4 form: [16 n_grp]
                     // positions, slot j of group g at 16 g + 4 j, then
-  uint32_t* gneg;   // [n_grp] bit 4 j + e set when entry e of slot j has w < 0
+  uint2* gln;       // degree-4 form: [n_grp] {leader id, negative-weight bits}:
+                    // bit 4 j + e set when entry e of slot j has w < 0
   uint32_t* flips;  // [BLOCK/64][256] per-wave lists of flipped vertices (CSR form)
 };
 
@@ -280,7 +281,7 @@ __device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int tq_wo
   // 128-bit reads (and four general entries one 64-bit read)
   const int used = words + tq_words + cls_words + 3 * n_grp;
   u.adj16 = reinterpret_cast<uint16_t*>(u.gdeg + n_grp + ((4 - (used & 3)) & 3));
-  u.gneg = nullptr;
+  u.gln = nullptr;
   u.flips = nullptr;
   return u;
 }
@@ -304,7 +305,7 @@ __device__ __forceinline__ void stage_adjacency_deg4(const JobDev& J, UnitLds& u
   const GLOBAL_AS int32_t* grp = gconst(J.grp);
   const GLOBAL_AS int32_t* gbase = gconst(J.gbase);
   const int n_grp = J.n_pad >> 2;
-  u.gneg = reinterpret_cast<uint32_t*>(u.adj16) + 8 * n_grp;
+  u.gln = reinterpret_cast<uint2*>(reinterpret_cast<uint32_t*>(u.adj16) + 8 * n_grp);
   for (int g = threadIdx.x; g < n_grp; g += blockDim.x) {
     const int cnt = (grp[g] >> kGroupCountShift) + 1;
     uint32_t pos[8], neg = 0;
@@ -325,7 +326,7 @@ __device__ __forceinline__ void stage_adjacency_deg4(const JobDev& J, UnitLds& u
     uint4* dst = reinterpret_cast<uint4*>(u.adj16) + 2 * g;
     dst[0] = make_uint4(pos[0], pos[1], pos[2], pos[3]);
     dst[1] = make_uint4(pos[4], pos[5], pos[6], pos[7]);
-    u.gneg[g] = neg;
+    u.gln[g] = make_uint2((uint32_t)(grp[g] & kGroupLeaderMask), neg);
   }
 }
 
@@ -480,6 +481,21 @@ __device__ __forceinline__ void push_deg4_pair(uint32_t base, uint32_t two, int 
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// The four pushes of slot j (unrolled callers pass a constant j).
+__device__ __forceinline__ void push_deg4_slot(uint32_t base, uint32_t lo, uint32_t hi, int q, int j) {
+  switch (j) {
+    case 0: push_deg4_pair<0>(base, lo, q); push_deg4_pair<2>(base, hi, q); break;
+    case 1: push_deg4_pair<4>(base, lo, q); push_deg4_pair<6>(base, hi, q); break;
+    case 2: push_deg4_pair<8>(base, lo, q); push_deg4_pair<10>(base, hi, q); break;
+    default: push_deg4_pair<12>(base, lo, q); push_deg4_pair<14>(base, hi, q); break;
+  }
+}
+
+// (mask & a) | (~mask & b)
+__device__ __forceinline__ uint32_t bit_insert(uint32_t mask, uint32_t a, uint32_t b) {
+  return (mask & a) | (~mask & b);
+}
+
 // k = s h for a packed word (h << 1) | b, s = 2 b - 1: with m = -b,
 // k = (h XNOR m) + m + 1.  Written out (four operations where the compiler
 // emits five), like the threshold index: k clamped to [0, kw] by one
@@ -629,18 +645,27 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
         nb1 = U.cls[2 * cn + 1];
       }
       if (live) {
-        for (int g = g0 + lt; g < g1; g += TPR) {
-          const int gw = U.gword[g];
+        for (int gi = g0 + lt; gi < g1; gi += TPR) {
+          // Addresses are formed from the group index in each iteration:
+          // most lanes run one iteration per pass, and a separate induction
+          // variable per array (the compiler's default) costs more.
+          int g = gi;
+          asm("" : "+v"(g));
           const int4 w4 = *reinterpret_cast<const int4*>(st + 4 * g);
           // degree-4 form: the group's entries are fetched with its state,
           // so their latency is covered by the Philox block
           uint4 a01 = make_uint4(0u, 0u, 0u, 0u), a23 = a01;
-          uint32_t neg = 0;
+          uint32_t neg = 0, leader;
           if (ADJ == kAdjLdsDeg4) {
+            const uint2 ln = U.gln[g];
+            leader = ln.x;
+            neg = ln.y;
             a01 = reinterpret_cast<const uint4*>(U.adj16)[2 * g];
             a23 = reinterpret_cast<const uint4*>(U.adj16)[2 * g + 1];
-            neg = U.gneg[g];
-          } else if (ADJ == kAdjHbmDeg4) {
+          } else {
+            leader = (uint32_t)(U.gword[g] & kGroupLeaderMask);
+          }
+          if (ADJ == kAdjHbmDeg4) {
             const GLOBAL_AS u32x4* a4 = gconst(reinterpret_cast<const u32x4*>(J.adj4)) + 2 * g;
             const u32x4 b01 = a4[0], b23 = a4[1];
             a01 = make_uint4(b01.x, b01.y, b01.z, b01.w);
@@ -666,7 +691,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           for (int j = 0; j < 4; ++j) thr[j] = row[clamp_row_index(k[j], kw)];
           // keep the reads ahead of the Philox arithmetic
           __builtin_amdgcn_sched_barrier(0);
-          const uint4 x = philox10(gw & kGroupLeaderMask, t, r, kTagSweep, k0, k1);
+          const uint4 x = philox10(leader, t, r, kTagSweep, k0, k1);
           bool acc[4];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
@@ -679,16 +704,20 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             // the spin bit under the accept mask: no per-slot selects.
             const uint32_t e[8] = {a01.x, a01.y, a01.z, a01.w, a23.x, a23.y, a23.z, a23.w};
             const uint32_t gaddr = st_base + 16u * (uint32_t)g;
+            // bit 4 j + e of q: entry e of slot j adds -4.  The new spin bit
+            // is the old one flipped, so q = neg XNOR (slot j's -(old bit)
+            // spread over nibble j), built once for the four slots.
+            const uint32_t ms = bit_insert(0x000Fu, (uint32_t)m[0],
+                                bit_insert(0x00F0u, (uint32_t)m[1],
+                                bit_insert(0x0F00u, (uint32_t)m[2], (uint32_t)m[3])));
+            const int q = (int)~(neg ^ ms);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               if (acc[j]) {
                 __hip_atomic_fetch_xor((lds_i32*)(uintptr_t)(gaddr + 4 * j), 1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 dk += k[j];
-                // new spin bit = old ^ 1, so q = neg ^ ~m
-                const int q = ~((int)(neg >> (4 * j)) ^ m[j]);
-                push_deg4_pair<0>(st_base, e[2 * j], q);
-                push_deg4_pair<2>(st_base, e[2 * j + 1], q);
+                push_deg4_slot(st_base, e[2 * j], e[2 * j + 1], q, j);
               }
             }
           } else {
