@@ -10,7 +10,7 @@
 // over end-of-sweep states (strict improvement).
 //
 // Random numbers: word j of Philox4x32-10 with key = seed and counter =
-// (leader, t, r, tag) serves the j-th vertex of a group -- four consecutive
+// (t, leader, r, tag) serves the j-th vertex of a group -- four consecutive
 // same-colour vertices.  One block call therefore feeds four attempts of one
 // replica, which lets a single replica be a unit of parallel work.
 //
@@ -40,10 +40,10 @@ constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
 // products; key advanced by the Weyl constants between rounds.  From the
-// third round on every word differs per lane, and each new word's two
+// fourth round on every word differs per lane, and each new word's two
 // XORs are one three-input bitwise operation (truth table 0x96); the first
-// two rounds keep plain XORs, which the compiler folds where counter words
-// are the same for the whole wave.
+// three rounds keep plain XORs, which the compiler folds where words are
+// the same for the whole wave.
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
@@ -54,8 +54,8 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
   for (int i = 0; i < 10; ++i) {
     const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
     const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-    const uint32_t n0 = i < 2 ? (uint32_t)(p1 >> 32) ^ c1 ^ k0 : xor3((uint32_t)(p1 >> 32), c1, k0);
-    const uint32_t n2 = i < 2 ? (uint32_t)(p0 >> 32) ^ c3 ^ k1 : xor3((uint32_t)(p0 >> 32), c3, k1);
+    const uint32_t n0 = i < 3 ? (uint32_t)(p1 >> 32) ^ c1 ^ k0 : xor3((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = i < 3 ? (uint32_t)(p0 >> 32) ^ c3 ^ k1 : xor3((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -64,6 +64,16 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     k1 += kPhiloxW1;
   }
   return make_uint4(c0, c1, c2, c3);
+}
+
+// The block of a four-vertex group: counter (sweep, leader id, replica,
+// tag), key (seed low, seed high); the group's j-th vertex uses word j.
+// Sweep, replica and tag are the same for a whole wave, so with the leader
+// in word 1 the first round's products and one product of each of the next
+// two rounds do not depend on the lane.
+__device__ __forceinline__ uint4 group_block(uint32_t leader, uint32_t t, uint32_t r,
+                                             uint32_t tag, uint32_t k0, uint32_t k1) {
+  return philox10(t, leader, r, tag, k0, k1);
 }
 
 // Pointers fetched from a descriptor are generic; re-qualifying them as
@@ -136,7 +146,7 @@ __global__ void k_plain_init(PlainDev P) {
     for (int j = 0; j < cnt; ++j)
       bits |= (P.init_spins[(int64_t)r * P.n_pad + 4 * g + j] > 0 ? 1u : 0u) << j;
   } else {
-    const uint4 x = philox10(gw & kGroupLeaderMask, 0, r, kTagInit, P.seed_lo, P.seed_hi);
+    const uint4 x = group_block(gw & kGroupLeaderMask, 0, r, kTagInit, P.seed_lo, P.seed_hi);
     bits = (x.x >> 31) | ((x.y >> 31) << 1) | ((x.z >> 31) << 2) | ((x.w >> 31) << 3);
   }
   for (int j = 0; j < 4; ++j)
@@ -191,7 +201,7 @@ __global__ void k_plain_sweep(PlainDev P, int t, int g0, int g1) {
     }
   }
   uint4 x = make_uint4(0, 0, 0, 0);
-  if (need) x = philox10(gw & kGroupLeaderMask, t, r, kTagSweep, P.seed_lo, P.seed_hi);
+  if (need) x = group_block(gw & kGroupLeaderMask, t, r, kTagSweep, P.seed_lo, P.seed_hi);
   int dE = 0, nacc = 0;
   for (int j = 0; j < cnt; ++j) {
     if (k[j] <= 0 || accept_pos(k[j], len, pick(x, j), row)) {
@@ -298,8 +308,9 @@ __device__ __forceinline__ void stage_adjacency(const JobDev& J, const UnitLds& 
   for (int i = threadIdx.x; i < n; i += blockDim.x) u.adj16[i] = (uint16_t)adjm[i];
 }
 
-// Degree-4 form: positions and negative-weight bits of the four entries of
-// each real slot; zeros for padding slots (never pushed: padding never flips).
+// Degree-4 form: LDS word indices (slot-major, see field_unit) and
+// negative-weight bits of the four entries of each real slot; zeros for
+// padding slots (never pushed: padding never flips).
 __device__ __forceinline__ void stage_adjacency_deg4(const JobDev& J, UnitLds& u) {
   const GLOBAL_AS uint32_t* adjm = gconst(J.adjm);
   const GLOBAL_AS int32_t* grp = gconst(J.grp);
@@ -318,7 +329,9 @@ __device__ __forceinline__ void stage_adjacency_deg4(const JobDev& J, UnitLds& u
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const uint32_t a = adjm[o + e];
-          pos[2 * j + (e >> 1)] |= (a >> 1) << (16 * (e & 1));
+          const uint32_t q = a >> 1;  // neighbour position
+          const uint32_t word = (q & 3u) * (uint32_t)n_grp + (q >> 2);
+          pos[2 * j + (e >> 1)] |= word << (16 * (e & 1));
           neg |= ((a & 1u) ^ 1u) << (4 * j + e);
         }
       }
@@ -525,6 +538,13 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   const bool live = r < J.R;
   const int n_pad = J.n_pad, n_grp = n_pad >> 2;
   int32_t* st = smem + rl * n_pad;
+  // Word of slot j of group g.  The degree-4 forms keep the state
+  // slot-major, so that per-slot accesses of consecutive groups (the spin
+  // flips, and the pushes, whose neighbours are consecutive groups of
+  // another class) hit consecutive LDS banks; the other forms keep a
+  // group's four words together.
+  constexpr bool SOA = ADJ == kAdjLdsDeg4 || ADJ == kAdjHbmDeg4;
+  auto widx = [&](int g, int j) { return SOA ? j * n_grp + g : 4 * g + j; };
   const int C = J.n_colours;
   const int RW = J.kw + 2;  // row words
   UnitLds U = unit_lds(reinterpret_cast<uint32_t*>(smem), G * n_pad, J.row_chunk * RW, 2 * C, n_grp);
@@ -549,7 +569,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           for (int j = 0; j < cnt; ++j)
             bits |= (J.init_spins[(int64_t)r * n_pad + 4 * g + j] > 0 ? 1u : 0u) << j;
         } else {
-          const uint4 x = philox10(gw & kGroupLeaderMask, 0, r, kTagInit, k0, k1);
+          const uint4 x = group_block(gw & kGroupLeaderMask, 0, r, kTagInit, k0, k1);
           bits = (x.x >> 31) | ((x.y >> 31) << 1) | ((x.z >> 31) << 2) | ((x.w >> 31) << 3);
         }
         w4.x = (int)(bits & 1u);
@@ -559,7 +579,14 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
       } else {
         w4 = *reinterpret_cast<const int4*>(J.save + (int64_t)r * n_pad + 4 * g);
       }
-      *reinterpret_cast<int4*>(st + 4 * g) = w4;
+      if (SOA) {
+        st[widx(g, 0)] = w4.x;
+        st[widx(g, 1)] = w4.y;
+        st[widx(g, 2)] = w4.z;
+        st[widx(g, 3)] = w4.w;
+      } else {
+        *reinterpret_cast<int4*>(st + 4 * g) = w4;
+      }
     }
   }
   const int CH = J.row_chunk;
@@ -573,8 +600,11 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
     stage_adjacency_deg4(J, U);
   }
   uint32_t* flist = ADJ == kAdjLds ? U.flips + (threadIdx.x >> 6) * 256 : nullptr;
-  // LDS byte address of this replica's words (degree-4 pushes)
+  // LDS byte address of this replica's words (degree-4 pushes), and of its
+  // four slot planes
   const uint32_t st_base = (uint32_t)(uintptr_t)(lds_i32*)st;
+  const uint32_t sb1 = st_base + 4u * (uint32_t)n_grp, sb2 = sb1 + 4u * (uint32_t)n_grp,
+                 sb3 = sb2 + 4u * (uint32_t)n_grp;
   __syncthreads();
 
   int E, best_cut, best_sweep;
@@ -594,10 +624,10 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
         int h = 0;
         for (int e = 0; e < d; ++e) {
           const i32x2 q = aw[a + e];
-          h -= q.y * ((st[q.x] & 1) ? 1 : -1);
+          h -= q.y * ((st[widx(q.x >> 2, q.x & 3)] & 1) ? 1 : -1);
         }
-        const int b = st[p] & 1;
-        st[p] = (h << 1) | b;
+        const int b = st[widx(g, j)] & 1;
+        st[widx(g, j)] = (h << 1) | b;
         part += b ? h : -h;
       }
     }
@@ -651,7 +681,15 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           // variable per array (the compiler's default) costs more.
           int g = gi;
           asm("" : "+v"(g));
-          const int4 w4 = *reinterpret_cast<const int4*>(st + 4 * g);
+          int4 w4;
+          if (SOA) {
+            w4.x = st[g];
+            w4.y = st[n_grp + g];
+            w4.z = st[2 * n_grp + g];
+            w4.w = st[3 * n_grp + g];
+          } else {
+            w4 = *reinterpret_cast<const int4*>(st + 4 * g);
+          }
           // degree-4 form: the group's entries are fetched with its state,
           // so their latency is covered by the Philox block
           uint4 a01 = make_uint4(0u, 0u, 0u, 0u), a23 = a01;
@@ -691,7 +729,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           for (int j = 0; j < 4; ++j) thr[j] = row[clamp_row_index(k[j], kw)];
           // keep the reads ahead of the Philox arithmetic
           __builtin_amdgcn_sched_barrier(0);
-          const uint4 x = philox10(leader, t, r, kTagSweep, k0, k1);
+          const uint4 x = group_block(leader, t, r, kTagSweep, k0, k1);
           bool acc[4];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
@@ -703,7 +741,8 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             // (neighbours are in other classes), so a flip is an LDS XOR of
             // the spin bit under the accept mask: no per-slot selects.
             const uint32_t e[8] = {a01.x, a01.y, a01.z, a01.w, a23.x, a23.y, a23.z, a23.w};
-            const uint32_t gaddr = st_base + 16u * (uint32_t)g;
+            const uint32_t g4 = 4u * (uint32_t)g;
+            const uint32_t gaddr[4] = {st_base + g4, sb1 + g4, sb2 + g4, sb3 + g4};
             // bit 4 j + e of q: entry e of slot j adds -4.  The new spin bit
             // is the old one flipped, so q = neg XNOR (slot j's -(old bit)
             // spread over nibble j), built once for the four slots.
@@ -714,7 +753,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               if (acc[j]) {
-                __hip_atomic_fetch_xor((lds_i32*)(uintptr_t)(gaddr + 4 * j), 1, __ATOMIC_RELAXED,
+                __hip_atomic_fetch_xor((lds_i32*)(uintptr_t)gaddr[j], 1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 dk += k[j];
                 push_deg4_slot(st_base, e[2 * j], e[2 * j + 1], q, j);
@@ -758,7 +797,12 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   // ---- state out
   if (live) {
     for (int g = lt; g < n_grp; g += TPR) {
-      const int4 w4 = *reinterpret_cast<const int4*>(st + 4 * g);
+      int4 w4;
+      if (SOA) {
+        w4 = make_int4(st[widx(g, 0)], st[widx(g, 1)], st[widx(g, 2)], st[widx(g, 3)]);
+      } else {
+        w4 = *reinterpret_cast<const int4*>(st + 4 * g);
+      }
       if (snap) {
         const uint32_t bits = (w4.x & 1) | ((w4.y & 1) << 1) | ((w4.z & 1) << 2) | ((w4.w & 1) << 3);
         *reinterpret_cast<GLOBAL_AS uint32_t*>(best + 4 * g) = spins_to_bytes(bits);
@@ -932,7 +976,7 @@ __device__ void msc_unit(const JobDev& J, const int block, uint32_t* smem, MscSh
         } else {
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
-            const uint4 x = philox10(gw & kGroupLeaderMask, 0, rb + i, kTagInit, k0, k1);
+            const uint4 x = group_block(gw & kGroupLeaderMask, 0, rb + i, kTagInit, k0, k1);
             b[0] |= (x.x >> 31) << (8 * o + i);
             b[1] |= (x.y >> 31) << (8 * o + i);
             b[2] |= (x.z >> 31) << (8 * o + i);
@@ -1030,7 +1074,7 @@ __device__ void msc_unit(const JobDev& J, const int block, uint32_t* smem, MscSh
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
             uint4 x = make_uint4(0, 0, 0, 0);
-            if (draw_needed) x = philox10(gw & kGroupLeaderMask, t, rb + i, kTagSweep, k0, k1);
+            if (draw_needed) x = group_block(gw & kGroupLeaderMask, t, rb + i, kTagSweep, k0, k1);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               if (j < cnt) {

@@ -211,8 +211,11 @@ int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, cons
         if (g.orig[4 * q + (size_t)j] < 0) continue;  // padding slot: never pushed
         const int32_t o = g.row[4 * q + (size_t)j];
         for (int e = 0; e < 4; ++e) {
+          // the FIELD kernel keeps the state slot-major in these forms:
+          // position p is word (p mod 4) * n_grp + p / 4
           const uint32_t pos = (uint32_t)g.adj[(size_t)(o + e)];
-          g.adj4[8 * q + (size_t)(2 * j + e / 2)] |= pos << (16 * (e & 1));
+          const uint32_t word = (pos & 3u) * (uint32_t)ng + (pos >> 2);
+          g.adj4[8 * q + (size_t)(2 * j + e / 2)] |= word << (16 * (e & 1));
           if (g.wgt[(size_t)(o + e)] < 0) g.neg4[q] |= 1u << (4 * j + e);
         }
       }

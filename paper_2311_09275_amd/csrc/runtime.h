@@ -99,8 +99,9 @@ struct HostGraph {
   std::vector<int32_t> aw;             // [2m][2] {position, w}
   std::vector<int32_t> gbase;          // [n_pad/4] = row[4g]
   std::vector<uint32_t> gdeg;          // [n_pad/4] packed slot degrees
-  // degree-4 graphs with fewer than 2^16 positions: per group eight words
-  // of 16-bit neighbour positions (slot j's four at 16-bit index 4j..4j+3)
+  // degree-4 graphs with at most 2^16 positions: per group eight words of
+  // 16-bit neighbour word indices in the slot-major state layout (position
+  // p -> (p mod 4) * n_pad/4 + p/4; slot j's four at 16-bit index 4j..4j+3)
   // and a word whose bit 4j+e is set when entry e of slot j has w < 0
   std::vector<uint32_t> adj4, neg4;
 };
