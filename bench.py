@@ -30,13 +30,19 @@ sys.path.insert(0, ROOT)
 METRIC = "spin-flip attempts/s + time-to-target cut, batched vs plain, 1 MI355X"
 UNIT = "spin-flip attempts/s"
 
-# MI355X published figures used as roofline peaks.
+# MI355X figures used as roofline peaks.
 HBM_PEAK_GBS = 8000.0
 CUS, CLOCK_GHZ = 256, 2.4
-# 32x32->64-bit integer products (v_mad_u64_u32) issue at a quarter of the
-# full VALU rate: 64 lanes / 4 per CU per clock.
-MUL64_PEAK_PER_S = CUS * 16 * CLOCK_GHZ * 1e9
-PRODUCTS_PER_PHILOX = 20  # ten rounds, two products each
+# Integer VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s.
+# On gfx950 the 32x32->64-bit products of the RNG issue at (nearly) this
+# full rate too; ising_valu_rates measures the rates live.
+VALU_PEAK_PER_S = CUS * 64 * CLOCK_GHZ * 1e9
+# Algorithmic 32-bit integer operations: a Philox4x32-10 block is ten
+# rounds of two products and four XORs; an attempt's accept test is k = s h,
+# the row index and one compare; an accepted flip updates the spin, the
+# energy and one field per neighbour.
+OPS_PER_PHILOX = 60
+OPS_PER_TEST = 3
 
 
 def _profile_figure(name, pattern, cast):
@@ -218,7 +224,7 @@ def main():
 
     # ------------------------------------------------------------ CPU oracle
     cpu = None
-    draws_per_attempt = None
+    draws_per_attempt = accepts_per_attempt = None
     if not args.no_cpu:
         from oracle import oracle as O
         O.build(force=False)
@@ -238,6 +244,7 @@ def main():
                "sample": f"replicas 0..{sample - 1} of 256, all {S} sweeps, {threads} threads, {cpu_s:.1f} s",
                "one_thread_value": inst.n * 2 * S / one_s, "cpu_model": cpu_model()}
         draws_per_attempt = float(o.draws.sum()) / (inst.n * sample * S)
+        accepts_per_attempt = float(o.accepts.sum()) / (inst.n * sample * S)
         if ttt_rows is not None:
             # the oracle's wall time for all R replicas at its measured rate
             oracle_wall = attempts / cpu["value"]
@@ -245,15 +252,20 @@ def main():
                 row["ttt_oracle_s"] = ttt.replica_ttt(per_rep, row["target"], oracle_wall, S)["ttt_s"]
 
     # ------------------------------------------------------------ roofline
-    # Algorithmic ALU work: the Philox blocks the method needs (counted by
-    # the oracle on its sample), 20 products each, per launch.
+    # Algorithmic integer work per launch, from the exact counts of the
+    # oracle's sample (Philox blocks drawn, moves accepted).
     if draws_per_attempt is None:
-        draws_per_attempt = 0.24
-    products = draws_per_attempt * attempts * PRODUCTS_PER_PHILOX
-    achieved = products / (kern_ms / 1e3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": MUL64_PEAK_PER_S / 1e12,
-                "unit": "T int32x32->64 products/s", "frac": achieved / MUL64_PEAK_PER_S,
-                "traffic": measured_traffic(), "valu_issue_frac": measured_valu_issue()}
+        draws_per_attempt, accepts_per_attempt = 0.24, 0.36
+    mean_degree = 2.0 * inst.m / inst.n
+    ops_per_attempt = (OPS_PER_PHILOX * draws_per_attempt + OPS_PER_TEST +
+                       accepts_per_attempt * (2.0 + mean_degree))
+    achieved = ops_per_attempt * attempts / (kern_ms / 1e3)
+    rates = B.ising_valu_rates()
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_PER_S / 1e12,
+                "unit": "T int32 ops/s", "frac": achieved / VALU_PEAK_PER_S,
+                "traffic": measured_traffic(), "valu_issue_frac": measured_valu_issue(),
+                "ops_per_attempt": ops_per_attempt,
+                "measured_lane_ops_per_s": {k: v for k, v in rates.items()}}
 
     line = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,

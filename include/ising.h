@@ -18,8 +18,9 @@
  * the updates of one class are independent), each with
  *     k = s_i h_i,  h_i = -sum_j w_ij s_j   (flipping s_i changes E by 2k)
  *     accept iff k <= 0 or u < Tq(beta_t, k),  Tq = floor(2^32 exp(-2 k beta_t))
- * where u is word r of Philox4x32-10(key = seed, counter = (leader, t, r,
- * 0)) -- see ising_create for the leader/word assignment.  The best cut of a
+ * where u is word j of Philox4x32-10(key = seed, counter = (t, leader, r,
+ * 0)), j being the vertex's rank in its group -- see ising_create for the
+ * leader/word assignment.  The best cut of a
  * replica is taken over its initial state and its end-of-sweep states
  * (strict improvement, earliest sweep wins).  Every step is integer
  * arithmetic on the device, so results are bit-identical across kernel
@@ -302,6 +303,17 @@ int ising_server_footprint(const ising_problem* p, const ising_schedule* s,
 int ising_server_stats(ising_server* srv, int64_t* steps, int64_t* finished,
                        int32_t* peak_resident);
 int ising_server_destroy(ising_server* srv);
+
+/*
+ * Measurement helper for the roofline, not part of the method: issue rates
+ * of the integer VALU instructions the anneal kernels are built from, on
+ * the current device, in lane-operations per second, from independent
+ * register-only chains at eight waves per SIMD.  rates[0..3] =
+ * v_mad_u64_u32, v_mul_lo_u32, v_mul_hi_u32, v_xor_b32.  Synchronous; takes
+ * a small temporary device buffer.  Errors: ISING_ERR_INVALID (rates NULL),
+ * ISING_ERR_DEVICE.
+ */
+int ising_valu_rates(double* rates);
 
 #ifdef __cplusplus
 }

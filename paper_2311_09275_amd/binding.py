@@ -111,6 +111,7 @@ _sig = {
     "ising_server_footprint": ([P, C.POINTER(Schedule), C.c_int32, C.POINTER(C.c_uint64)], C.c_int),
     "ising_server_stats": ([P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)], C.c_int),
     "ising_server_destroy": ([P], C.c_int),
+    "ising_valu_rates": ([P], C.c_int),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_L, _name)
@@ -266,6 +267,17 @@ def ising_last_batch_ms() -> float:
     out = C.c_double()
     _check(_L.ising_last_batch_ms(C.byref(out)), "ising_last_batch_ms")
     return out.value
+
+
+VALU_RATE_NAMES = ("v_mad_u64_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_xor_b32")
+
+
+def ising_valu_rates() -> dict:
+    """Measured lane-operations per second of the integer VALU instructions
+    the kernels use (a roofline measurement helper)."""
+    out = np.zeros(4, np.float64)
+    _check(_L.ising_valu_rates(_ptr(out)), "ising_valu_rates")
+    return dict(zip(VALU_RATE_NAMES, (float(x) for x in out)))
 
 
 def ising_autotune(handles, sched: Schedule, n_replicas, prefix_sweeps=0, stream=None) -> Tuning:
