@@ -93,8 +93,7 @@ int upload_graph(const HostGraph& g, DevGraph& d) {
                  3 * DeviceArena::span(sizeof(int32_t) * g.grp.size()) +
                  DeviceArena::span(sizeof(int32_t) * g.cls.size()) +
                  DeviceArena::span(sizeof(int32_t) * g.n) +
-                 DeviceArena::span(sizeof(uint32_t) * g.adj4.size()) +
-                 DeviceArena::span(sizeof(uint32_t) * g.neg4.size());
+                 DeviceArena::span(sizeof(uint32_t) * g.adj4.size());
   IRET(d.arena.reserve(bytes));
   d.device = d.arena.device;
   d.row = d.arena.take<int32_t>(g.n_pad + 1);
@@ -108,11 +107,8 @@ int upload_graph(const HostGraph& g, DevGraph& d) {
   d.cls = d.arena.take<int32_t>(g.cls.size());
   d.pos = d.arena.take<int32_t>(g.n);
   d.adj4 = g.adj4.empty() ? nullptr : d.arena.take<uint32_t>(g.adj4.size());
-  d.neg4 = g.neg4.empty() ? nullptr : d.arena.take<uint32_t>(g.neg4.size());
-  if (d.adj4) {
+  if (d.adj4)
     ICHK(hipMemcpy(d.adj4, g.adj4.data(), sizeof(uint32_t) * g.adj4.size(), hipMemcpyHostToDevice));
-    ICHK(hipMemcpy(d.neg4, g.neg4.data(), sizeof(uint32_t) * g.neg4.size(), hipMemcpyHostToDevice));
-  }
   ICHK(hipMemcpy(d.row, g.row.data(), sizeof(int32_t) * g.row.size(), hipMemcpyHostToDevice));
   if (e2) {
     ICHK(hipMemcpy(d.adj, g.adj.data(), sizeof(int32_t) * e2, hipMemcpyHostToDevice));
@@ -191,10 +187,10 @@ constexpr int kFormHbmDeg4 = 4;  // degree-4 blocks read from HBM (too large for
 // Extra LDS of a staged form: up to 12 bytes that align the entries to 16
 // bytes, then the CSR form's 2m entries, a gap word and the per-wave flip
 // lists (256 entries per wave of the largest block), or the degree-4 form's
-// 32 bytes of positions and 8 bytes of {leader, weight signs} per group.
+// 48-byte group blocks.
 static size_t adjacency_lds(const HostGraph& g, int form) {
   if (form == kFormHbmDeg4) return 0;
-  if (form == kFormDeg4) return 12 + 40 * (size_t)(g.n_pad / 4);
+  if (form == kFormDeg4) return 12 + 4 * kDeg4BlockWords * (size_t)(g.n_pad / 4);
   return 12 + 4 * (size_t)g.m + 4 + (size_t)(1024 / 64) * 256 * 4;
 }
 static bool adjacency_fits(const HostGraph& g, int form) {
@@ -442,7 +438,6 @@ JobDev make_job(const HostGraph& g, const DevGraph& d, const RunBuffers& b, int 
   J.wgt = d.wgt;
   J.adjm = d.adjm;
   J.adj4 = reinterpret_cast<const uint4*>(d.adj4);
-  J.neg4 = d.neg4;
   J.aw = d.aw;
   J.grp = d.grp;
   J.gbase = d.gbase;

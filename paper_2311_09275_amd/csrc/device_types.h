@@ -21,6 +21,15 @@ constexpr uint32_t kTagInit = 1;
 // Threshold row length meaning "beta_t == 0: accept every move".
 constexpr int32_t kAcceptAll = -1;
 
+// Degree-4 group block, 12 words (48 bytes): words 0..7 hold the 16-bit LDS
+// word indices of the 16 neighbour entries (slot j's four at 16-bit index
+// 4j..4j+3), word 8 the leader id, words 9 and 10 one 4-bit field per entry
+// (entry e of slot j in word 9 + j/2, nibble 4 (j mod 2) + e): 0xC, with bit
+// 3 cleared when the entry's weight is negative.  XOR-ed with the slot's old
+// spin bit in bit 3, the nibble read as a signed 4-bit number is the push
+// -4 w s_new: 0100b = +4, 1100b = -4.
+constexpr int kDeg4BlockWords = 12;
+
 // FIELD path: packed word of a padding slot.  Its k = s h = 2^30 - 1 is
 // above every row's acceptable length (k never exceeds the problem's
 // kmax < 2^29), so padding is never flipped.
@@ -46,8 +55,7 @@ struct JobDev {
   const int32_t* wgt;    // [2m] MaxCut weight w (coupling J = -w)
   const uint32_t* adjm;  // [2m] (position << 1) | (w > 0), unit weights only
   const int2* aw;        // [2m] {neighbour position, w}
-  const uint4* adj4;     // degree-4 graphs: [n_pad/4][2] 16-bit neighbour positions
-  const uint32_t* neg4;  // degree-4 graphs: [n_pad/4] negative-weight bits (4 j + e)
+  const uint4* adj4;     // degree-4 graphs: [n_pad/4][3] group blocks (kDeg4Block*)
   const int32_t* grp;    // [n_pad/4] group words
   const int32_t* gbase;  // [n_pad/4] first adjacency entry of the group
   const uint32_t* gdeg;  // [n_pad/4] degrees of the group's four slots, 8 bits each

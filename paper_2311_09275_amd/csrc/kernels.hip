@@ -267,8 +267,8 @@ struct UnitLds {
   uint16_t* adj16;  // staged adjacency.  CSR form: [2m] entries
                     // (position << 1) | (w > 0).  Degree-4 form: [16 n_grp]
                     // positions, slot j of group g at 16 g + 4 j, then
-  uint2* gln;       // degree-4 form: [n_grp] {leader id, negative-weight bits}:
-                    // bit 4 j + e set when entry e of slot j has w < 0
+                    // (degree-4 form: [n_grp] 48-byte group blocks, see
+                    // kDeg4BlockWords)
   uint32_t* flips;  // [BLOCK/64][256] per-wave lists of flipped vertices (CSR form)
 };
 
@@ -291,7 +291,6 @@ __device__ __forceinline__ UnitLds unit_lds(uint32_t* smem, int words, int tq_wo
   // 128-bit reads (and four general entries one 64-bit read)
   const int used = words + tq_words + cls_words + 3 * n_grp;
   u.adj16 = reinterpret_cast<uint16_t*>(u.gdeg + n_grp + ((4 - (used & 3)) & 3));
-  u.gln = nullptr;
   u.flips = nullptr;
   return u;
 }
@@ -308,18 +307,17 @@ __device__ __forceinline__ void stage_adjacency(const JobDev& J, const UnitLds& 
   for (int i = threadIdx.x; i < n; i += blockDim.x) u.adj16[i] = (uint16_t)adjm[i];
 }
 
-// Degree-4 form: LDS word indices (slot-major, see field_unit) and
-// negative-weight bits of the four entries of each real slot; zeros for
-// padding slots (never pushed: padding never flips).
+// Degree-4 form: the 48-byte group blocks (kDeg4BlockWords) of the unit,
+// with slot-major LDS word indices (see field_unit); padding slots get
+// zero entries (never pushed: padding never flips).
 __device__ __forceinline__ void stage_adjacency_deg4(const JobDev& J, UnitLds& u) {
   const GLOBAL_AS uint32_t* adjm = gconst(J.adjm);
   const GLOBAL_AS int32_t* grp = gconst(J.grp);
   const GLOBAL_AS int32_t* gbase = gconst(J.gbase);
   const int n_grp = J.n_pad >> 2;
-  u.gln = reinterpret_cast<uint2*>(reinterpret_cast<uint32_t*>(u.adj16) + 8 * n_grp);
   for (int g = threadIdx.x; g < n_grp; g += blockDim.x) {
     const int cnt = (grp[g] >> kGroupCountShift) + 1;
-    uint32_t pos[8], neg = 0;
+    uint32_t pos[8], nib[2] = {0xCCCCCCCCu, 0xCCCCCCCCu};
 #pragma unroll
     for (int i = 0; i < 8; ++i) pos[i] = 0;
 #pragma unroll
@@ -332,14 +330,14 @@ __device__ __forceinline__ void stage_adjacency_deg4(const JobDev& J, UnitLds& u
           const uint32_t q = a >> 1;  // neighbour position
           const uint32_t word = (q & 3u) * (uint32_t)n_grp + (q >> 2);
           pos[2 * j + (e >> 1)] |= word << (16 * (e & 1));
-          neg |= ((a & 1u) ^ 1u) << (4 * j + e);
+          if (!(a & 1u)) nib[j >> 1] ^= 8u << (4 * (4 * (j & 1) + e));  // w < 0
         }
       }
     }
-    uint4* dst = reinterpret_cast<uint4*>(u.adj16) + 2 * g;
+    uint4* dst = reinterpret_cast<uint4*>(u.adj16) + 3 * g;
     dst[0] = make_uint4(pos[0], pos[1], pos[2], pos[3]);
     dst[1] = make_uint4(pos[4], pos[5], pos[6], pos[7]);
-    u.gln[g] = make_uint2((uint32_t)(grp[g] & kGroupLeaderMask), neg);
+    dst[2] = make_uint4((uint32_t)(grp[g] & kGroupLeaderMask), nib[0], nib[1], 0u);
   }
 }
 
@@ -478,35 +476,35 @@ __device__ __forceinline__ uint32_t lds_byte_addr(uint32_t two, uint32_t base) {
   return a;
 }
 
-template <int E>
-__device__ __forceinline__ int plus_minus4(int q) {
-  int m, v;
-  asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(m) : "v"(q), "i"(E));
-  asm("v_lshl_or_b32 %0, %1, 3, 4" : "=v"(v) : "v"(m));
+// Push value of the entry whose 4-bit field starts at bit OFF: the field
+// read as a signed number (one sign-extending bit-field extract).
+template <int OFF>
+__device__ __forceinline__ int nibble_value(uint32_t r) {
+  int v;
+  asm("v_bfe_i32 %0, %1, %2, 4" : "=v"(v) : "v"(r), "i"(OFF));
   return v;
 }
 
-template <int E>
-__device__ __forceinline__ void push_deg4_pair(uint32_t base, uint32_t two, int q) {
-  __hip_atomic_fetch_add((lds_i32*)(uintptr_t)lds_byte_addr<0>(two, base), plus_minus4<E>(q),
+// Pushes of the two entries packed in `two`; K = nibble of the first.
+template <int K>
+__device__ __forceinline__ void push_deg4_pair(uint32_t base, uint32_t two, uint32_t r) {
+  __hip_atomic_fetch_add((lds_i32*)(uintptr_t)lds_byte_addr<0>(two, base), nibble_value<4 * K>(r),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  __hip_atomic_fetch_add((lds_i32*)(uintptr_t)lds_byte_addr<1>(two, base), plus_minus4<E + 1>(q),
+  __hip_atomic_fetch_add((lds_i32*)(uintptr_t)lds_byte_addr<1>(two, base), nibble_value<4 * K + 4>(r),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// The four pushes of slot j (unrolled callers pass a constant j).
-__device__ __forceinline__ void push_deg4_slot(uint32_t base, uint32_t lo, uint32_t hi, int q, int j) {
-  switch (j) {
-    case 0: push_deg4_pair<0>(base, lo, q); push_deg4_pair<2>(base, hi, q); break;
-    case 1: push_deg4_pair<4>(base, lo, q); push_deg4_pair<6>(base, hi, q); break;
-    case 2: push_deg4_pair<8>(base, lo, q); push_deg4_pair<10>(base, hi, q); break;
-    default: push_deg4_pair<12>(base, lo, q); push_deg4_pair<14>(base, hi, q); break;
+// The four pushes of slot j (unrolled callers pass a constant j); r holds
+// the nibbles of slots 2 (j/2) and 2 (j/2) + 1.
+__device__ __forceinline__ void push_deg4_slot(uint32_t base, uint32_t lo, uint32_t hi, uint32_t r,
+                                               int j) {
+  if (j & 1) {
+    push_deg4_pair<4>(base, lo, r);
+    push_deg4_pair<6>(base, hi, r);
+  } else {
+    push_deg4_pair<0>(base, lo, r);
+    push_deg4_pair<2>(base, hi, r);
   }
-}
-
-// (mask & a) | (~mask & b)
-__device__ __forceinline__ uint32_t bit_insert(uint32_t mask, uint32_t a, uint32_t b) {
-  return (mask & a) | (~mask & b);
 }
 
 // k = s h for a packed word (h << 1) | b, s = 2 b - 1: with m = -b,
@@ -692,24 +690,22 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           }
           // degree-4 form: the group's entries are fetched with its state,
           // so their latency is covered by the Philox block
-          uint4 a01 = make_uint4(0u, 0u, 0u, 0u), a23 = a01;
-          uint32_t neg = 0, leader;
+          uint4 a01 = make_uint4(0u, 0u, 0u, 0u), a23 = a01, lnb = a01;
           if (ADJ == kAdjLdsDeg4) {
-            const uint2 ln = U.gln[g];
-            leader = ln.x;
-            neg = ln.y;
-            a01 = reinterpret_cast<const uint4*>(U.adj16)[2 * g];
-            a23 = reinterpret_cast<const uint4*>(U.adj16)[2 * g + 1];
+            const uint4* blk = reinterpret_cast<const uint4*>(U.adj16) + 3 * g;
+            a01 = blk[0];
+            a23 = blk[1];
+            lnb = blk[2];
+          } else if (ADJ == kAdjHbmDeg4) {
+            const GLOBAL_AS u32x4* blk = gconst(reinterpret_cast<const u32x4*>(J.adj4)) + 3 * g;
+            const u32x4 b0 = blk[0], b1 = blk[1], b2 = blk[2];
+            a01 = make_uint4(b0.x, b0.y, b0.z, b0.w);
+            a23 = make_uint4(b1.x, b1.y, b1.z, b1.w);
+            lnb = make_uint4(b2.x, b2.y, b2.z, b2.w);
           } else {
-            leader = (uint32_t)(U.gword[g] & kGroupLeaderMask);
+            lnb.x = (uint32_t)(U.gword[g] & kGroupLeaderMask);
           }
-          if (ADJ == kAdjHbmDeg4) {
-            const GLOBAL_AS u32x4* a4 = gconst(reinterpret_cast<const u32x4*>(J.adj4)) + 2 * g;
-            const u32x4 b01 = a4[0], b23 = a4[1];
-            a01 = make_uint4(b01.x, b01.y, b01.z, b01.w);
-            a23 = make_uint4(b23.x, b23.y, b23.z, b23.w);
-            neg = gconst(J.neg4)[g];
-          }
+          const uint32_t leader = lnb.x;
           int w[4] = {w4.x, w4.y, w4.z, w4.w};
           if (snap) {
             const uint32_t bits = (w[0] & 1) | ((w[1] & 1) << 1) | ((w[2] & 1) << 2) | ((w[3] & 1) << 3);
@@ -743,20 +739,17 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             const uint32_t e[8] = {a01.x, a01.y, a01.z, a01.w, a23.x, a23.y, a23.z, a23.w};
             const uint32_t g4 = 4u * (uint32_t)g;
             const uint32_t gaddr[4] = {st_base + g4, sb1 + g4, sb2 + g4, sb3 + g4};
-            // bit 4 j + e of q: entry e of slot j adds -4.  The new spin bit
-            // is the old one flipped, so q = neg XNOR (slot j's -(old bit)
-            // spread over nibble j), built once for the four slots.
-            const uint32_t ms = bit_insert(0x000Fu, (uint32_t)m[0],
-                                bit_insert(0x00F0u, (uint32_t)m[1],
-                                bit_insert(0x0F00u, (uint32_t)m[2], (uint32_t)m[3])));
-            const int q = (int)~(neg ^ ms);
+            // push fields: the block's nibbles with each slot's old spin
+            // bit (m = -bit) XOR-ed into bit 3 of its entries' nibbles
+            const uint32_t r01 = lnb.y ^ ((uint32_t)m[0] & 0x00008888u) ^ ((uint32_t)m[1] & 0x88880000u);
+            const uint32_t r23 = lnb.z ^ ((uint32_t)m[2] & 0x00008888u) ^ ((uint32_t)m[3] & 0x88880000u);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               if (acc[j]) {
                 __hip_atomic_fetch_xor((lds_i32*)(uintptr_t)gaddr[j], 1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 dk += k[j];
-                push_deg4_slot(st_base, e[2 * j], e[2 * j + 1], q, j);
+                push_deg4_slot(st_base, e[2 * j], e[2 * j + 1], j < 2 ? r01 : r23, j);
               }
             }
           } else {

@@ -204,9 +204,11 @@ int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, cons
   for (int32_t i = 0; i < n && g.deg4; ++i) g.deg4 = deg[(size_t)i + 1] - deg[(size_t)i] == 4;
   if (g.deg4 && g.unit && g.n_pad <= (1 << 16)) {
     const size_t ng = (size_t)g.n_pad / 4;
-    g.adj4.assign(8 * ng, 0u);
-    g.neg4.assign(ng, 0u);
-    for (size_t q = 0; q < ng; ++q)
+    g.adj4.assign((size_t)kDeg4BlockWords * ng, 0u);
+    for (size_t q = 0; q < ng; ++q) {
+      uint32_t* blk = g.adj4.data() + (size_t)kDeg4BlockWords * q;
+      blk[8] = (uint32_t)(g.grp[q] & kGroupLeaderMask);
+      blk[9] = blk[10] = 0xCCCCCCCCu;
       for (int j = 0; j < 4; ++j) {
         if (g.orig[4 * q + (size_t)j] < 0) continue;  // padding slot: never pushed
         const int32_t o = g.row[4 * q + (size_t)j];
@@ -215,10 +217,11 @@ int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, cons
           // position p is word (p mod 4) * n_grp + p / 4
           const uint32_t pos = (uint32_t)g.adj[(size_t)(o + e)];
           const uint32_t word = (pos & 3u) * (uint32_t)ng + (pos >> 2);
-          g.adj4[8 * q + (size_t)(2 * j + e / 2)] |= word << (16 * (e & 1));
-          if (g.wgt[(size_t)(o + e)] < 0) g.neg4[q] |= 1u << (4 * j + e);
+          blk[2 * j + e / 2] |= word << (16 * (e & 1));
+          if (g.wgt[(size_t)(o + e)] < 0) blk[9 + j / 2] ^= 8u << (4 * (4 * (j & 1) + e));
         }
       }
+    }
   }
   return ISING_OK;
 }

@@ -99,11 +99,11 @@ struct HostGraph {
   std::vector<int32_t> aw;             // [2m][2] {position, w}
   std::vector<int32_t> gbase;          // [n_pad/4] = row[4g]
   std::vector<uint32_t> gdeg;          // [n_pad/4] packed slot degrees
-  // degree-4 graphs with at most 2^16 positions: per group eight words of
-  // 16-bit neighbour word indices in the slot-major state layout (position
-  // p -> (p mod 4) * n_pad/4 + p/4; slot j's four at 16-bit index 4j..4j+3)
-  // and a word whose bit 4j+e is set when entry e of slot j has w < 0
-  std::vector<uint32_t> adj4, neg4;
+  // degree-4 graphs with at most 2^16 positions: the 48-byte group blocks
+  // of the FIELD kernel (kDeg4BlockWords), neighbour entries as 16-bit word
+  // indices of the slot-major state layout (position p -> (p mod 4) *
+  // n_pad/4 + p/4)
+  std::vector<uint32_t> adj4;
 };
 
 int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, const int32_t* w,
@@ -129,7 +129,7 @@ struct DevGraph {
   int32_t *row = nullptr, *adj = nullptr, *wgt = nullptr, *grp = nullptr, *cls = nullptr,
           *pos = nullptr, *gbase = nullptr;
   uint32_t *adjm = nullptr, *gdeg = nullptr;
-  uint32_t *adj4 = nullptr, *neg4 = nullptr;
+  uint32_t* adj4 = nullptr;
   int2* aw = nullptr;
 };
 int upload_graph(const HostGraph& g, DevGraph& d);
