@@ -291,10 +291,10 @@ static int graph_build(const or_graph_in* in, or_graph* G) {
 }
 
 /* u32 random number for (vertex, sweep, replica, purpose): word rank(v) of
- * Philox4x32-10 with key = seed and counter = (leader(v), t, r, tag). */
+ * Philox4x32-10 with key = seed and counter = (t, leader(v), r, tag). */
 static uint32_t draw(const or_graph* G, uint64_t seed, int32_t v, uint32_t t,
                      uint32_t r, uint32_t tag) {
-  uint32_t ctr[4] = {(uint32_t)G->leader[v], t, r, tag};
+  uint32_t ctr[4] = {t, (uint32_t)G->leader[v], r, tag};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t out[4];
   oracle_philox4x32_10(ctr, key, out);
