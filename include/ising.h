@@ -155,7 +155,7 @@ enum {
  *                        from HBM, 3 = stage it in CSR order even when the
  *                        degree-4 form applies, 4 = read the degree-4 form
  *                        from HBM (unit weights, every vertex of degree 4,
- *                        at most 2^16 vertices).  With 0 a graph whose
+ *                        state of at most 2^16 words).  With 0 a graph whose
  *                        degree-4 form does not fit LDS reads it from HBM.
  */
 typedef struct {

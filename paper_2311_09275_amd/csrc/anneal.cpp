@@ -152,7 +152,7 @@ static int row_chunk(const Table& t) {
 
 static size_t persistent_lds(const HostGraph& g, const Table& t, const PersistentConfig& c) {
   const size_t rows = (size_t)row_chunk(t) * (size_t)(std::max(t.kw, 1) + 2);
-  return sizeof(int32_t) * ((size_t)c.G * g.n_pad + rows + 2 * (size_t)g.C) +
+  return sizeof(int32_t) * ((size_t)c.G * field_state_words(g.n_pad) + rows + 2 * (size_t)g.C) +
          3 * sizeof(int32_t) * (size_t)(g.n_pad / 4);
 }
 

@@ -30,6 +30,13 @@ constexpr int32_t kAcceptAll = -1;
 // -4 w s_new: 0100b = +4, 1100b = -4.
 constexpr int kDeg4BlockWords = 12;
 
+// FIELD path: LDS words of one replica's state.  The degree-4 forms lay the
+// state out in tiles of 64 groups, each tile holding its four slot planes
+// of 64 words (position 4 g + j -> word 256 (g / 64) + 64 j + g mod 64), so
+// the group count is rounded up to a multiple of 64.
+constexpr int field_state_words(int n_pad) { return 4 * ((n_pad / 4 + 63) & ~63); }
+constexpr int tile_word(int g, int j) { return ((g >> 6) << 8) + (j << 6) + (g & 63); }
+
 // FIELD path: packed word of a padding slot.  Its k = s h = 2^30 - 1 is
 // above every row's acceptable length (k never exceeds the problem's
 // kmax < 2^29), so padding is never flipped.

@@ -328,7 +328,7 @@ __device__ __forceinline__ void stage_adjacency_deg4(const JobDev& J, UnitLds& u
         for (int e = 0; e < 4; ++e) {
           const uint32_t a = adjm[o + e];
           const uint32_t q = a >> 1;  // neighbour position
-          const uint32_t word = (q & 3u) * (uint32_t)n_grp + (q >> 2);
+          const uint32_t word = (uint32_t)tile_word((int)(q >> 2), (int)(q & 3u));
           pos[2 * j + (e >> 1)] |= word << (16 * (e & 1));
           if (!(a & 1u)) nib[j >> 1] ^= 8u << (4 * (4 * (j & 1) + e));  // w < 0
         }
@@ -535,17 +535,19 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   const int r = block * G + rl;
   const bool live = r < J.R;
   const int n_pad = J.n_pad, n_grp = n_pad >> 2;
-  int32_t* st = smem + rl * n_pad;
-  // Word of slot j of group g.  The degree-4 forms keep the state
-  // slot-major, so that per-slot accesses of consecutive groups (the spin
-  // flips, and the pushes, whose neighbours are consecutive groups of
-  // another class) hit consecutive LDS banks; the other forms keep a
-  // group's four words together.
+  const int SW = field_state_words(n_pad);
+  int32_t* st = smem + rl * SW;
+  // Word of slot j of group g.  The degree-4 forms keep the state in tiles
+  // of 64 groups with a plane per slot, so that per-slot accesses of
+  // consecutive groups (the spin flips, and the pushes, whose neighbours
+  // are consecutive groups of another class) hit consecutive LDS banks and
+  // a group's four words are constant offsets (256 bytes) apart; the other
+  // forms keep a group's four words together.
   constexpr bool SOA = ADJ == kAdjLdsDeg4 || ADJ == kAdjHbmDeg4;
-  auto widx = [&](int g, int j) { return SOA ? j * n_grp + g : 4 * g + j; };
+  auto widx = [&](int g, int j) { return SOA ? tile_word(g, j) : 4 * g + j; };
   const int C = J.n_colours;
   const int RW = J.kw + 2;  // row words
-  UnitLds U = unit_lds(reinterpret_cast<uint32_t*>(smem), G * n_pad, J.row_chunk * RW, 2 * C, n_grp);
+  UnitLds U = unit_lds(reinterpret_cast<uint32_t*>(smem), G * SW, J.row_chunk * RW, 2 * C, n_grp);
   const uint32_t k0 = J.seed_lo, k1 = J.seed_hi;
   const int W = J.W;
   const GLOBAL_AS i32x2* __restrict__ aw = gconst(reinterpret_cast<const i32x2*>(J.aw));
@@ -598,11 +600,8 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
     stage_adjacency_deg4(J, U);
   }
   uint32_t* flist = ADJ == kAdjLds ? U.flips + (threadIdx.x >> 6) * 256 : nullptr;
-  // LDS byte address of this replica's words (degree-4 pushes), and of its
-  // four slot planes
+  // LDS byte address of this replica's words (degree-4 pushes)
   const uint32_t st_base = (uint32_t)(uintptr_t)(lds_i32*)st;
-  const uint32_t sb1 = st_base + 4u * (uint32_t)n_grp, sb2 = sb1 + 4u * (uint32_t)n_grp,
-                 sb3 = sb2 + 4u * (uint32_t)n_grp;
   __syncthreads();
 
   int E, best_cut, best_sweep;
@@ -681,10 +680,11 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           asm("" : "+v"(g));
           int4 w4;
           if (SOA) {
-            w4.x = st[g];
-            w4.y = st[n_grp + g];
-            w4.z = st[2 * n_grp + g];
-            w4.w = st[3 * n_grp + g];
+            const int32_t* s0 = st + tile_word(g, 0);
+            w4.x = s0[0];
+            w4.y = s0[64];
+            w4.z = s0[128];
+            w4.w = s0[192];
           } else {
             w4 = *reinterpret_cast<const int4*>(st + 4 * g);
           }
@@ -706,11 +706,18 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             lnb.x = (uint32_t)(U.gword[g] & kGroupLeaderMask);
           }
           const uint32_t leader = lnb.x;
+          // all of the group's reads go out before any arithmetic
+          __builtin_amdgcn_sched_barrier(0);
           int w[4] = {w4.x, w4.y, w4.z, w4.w};
-          if (snap) {
+          // Lazy best-state snapshot of this group (its end-of-previous-sweep
+          // spins).  The degree-4 forms keep w unchanged in registers and
+          // take it at the end of the iteration, so that no branch separates
+          // the group's loads from their first use.
+          auto snapshot = [&]() {
             const uint32_t bits = (w[0] & 1) | ((w[1] & 1) << 1) | ((w[2] & 1) << 2) | ((w[3] & 1) << 3);
             *reinterpret_cast<GLOBAL_AS uint32_t*>(best + 4 * g) = spins_to_bytes(bits);
-          }
+          };
+          if (!SOA && snap) snapshot();
           // Nearly every group needs its Philox block, so it is drawn
           // unconditionally.  The four threshold reads are issued first so
           // that the block's arithmetic covers their latency.  Row entry 0
@@ -737,8 +744,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             // (neighbours are in other classes), so a flip is an LDS XOR of
             // the spin bit under the accept mask: no per-slot selects.
             const uint32_t e[8] = {a01.x, a01.y, a01.z, a01.w, a23.x, a23.y, a23.z, a23.w};
-            const uint32_t g4 = 4u * (uint32_t)g;
-            const uint32_t gaddr[4] = {st_base + g4, sb1 + g4, sb2 + g4, sb3 + g4};
+            const uint32_t ga = st_base + 4u * (uint32_t)tile_word(g, 0);
             // push fields: the block's nibbles with each slot's old spin
             // bit (m = -bit) XOR-ed into bit 3 of its entries' nibbles
             const uint32_t r01 = lnb.y ^ ((uint32_t)m[0] & 0x00008888u) ^ ((uint32_t)m[1] & 0x88880000u);
@@ -746,12 +752,13 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               if (acc[j]) {
-                __hip_atomic_fetch_xor((lds_i32*)(uintptr_t)gaddr[j], 1, __ATOMIC_RELAXED,
+                __hip_atomic_fetch_xor((lds_i32*)(uintptr_t)(ga + 256u * j), 1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 dk += k[j];
                 push_deg4_slot(st_base, e[2 * j], e[2 * j + 1], j < 2 ? r01 : r23, j);
               }
             }
+            if (snap) snapshot();
           } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {

@@ -202,7 +202,7 @@ int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, cons
   }
   g.deg4 = n > 0;
   for (int32_t i = 0; i < n && g.deg4; ++i) g.deg4 = deg[(size_t)i + 1] - deg[(size_t)i] == 4;
-  if (g.deg4 && g.unit && g.n_pad <= (1 << 16)) {
+  if (g.deg4 && g.unit && field_state_words(g.n_pad) <= (1 << 16)) {
     const size_t ng = (size_t)g.n_pad / 4;
     g.adj4.assign((size_t)kDeg4BlockWords * ng, 0u);
     for (size_t q = 0; q < ng; ++q) {
@@ -213,10 +213,10 @@ int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, cons
         if (g.orig[4 * q + (size_t)j] < 0) continue;  // padding slot: never pushed
         const int32_t o = g.row[4 * q + (size_t)j];
         for (int e = 0; e < 4; ++e) {
-          // the FIELD kernel keeps the state slot-major in these forms:
-          // position p is word (p mod 4) * n_grp + p / 4
+          // the FIELD kernel keeps the state in 64-group tiles of slot
+          // planes in these forms (tile_word)
           const uint32_t pos = (uint32_t)g.adj[(size_t)(o + e)];
-          const uint32_t word = (pos & 3u) * (uint32_t)ng + (pos >> 2);
+          const uint32_t word = (uint32_t)tile_word((int)(pos >> 2), (int)(pos & 3u));
           blk[2 * j + e / 2] |= word << (16 * (e & 1));
           if (g.wgt[(size_t)(o + e)] < 0) blk[9 + j / 2] ^= 8u << (4 * (4 * (j & 1) + e));
         }

@@ -101,8 +101,7 @@ struct HostGraph {
   std::vector<uint32_t> gdeg;          // [n_pad/4] packed slot degrees
   // degree-4 graphs with at most 2^16 positions: the 48-byte group blocks
   // of the FIELD kernel (kDeg4BlockWords), neighbour entries as 16-bit word
-  // indices of the slot-major state layout (position p -> (p mod 4) *
-  // n_pad/4 + p/4)
+  // indices of the tiled state layout (tile_word)
   std::vector<uint32_t> adj4;
 };
 
