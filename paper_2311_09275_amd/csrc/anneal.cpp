@@ -140,9 +140,12 @@ static int ensure_device(ising_problem* p) { return upload_graph_once(p->g, p->d
 // ---------------------------------------------------------------- planning
 static bool pow2_upto(int x, int hi) { return x >= 1 && x <= hi && (x & (x - 1)) == 0; }
 
+// Words of one FIELD row: entries for the keys x = 0 .. 2 kw and the bound.
+static int field_row_words(const Table& t) { return 2 * std::max(t.kw, 1) + 2; }
+
 // FIELD rows are staged in chunks of up to 256 sweeps and about 8 KB.
 static int row_chunk(const Table& t) {
-  const int rw = std::max(t.kw, 1) + 2;
+  const int rw = field_row_words(t);
   return std::max(1, std::min(256, 2048 / rw));
 }
 
@@ -151,30 +154,33 @@ static int row_chunk(const Table& t) {
 // degrees).  The multispin kernel needs less (two rows, no class bounds).
 
 static size_t persistent_lds(const HostGraph& g, const Table& t, const PersistentConfig& c) {
-  const size_t rows = (size_t)row_chunk(t) * (size_t)(std::max(t.kw, 1) + 2);
+  const size_t rows = (size_t)row_chunk(t) * (size_t)field_row_words(t);
   return sizeof(int32_t) * ((size_t)c.G * field_state_words(g.n_pad) + rows + 2 * (size_t)g.C) +
          3 * sizeof(int32_t) * (size_t)(g.n_pad / 4);
 }
 
-// Rows of the FIELD kernel (JobDev::tqp): fixed stride kw + 2 so that a
-// sweep's row is fetched without first reading its offset.
+// Rows of the FIELD kernel (JobDev::tqp): fixed stride so that a sweep's
+// row is fetched without first reading its offset.  The kernel indexes a
+// row by the key x = 2 k - c (c = 1 for spin -1, else 0), so entries
+// 2 k - 1 and 2 k both hold the threshold of k.
 static size_t padded_rows(const Table& t) {
-  return (size_t)t.S * (size_t)(std::max(t.kw, 1) + 2);
+  return (size_t)t.S * (size_t)field_row_words(t);
 }
 
 static void build_padded_rows(const Table& t, std::vector<uint32_t>& out) {
-  const int kw = std::max(t.kw, 1), rw = kw + 2;
+  const int kw = std::max(t.kw, 1), rw = field_row_words(t);
   out.assign(padded_rows(t), 0u);
   for (int s = 0; s < t.S; ++s) {
     uint32_t* row = out.data() + (size_t)s * rw;
     const int len = t.len[(size_t)s];
     row[0] = 0xFFFFFFFFu;
     if (len == kAcceptAll) {
-      for (int k = 1; k <= kw; ++k) row[k] = 0xFFFFFFFFu;
-      row[kw + 1] = (uint32_t)t.kmax;
+      for (int x = 1; x <= 2 * kw; ++x) row[x] = 0xFFFFFFFFu;
+      row[2 * kw + 1] = 2u * (uint32_t)t.kmax;
     } else {
-      for (int k = 1; k <= len; ++k) row[k] = t.tq[(size_t)(t.off[(size_t)s] + k - 1)];
-      row[kw + 1] = (uint32_t)len;
+      for (int x = 1; x <= 2 * len; ++x)
+        row[x] = t.tq[(size_t)(t.off[(size_t)s] + (x + 1) / 2 - 1)];
+      row[2 * kw + 1] = 2u * (uint32_t)len;
     }
   }
 }

@@ -74,10 +74,12 @@ struct JobDev {
   const uint32_t* tq;    // thresholds minus one, rows back to back
   const int32_t* tq_off; // [S] row offsets into tq
   const int32_t* tq_len; // [S] row lengths, or kAcceptAll
-  // FIELD: rows of kw + 2 words: [0] = 0xFFFFFFFF (k <= 0 always accepts),
-  // [1..kw] = Tq - 1 for k = 1..len and 0 beyond, [kw + 1] = the largest
-  // acceptable k (len, or kmax when beta = 0 and the row is all 0xFFFFFFFF)
-  const uint32_t* tqp;   // [S][kw + 2]
+  // FIELD: rows of 2 kw + 2 words indexed by the key x = 2 k - c (c = 1
+  // for spin -1): [0] = 0xFFFFFFFF (k <= 0 always accepts), [x] for
+  // x = 1..2 kw = Tq - 1 of k = ceil(x / 2), 0 beyond k = len,
+  // [2 kw + 1] = twice the largest acceptable k (len, or kmax when beta = 0
+  // and the row is all 0xFFFFFFFF)
+  const uint32_t* tqp;   // [S][2 kw + 2]
   int32_t row_chunk;     // FIELD: sweeps whose rows are staged in LDS at once
   int32_t S, t_begin, t_end, flags;
   int32_t kw;            // longest row (LDS row capacity)

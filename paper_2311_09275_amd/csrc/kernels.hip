@@ -456,14 +456,14 @@ __device__ __forceinline__ void push_wave_compacted(int32_t* st, const uint16_t*
   }
 }
 
-// Degree-4 pushes.  The packed word of a neighbour changes by -4 w s_new:
-// +4 when the entry's negative-weight bit equals the new spin's bit (1 for
-// +1), -4 otherwise.  With q = negative-weight bits XOR the new spin bit,
-// entry e adds 4 when bit e of q is clear and -4 when it is set.  Each entry is decoded in three VALU operations, written out
-// because the compiler folds the field extracts into longer sequences:
-// the LDS byte address is one 16 x 16 + 32 multiply-add of the 16-bit
-// position (low or high half of the word), the value a sign-extended bit
-// field shifted and or-ed with 4.
+// Degree-4 pushes.  The packed word of a neighbour changes by -4 w s_new
+// = 4 w s_old.  Each entry carries a 4-bit field 0xC (-4 as a signed
+// nibble) with bit 3 cleared for w < 0 (+4); XOR-ing the flipping slot's
+// old spin bit into bit 3 gives the push value.  Each entry is then two
+// VALU operations, written out because the compiler folds the field
+// extracts into longer sequences: the LDS byte address is one 16 x 16 + 32
+// multiply-add of the 16-bit word index (low or high half of the word), the
+// value a sign-extending 4-bit field extract.
 typedef __attribute__((address_space(3))) int32_t lds_i32;
 
 template <int HI>
@@ -507,22 +507,25 @@ __device__ __forceinline__ void push_deg4_slot(uint32_t base, uint32_t lo, uint3
   }
 }
 
-// k = s h for a packed word (h << 1) | b, s = 2 b - 1: with m = -b,
-// k = (h XNOR m) + m + 1.  Written out (four operations where the compiler
-// emits five), like the threshold index: k clamped to [0, kw] by one
-// median-of-three.
-__device__ __forceinline__ int spin_times_field(int w, int& m) {
-  const int h = w >> 1;
-  int x, k;
+// Test key of a packed word w = (h << 1) | b (spin s = 2 b - 1), with
+// k = s h the quantity the acceptance test compares (the energy moves by
+// 2 k): x = 2 k - c, where c = 1 - b.  For b = 1, x = w XOR 1 = 2 h; for
+// b = 0, x = NOT w = -2 h - 1.  So x = w XNOR (m AND -2) with m = -b: one
+// bit-field extract and one three-input logic operation.  x <= 2 len holds
+// exactly when k <= len, and entry x of a row (rows of 2 kw + 2 words)
+// holds the threshold of k = ceil(x / 2).  Written out because the
+// compiler turns the select into longer sequences.
+__device__ __forceinline__ int field_key(int w, int& m) {
+  int x;
   asm("v_bfe_i32 %0, %1, 0, 1" : "=v"(m) : "v"(w));
-  asm("v_xnor_b32 %0, %1, %2" : "=v"(x) : "v"(h), "v"(m));
-  asm("v_add3_u32 %0, %1, %2, 1" : "=v"(k) : "v"(x), "v"(m));
-  return k;
+  asm("v_bitop3_b32 %0, %1, %2, -2 bitop3:0x87" : "=v"(x) : "v"(w), "v"(m));
+  return x;
 }
 
-__device__ __forceinline__ int clamp_row_index(int k, int kw) {
+// Row entry of key x: x clamped to [0, 2 kw] by one median-of-three.
+__device__ __forceinline__ int clamp_row_index(int x, int kw2) {
   int i;
-  asm("v_med3_i32 %0, %1, 0, %2" : "=v"(i) : "v"(k), "s"(kw));
+  asm("v_med3_i32 %0, %1, 0, %2" : "=v"(i) : "v"(x), "s"(kw2));
   return i;
 }
 
@@ -546,7 +549,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   constexpr bool SOA = ADJ == kAdjLdsDeg4 || ADJ == kAdjHbmDeg4;
   auto widx = [&](int g, int j) { return SOA ? tile_word(g, j) : 4 * g + j; };
   const int C = J.n_colours;
-  const int RW = J.kw + 2;  // row words
+  const int RW = 2 * J.kw + 2;  // row words
   UnitLds U = unit_lds(reinterpret_cast<uint32_t*>(smem), G * SW, J.row_chunk * RW, 2 * C, n_grp);
   const uint32_t k0 = J.seed_lo, k1 = J.seed_hi;
   const int W = J.W;
@@ -600,8 +603,9 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
     stage_adjacency_deg4(J, U);
   }
   uint32_t* flist = ADJ == kAdjLds ? U.flips + (threadIdx.x >> 6) * 256 : nullptr;
-  // LDS byte address of this replica's words (degree-4 pushes)
+  // LDS byte addresses of this replica's words and of the degree-4 blocks
   const uint32_t st_base = (uint32_t)(uintptr_t)(lds_i32*)st;
+  const uint32_t blk_base = (uint32_t)(uintptr_t)(lds_i32*)U.adj16;
   __syncthreads();
 
   int E, best_cut, best_sweep;
@@ -646,9 +650,12 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   }
 
   GLOBAL_AS int8_t* best = gmut(static_cast<int8_t*>(J.best)) + (int64_t)r * n_pad;
-  const int kw = J.kw;
-  int dk = 0;    // sum of k over this lane's accepted flips (the energy moves by 2 k)
-  int nacc = 0;  // accepted flips of this wave (wave-uniform)
+  const int kw2 = 2 * J.kw;
+  // sum over this lane's accepted flips of x + m = 2 k - 1; the sweep's
+  // energy change adds the wave's accepted count
+  int dk = 0;
+  int nacc = 0;       // accepted flips of this wave (wave-uniform)
+  int nacc_mark = 0;  // nacc at the start of the sweep
   // class bounds of the next pass, read one pass ahead
   int nb0 = U.cls[0], nb1 = U.cls[1];
   // Rows come in chunks of CH sweeps, one HBM copy and barrier per chunk,
@@ -662,7 +669,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
       __syncthreads();
     }
     const uint32_t* row = U.tq + tc * RW;
-    const int len = (int)row[RW - 1];
+    const int len2 = (int)row[RW - 1];  // twice the largest acceptable k
     ++tc;
     for (int c = 0; c < C; ++c) {
       const int g0 = nb0, g1 = nb1;
@@ -678,9 +685,12 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           // variable per array (the compiler's default) costs more.
           int g = gi;
           asm("" : "+v"(g));
+          // byte address of the group's slot-0 word in the tiled layout:
+          // 4 tile_word(g, 0) = 4 g + 12 (g AND -64)
+          lds_i32* const s0 =
+              (lds_i32*)(uintptr_t)(st_base + ((uint32_t)g << 2) + __umul24((uint32_t)g & ~63u, 12u));
           int4 w4;
           if (SOA) {
-            const int32_t* s0 = st + tile_word(g, 0);
             w4.x = s0[0];
             w4.y = s0[64];
             w4.z = s0[128];
@@ -692,10 +702,12 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           // so their latency is covered by the Philox block
           uint4 a01 = make_uint4(0u, 0u, 0u, 0u), a23 = a01, lnb = a01;
           if (ADJ == kAdjLdsDeg4) {
-            const uint4* blk = reinterpret_cast<const uint4*>(U.adj16) + 3 * g;
-            a01 = blk[0];
-            a23 = blk[1];
-            lnb = blk[2];
+            typedef __attribute__((address_space(3))) const u32x4 lds_u32x4;
+            lds_u32x4* blk = (lds_u32x4*)(uintptr_t)(blk_base + __umul24((uint32_t)g, 48u));
+            const u32x4 b0 = blk[0], b1 = blk[1], b2 = blk[2];
+            a01 = make_uint4(b0.x, b0.y, b0.z, b0.w);
+            a23 = make_uint4(b1.x, b1.y, b1.z, b1.w);
+            lnb = make_uint4(b2.x, b2.y, b2.z, b2.w);
           } else if (ADJ == kAdjHbmDeg4) {
             const GLOBAL_AS u32x4* blk = gconst(reinterpret_cast<const u32x4*>(J.adj4)) + 3 * g;
             const u32x4 b0 = blk[0], b1 = blk[1], b2 = blk[2];
@@ -722,39 +734,44 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           // unconditionally.  The four threshold reads are issued first so
           // that the block's arithmetic covers their latency.  Row entry 0
           // accepts k <= 0 and k above the row's length is refused by the
-          // length test (padding slots have k = 2^30 - 1), so each slot's
-          // test is two comparisons.
-          int k[4], m[4];  // m = -(spin bit)
+          // length test (padding slots have the key 2^31 - 2), so each
+          // slot's test is two comparisons.
+          int k[4], m[4];  // k = field_key, m = -(spin bit)
           uint32_t thr[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) k[j] = spin_times_field(w[j], m[j]);
+          for (int j = 0; j < 4; ++j) k[j] = field_key(w[j], m[j]);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) thr[j] = row[clamp_row_index(k[j], kw)];
+          for (int j = 0; j < 4; ++j) thr[j] = row[clamp_row_index(k[j], kw2)];
           // keep the reads ahead of the Philox arithmetic
           __builtin_amdgcn_sched_barrier(0);
           const uint4 x = group_block(leader, t, r, kTagSweep, k0, k1);
           bool acc[4];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            acc[j] = (k[j] <= len) & (pick(x, j) <= thr[j]);
-            nacc += __popcll(__ballot(acc[j]));
+            const bool in_row = k[j] <= len2, below = pick(x, j) <= thr[j];
+            acc[j] = in_row & below;
+            // two ballots of comparisons: their masks are ANDed as scalars
+            nacc += __popcll(__ballot(in_row) & __ballot(below));
           }
           if (ADJ == kAdjLdsDeg4 || ADJ == kAdjHbmDeg4) {
             // Within a pass only the owning lane touches a group's words
             // (neighbours are in other classes), so a flip is an LDS XOR of
             // the spin bit under the accept mask: no per-slot selects.
             const uint32_t e[8] = {a01.x, a01.y, a01.z, a01.w, a23.x, a23.y, a23.z, a23.w};
-            const uint32_t ga = st_base + 4u * (uint32_t)tile_word(g, 0);
             // push fields: the block's nibbles with each slot's old spin
             // bit (m = -bit) XOR-ed into bit 3 of its entries' nibbles
-            const uint32_t r01 = lnb.y ^ ((uint32_t)m[0] & 0x00008888u) ^ ((uint32_t)m[1] & 0x88880000u);
-            const uint32_t r23 = lnb.z ^ ((uint32_t)m[2] & 0x00008888u) ^ ((uint32_t)m[3] & 0x88880000u);
+            // (one three-input operation per slot: B XOR (A AND C))
+            const uint32_t r01 = __builtin_amdgcn_bitop3_b32(
+                (uint32_t)m[1], __builtin_amdgcn_bitop3_b32((uint32_t)m[0], lnb.y, 0x00008888u, 0x6c),
+                0x88880000u, 0x6c);
+            const uint32_t r23 = __builtin_amdgcn_bitop3_b32(
+                (uint32_t)m[3], __builtin_amdgcn_bitop3_b32((uint32_t)m[2], lnb.z, 0x00008888u, 0x6c),
+                0x88880000u, 0x6c);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               if (acc[j]) {
-                __hip_atomic_fetch_xor((lds_i32*)(uintptr_t)(ga + 256u * j), 1, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-                dk += k[j];
+                __hip_atomic_fetch_xor(s0 + 64 * j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                dk += k[j] + m[j];
                 push_deg4_slot(st_base, e[2 * j], e[2 * j + 1], j < 2 ? r01 : r23, j);
               }
             }
@@ -763,7 +780,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               w[j] = acc[j] ? w[j] ^ 1 : w[j];
-              dk += acc[j] ? k[j] : 0;
+              dk += acc[j] ? k[j] + m[j] : 0;
             }
             const bool any = acc[0] | acc[1] | acc[2] | acc[3];
             if (any) *reinterpret_cast<int4*>(st + 4 * g) = make_int4(w[0], w[1], w[2], w[3]);
@@ -777,9 +794,10 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
         }
       }
       if (c == C - 1) {
-        const int s = 2 * wave_sum(dk);
+        const int s = wave_sum(dk) + (nacc - nacc_mark);
         if ((tid & 63) == 0 && s != 0) atomicAdd(&sh.eacc[t % 3][rl], s);
         dk = 0;
+        nacc_mark = nacc;
       }
       __syncthreads();
     }
