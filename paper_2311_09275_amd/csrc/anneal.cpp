@@ -142,10 +142,13 @@ static bool pow2_upto(int x, int hi) { return x >= 1 && x <= hi && (x & (x - 1))
 
 // Words of one FIELD row: entries for the keys x = 0 .. 2 kw and the bound.
 static int field_row_words(const Table& t) { return 2 * std::max(t.kw, 1) + 2; }
+// LDS stride budget of a row: either form (key rows, or the degree-4 forms'
+// kBondRowWords) fits.
+static int row_words_max(const Table& t) { return std::max(field_row_words(t), kBondRowWords); }
 
 // FIELD rows are staged in chunks of up to 256 sweeps and about 8 KB.
 static int row_chunk(const Table& t) {
-  const int rw = field_row_words(t);
+  const int rw = row_words_max(t);
   return std::max(1, std::min(256, 2048 / rw));
 }
 
@@ -154,7 +157,7 @@ static int row_chunk(const Table& t) {
 // degrees).  The multispin kernel needs less (two rows, no class bounds).
 
 static size_t persistent_lds(const HostGraph& g, const Table& t, const PersistentConfig& c) {
-  const size_t rows = (size_t)row_chunk(t) * (size_t)field_row_words(t);
+  const size_t rows = (size_t)row_chunk(t) * (size_t)row_words_max(t);
   return sizeof(int32_t) * ((size_t)c.G * field_state_words(g.n_pad) + rows + 2 * (size_t)g.C) +
          3 * sizeof(int32_t) * (size_t)(g.n_pad / 4);
 }
@@ -185,6 +188,26 @@ static void build_padded_rows(const Table& t, std::vector<uint32_t>& out) {
   }
 }
 
+// Rows of the degree-4 forms (JobDev::tqb), indexed by the bond count plus
+// one, c = popc(word) in 1..5, for k = 2 c - 6.
+static void build_bond_rows(const Table& t, std::vector<uint32_t>& out) {
+  out.assign((size_t)t.S * kBondRowWords, 0u);
+  for (int s = 0; s < t.S; ++s) {
+    uint32_t* row = out.data() + (size_t)s * kBondRowWords;
+    const int len = t.len[(size_t)s];
+    for (int c = 0; c <= 3; ++c) row[c] = 0xFFFFFFFFu;  // k <= 0
+    if (len == kAcceptAll) {
+      row[4] = row[5] = 0xFFFFFFFFu;
+      row[7] = 5;
+    } else {
+      const int32_t o = t.off[(size_t)s];
+      row[4] = len >= 2 ? t.tq[(size_t)(o + 1)] : 0u;  // k = 2
+      row[5] = len >= 4 ? t.tq[(size_t)(o + 3)] : 0u;  // k = 4
+      row[7] = (uint32_t)std::min(5, (len + 6) / 2);   // 2 c - 6 <= len
+    }
+  }
+}
+
 // Staged adjacency forms of the FIELD kernel (16-bit entries).
 constexpr int kFormHbm = 0, kFormCsr = 1, kFormDeg4 = 2;
 constexpr int kFormPerJob = 3;   // a launch whose jobs use different forms
@@ -201,7 +224,7 @@ static size_t adjacency_lds(const HostGraph& g, int form) {
 }
 static bool adjacency_fits(const HostGraph& g, int form) {
   if (form == kFormHbmDeg4) return !g.adj4.empty();
-  if (form == kFormDeg4) return g.unit && g.deg4 && g.n_pad < (1 << 15);
+  if (form == kFormDeg4) return !g.adj4.empty() && g.n_pad < (1 << 15);
   return g.unit && g.n_pad < (1 << 15) && 2 * g.m < (1 << 17) && g.max_deg <= 255;
 }
 // The adjacency form that tuning value `adj` (0 decide, 1 LDS, 2 HBM
@@ -326,7 +349,9 @@ size_t run_bytes(const HostGraph& g, const Table& table, int R, const Persistent
          DeviceArena::span(sizeof(int32_t) * (size_t)g.n) +
          DeviceArena::span(sizeof(uint32_t) * table.tq.size()) +
          2 * DeviceArena::span(sizeof(int32_t) * S) + (init_given ? DeviceArena::span(RR * np) : 0) +
-         (cfg.path == ISING_PATH_FIELD ? DeviceArena::span(sizeof(uint32_t) * padded_rows(table)) : 0) +
+         (cfg.path == ISING_PATH_FIELD ? DeviceArena::span(sizeof(uint32_t) * padded_rows(table)) +
+                                            DeviceArena::span(sizeof(uint32_t) * kBondRowWords * S)
+                                      : 0) +
          DeviceArena::span(sizeof(JobDev));
 }
 
@@ -372,6 +397,7 @@ int prepare_buffers(RunBuffers& b, const HostGraph& g, const Table& table, int R
   b.tq_off = b.arena.take<int32_t>((size_t)S);
   b.tq_len = b.arena.take<int32_t>((size_t)S);
   b.tqp = cfg.path == ISING_PATH_FIELD ? b.arena.take<uint32_t>(padded_rows(table)) : nullptr;
+  b.tqb = cfg.path == ISING_PATH_FIELD ? b.arena.take<uint32_t>((size_t)kBondRowWords * S) : nullptr;
   b.init_dev = init_given ? b.arena.take<int8_t>(RR * np) : nullptr;
   b.job_dev = b.arena.take<JobDev>(1);
   if (plain) {
@@ -407,6 +433,9 @@ int prepare_buffers(RunBuffers& b, const HostGraph& g, const Table& table, int R
     if (b.tqp) {
       build_padded_rows(b.table, b.tqp_host);
       ICHK(hipMemcpyAsync(b.tqp, b.tqp_host.data(), sizeof(uint32_t) * b.tqp_host.size(),
+                          hipMemcpyHostToDevice, stream));
+      build_bond_rows(b.table, b.tqb_host);
+      ICHK(hipMemcpyAsync(b.tqb, b.tqb_host.data(), sizeof(uint32_t) * b.tqb_host.size(),
                           hipMemcpyHostToDevice, stream));
     }
     b.up_table = table.id;
@@ -457,6 +486,7 @@ JobDev make_job(const HostGraph& g, const DevGraph& d, const RunBuffers& b, int 
   J.tq_off = b.tq_off;
   J.tq_len = b.tq_len;
   J.tqp = b.tqp;
+  J.tqb = b.tqb;
   J.row_chunk = row_chunk(table);
   J.S = table.S;
   J.t_begin = t_begin;

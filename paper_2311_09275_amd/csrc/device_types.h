@@ -23,12 +23,25 @@ constexpr int32_t kAcceptAll = -1;
 
 // Degree-4 group block, 12 words (48 bytes): words 0..7 hold the 16-bit LDS
 // word indices of the 16 neighbour entries (slot j's four at 16-bit index
-// 4j..4j+3), word 8 the leader id, words 9 and 10 one 4-bit field per entry
-// (entry e of slot j in word 9 + j/2, nibble 4 (j mod 2) + e): 0xC, with bit
-// 3 cleared when the entry's weight is negative.  XOR-ed with the slot's old
-// spin bit in bit 3, the nibble read as a signed 4-bit number is the push
-// -4 w s_new: 0100b = +4, 1100b = -4.
+// 4j..4j+3, in label order: entry e of v is the neighbour u whose entry
+// e XOR 1 is v), word 8 the leader id, word 9 bit 4j+e set when entry e of
+// slot j has w > 0; words 10 and 11 are zero.
 constexpr int kDeg4BlockWords = 12;
+
+// FIELD path, degree-4 forms: a vertex's LDS word holds bond bits instead
+// of a field.  Bit 0 is the spin bit b, bit 1 its complement, and bit
+// kBondShift + e says whether the edge to entry e is satisfied
+// (s_v J s_u = +1, J = -w).  The field follows: k = s h = 2 q - 4 for q
+// satisfied bonds, and popc(word) = q + 1.  A flip XORs kBondFlipMask, a
+// neighbour's flip one bond bit.
+constexpr int kBondShift = 2;
+constexpr int32_t kBondFlipMask = 0x3F;
+// padding: popc 6, above every row's bound (at most 5), never flipped
+constexpr int32_t kBondPadWord = 0x3F;
+// Rows of the degree-4 forms, indexed by popc(word): [1..3] = 0xFFFFFFFF
+// (k <= 0), [4], [5] = Tq - 1 of k = 2, 4 (0 beyond len), [6] = 0,
+// [7] = the largest acceptable popc.
+constexpr int kBondRowWords = 8;
 
 // FIELD path: LDS words of one replica's state.  The degree-4 forms lay the
 // state out in tiles of 64 groups, each tile holding its four slot planes
@@ -80,6 +93,7 @@ struct JobDev {
   // [2 kw + 1] = twice the largest acceptable k (len, or kmax when beta = 0
   // and the row is all 0xFFFFFFFF)
   const uint32_t* tqp;   // [S][2 kw + 2]
+  const uint32_t* tqb;   // FIELD degree-4 forms: [S][kBondRowWords]
   int32_t row_chunk;     // FIELD: sweeps whose rows are staged in LDS at once
   int32_t S, t_begin, t_end, flags;
   int32_t kw;            // longest row (LDS row capacity)

@@ -259,7 +259,7 @@ struct FieldShared {
 };
 
 struct UnitLds {
-  uint32_t* tq;     // FIELD: [row_chunk][kw + 2] rows; MSC: [2][kw] (t even, odd)
+  uint32_t* tq;     // FIELD: [row_chunk][row words] rows; MSC: [2][kw] (t even, odd)
   int32_t* cls;     // [2C] first and end group of each class (FIELD)
   int32_t* gword;   // [n_grp]
   int32_t* gbase;   // [n_grp]
@@ -307,38 +307,13 @@ __device__ __forceinline__ void stage_adjacency(const JobDev& J, const UnitLds& 
   for (int i = threadIdx.x; i < n; i += blockDim.x) u.adj16[i] = (uint16_t)adjm[i];
 }
 
-// Degree-4 form: the 48-byte group blocks (kDeg4BlockWords) of the unit,
-// with slot-major LDS word indices (see field_unit); padding slots get
-// zero entries (never pushed: padding never flips).
+// Degree-4 form: the unit's copy of the 48-byte group blocks
+// (kDeg4BlockWords), built on the host.
 __device__ __forceinline__ void stage_adjacency_deg4(const JobDev& J, UnitLds& u) {
-  const GLOBAL_AS uint32_t* adjm = gconst(J.adjm);
-  const GLOBAL_AS int32_t* grp = gconst(J.grp);
-  const GLOBAL_AS int32_t* gbase = gconst(J.gbase);
-  const int n_grp = J.n_pad >> 2;
-  for (int g = threadIdx.x; g < n_grp; g += blockDim.x) {
-    const int cnt = (grp[g] >> kGroupCountShift) + 1;
-    uint32_t pos[8], nib[2] = {0xCCCCCCCCu, 0xCCCCCCCCu};
-#pragma unroll
-    for (int i = 0; i < 8; ++i) pos[i] = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (j < cnt) {
-        const int o = gbase[g] + 4 * j;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint32_t a = adjm[o + e];
-          const uint32_t q = a >> 1;  // neighbour position
-          const uint32_t word = (uint32_t)tile_word((int)(q >> 2), (int)(q & 3u));
-          pos[2 * j + (e >> 1)] |= word << (16 * (e & 1));
-          if (!(a & 1u)) nib[j >> 1] ^= 8u << (4 * (4 * (j & 1) + e));  // w < 0
-        }
-      }
-    }
-    uint4* dst = reinterpret_cast<uint4*>(u.adj16) + 3 * g;
-    dst[0] = make_uint4(pos[0], pos[1], pos[2], pos[3]);
-    dst[1] = make_uint4(pos[4], pos[5], pos[6], pos[7]);
-    dst[2] = make_uint4((uint32_t)(grp[g] & kGroupLeaderMask), nib[0], nib[1], 0u);
-  }
+  const GLOBAL_AS u32x4* src = gconst(reinterpret_cast<const u32x4*>(J.adj4));
+  u32x4* dst = reinterpret_cast<u32x4*>(u.adj16);
+  const int n = 3 * (J.n_pad >> 2);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
 __device__ __forceinline__ void stage_row(const JobDev& J, int t, uint32_t* buf) {
@@ -348,11 +323,11 @@ __device__ __forceinline__ void stage_row(const JobDev& J, int t, uint32_t* buf)
   for (int i = threadIdx.x; i < len; i += blockDim.x) buf[(t & 1) * J.kw + i] = src[i];
 }
 
-// FIELD rows (kw + 2 words each, see JobDev::tqp) of sweeps t .. t+n-1,
-// one contiguous copy.
-__device__ __forceinline__ void stage_row_chunk(const JobDev& J, int t, int n, uint32_t* buf,
+// FIELD rows (rw words each, see JobDev::tqp and JobDev::tqb) of sweeps
+// t .. t+n-1, one contiguous copy.
+__device__ __forceinline__ void stage_row_chunk(const uint32_t* rows, int t, int n, uint32_t* buf,
                                                 int rw) {
-  const GLOBAL_AS uint32_t* src = gconst(J.tqp) + (int64_t)t * rw;
+  const GLOBAL_AS uint32_t* src = gconst(rows) + (int64_t)t * rw;
   for (int i = threadIdx.x; i < n * rw; i += blockDim.x) buf[i] = src[i];
 }
 
@@ -456,14 +431,12 @@ __device__ __forceinline__ void push_wave_compacted(int32_t* st, const uint16_t*
   }
 }
 
-// Degree-4 pushes.  The packed word of a neighbour changes by -4 w s_new
-// = 4 w s_old.  Each entry carries a 4-bit field 0xC (-4 as a signed
-// nibble) with bit 3 cleared for w < 0 (+4); XOR-ing the flipping slot's
-// old spin bit into bit 3 gives the push value.  Each entry is then two
-// VALU operations, written out because the compiler folds the field
-// extracts into longer sequences: the LDS byte address is one 16 x 16 + 32
-// multiply-add of the 16-bit word index (low or high half of the word), the
-// value a sign-extending 4-bit field extract.
+// Degree-4 (bond) pushes.  A flip of v changes the bond bit of each of its
+// edges, and neighbour u holds that bit at position kBondShift + (e XOR 1)
+// when u is entry e of v (the host labels edges that way), so a push is an
+// LDS XOR of a mask fixed by e.  The LDS byte address is one 16 x 16 + 32
+// multiply-add of the entry's 16-bit word index (low or high half of the
+// word), written out because the compiler extracts the halves separately.
 typedef __attribute__((address_space(3))) int32_t lds_i32;
 
 template <int HI>
@@ -476,35 +449,16 @@ __device__ __forceinline__ uint32_t lds_byte_addr(uint32_t two, uint32_t base) {
   return a;
 }
 
-// Push value of the entry whose 4-bit field starts at bit OFF: the field
-// read as a signed number (one sign-extending bit-field extract).
-template <int OFF>
-__device__ __forceinline__ int nibble_value(uint32_t r) {
-  int v;
-  asm("v_bfe_i32 %0, %1, %2, 4" : "=v"(v) : "v"(r), "i"(OFF));
-  return v;
-}
-
-// Pushes of the two entries packed in `two`; K = nibble of the first.
-template <int K>
-__device__ __forceinline__ void push_deg4_pair(uint32_t base, uint32_t two, uint32_t r) {
-  __hip_atomic_fetch_add((lds_i32*)(uintptr_t)lds_byte_addr<0>(two, base), nibble_value<4 * K>(r),
+// The four pushes of one slot; lo and hi hold its entries 0, 1 and 2, 3.
+__device__ __forceinline__ void push_bond_slot(uint32_t base, uint32_t lo, uint32_t hi) {
+  __hip_atomic_fetch_xor((lds_i32*)(uintptr_t)lds_byte_addr<0>(lo, base), 1 << (kBondShift + 1),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  __hip_atomic_fetch_add((lds_i32*)(uintptr_t)lds_byte_addr<1>(two, base), nibble_value<4 * K + 4>(r),
+  __hip_atomic_fetch_xor((lds_i32*)(uintptr_t)lds_byte_addr<1>(lo, base), 1 << kBondShift,
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// The four pushes of slot j (unrolled callers pass a constant j); r holds
-// the nibbles of slots 2 (j/2) and 2 (j/2) + 1.
-__device__ __forceinline__ void push_deg4_slot(uint32_t base, uint32_t lo, uint32_t hi, uint32_t r,
-                                               int j) {
-  if (j & 1) {
-    push_deg4_pair<4>(base, lo, r);
-    push_deg4_pair<6>(base, hi, r);
-  } else {
-    push_deg4_pair<0>(base, lo, r);
-    push_deg4_pair<2>(base, hi, r);
-  }
+  __hip_atomic_fetch_xor((lds_i32*)(uintptr_t)lds_byte_addr<0>(hi, base), 1 << (kBondShift + 3),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_fetch_xor((lds_i32*)(uintptr_t)lds_byte_addr<1>(hi, base), 1 << (kBondShift + 2),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Test key of a packed word w = (h << 1) | b (spin s = 2 b - 1), with
@@ -549,7 +503,10 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   constexpr bool SOA = ADJ == kAdjLdsDeg4 || ADJ == kAdjHbmDeg4;
   auto widx = [&](int g, int j) { return SOA ? tile_word(g, j) : 4 * g + j; };
   const int C = J.n_colours;
-  const int RW = 2 * J.kw + 2;  // row words
+  // row words: the degree-4 forms test a bond count, the others the key
+  // of field_key
+  const int RW = SOA ? kBondRowWords : 2 * J.kw + 2;
+  const uint32_t* const rows = SOA ? J.tqb : J.tqp;
   UnitLds U = unit_lds(reinterpret_cast<uint32_t*>(smem), G * SW, J.row_chunk * RW, 2 * C, n_grp);
   const uint32_t k0 = J.seed_lo, k1 = J.seed_hi;
   const int W = J.W;
@@ -593,7 +550,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
     }
   }
   const int CH = J.row_chunk;
-  stage_row_chunk(J, J.t_begin, min(CH, J.t_end - J.t_begin), U.tq, RW);
+  stage_row_chunk(rows, J.t_begin, min(CH, J.t_end - J.t_begin), U.tq, RW);
   for (int i = tid; i < 2 * C; i += BLOCK) U.cls[i] = gconst(J.cls)[i];
   stage_groups(J, U);
   if (ADJ == kAdjLds) {
@@ -610,7 +567,60 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
 
   int E, best_cut, best_sweep;
   bool snap;
-  if (fresh) {
+  if (SOA) {
+    // Bond words from the spins (bit 0 of every word at this point), for a
+    // fresh start and a resumed chunk alike.  Only bit 0 of other words is
+    // read while words are rewritten, and bit 0 keeps the spin.
+    int part = 0;
+    if (live) {
+      for (int p = lt; p < n_pad; p += TPR) {
+        const int g = p >> 2, j = p & 3;
+        int32_t* wp = st + tile_word(g, j);
+        if (j > (U.gword[g] >> kGroupCountShift)) {
+          *wp = kBondPadWord;
+          continue;
+        }
+        uint32_t blk[12];
+        if (ADJ == kAdjLdsDeg4) {
+          const uint4* b = reinterpret_cast<const uint4*>(U.adj16) + 3 * g;
+          *reinterpret_cast<uint4*>(blk) = b[0];
+          *reinterpret_cast<uint4*>(blk + 4) = b[1];
+          *reinterpret_cast<uint4*>(blk + 8) = b[2];
+        } else {
+          const GLOBAL_AS u32x4* b = gconst(reinterpret_cast<const u32x4*>(J.adj4)) + 3 * g;
+          for (int i = 0; i < 3; ++i) {
+            const u32x4 x = b[i];
+            blk[4 * i] = x.x;
+            blk[4 * i + 1] = x.y;
+            blk[4 * i + 2] = x.z;
+            blk[4 * i + 3] = x.w;
+          }
+        }
+        const uint32_t bv = (uint32_t)*wp & 1u;
+        uint32_t word = bv | ((bv ^ 1u) << 1);
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t nw = (blk[2 * j + (e >> 1)] >> (16 * (e & 1))) & 0xFFFFu;
+          const uint32_t bu = (uint32_t)st[nw] & 1u;
+          const uint32_t wpos = (blk[9] >> (4 * j + e)) & 1u;
+          word |= (1u ^ bv ^ bu ^ wpos) << (kBondShift + e);
+        }
+        part += 2 * __popc(word) - 6;  // k = s h
+        *wp = (int32_t)word;
+      }
+    }
+    __syncthreads();
+    if (fresh) {
+      part = wave_sum(part);
+      if ((tid & 63) == 0 && part != 0) atomicAdd(&sh.eacc[3][rl], part);
+      __syncthreads();
+      E = -sh.eacc[3][rl] / 2;
+    }
+  }
+  if (fresh && SOA) {
+    best_cut = (W - E) / 2;
+    best_sweep = -1;
+    snap = true;  // the initial state is written during sweep 0
+  } else if (fresh) {
     // fields from scratch: h_p = -sum_q w_pq s_q.  Only bit 0 of other
     // words is read while fields are written, and that bit is unchanged.
     int part = 0;
@@ -664,12 +674,14 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   int tc = 0;  // sweep within the staged chunk
   for (int t = J.t_begin; t < J.t_end; ++t) {
     if (tc == CH) {
-      stage_row_chunk(J, t, min(CH, J.t_end - t), U.tq, RW);
+      stage_row_chunk(rows, t, min(CH, J.t_end - t), U.tq, RW);
       tc = 0;
       __syncthreads();
     }
     const uint32_t* row = U.tq + tc * RW;
-    const int len2 = (int)row[RW - 1];  // twice the largest acceptable k
+    // the row's bound: twice the largest acceptable k (key rows), or the
+    // largest acceptable bond count plus one (degree-4 rows)
+    const int len2 = (int)row[RW - 1];
     ++tc;
     for (int c = 0; c < C; ++c) {
       const int g0 = nb0, g1 = nb1;
@@ -736,12 +748,19 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           // accepts k <= 0 and k above the row's length is refused by the
           // length test (padding slots have the key 2^31 - 2), so each
           // slot's test is two comparisons.
-          int k[4], m[4];  // k = field_key, m = -(spin bit)
+          // k: the bond count plus one (degree-4 forms, rows indexed by
+          // it directly) or field_key; m = -(spin bit)
+          int k[4], m[4];
           uint32_t thr[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) k[j] = field_key(w[j], m[j]);
+          for (int j = 0; j < 4; ++j) {
+            if (SOA)
+              k[j] = __popc((uint32_t)w[j]);
+            else
+              k[j] = field_key(w[j], m[j]);
+          }
 #pragma unroll
-          for (int j = 0; j < 4; ++j) thr[j] = row[clamp_row_index(k[j], kw2)];
+          for (int j = 0; j < 4; ++j) thr[j] = row[SOA ? k[j] : clamp_row_index(k[j], kw2)];
           // keep the reads ahead of the Philox arithmetic
           __builtin_amdgcn_sched_barrier(0);
           const uint4 x = group_block(leader, t, r, kTagSweep, k0, k1);
@@ -754,25 +773,18 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             nacc += __popcll(__ballot(in_row) & __ballot(below));
           }
           if (ADJ == kAdjLdsDeg4 || ADJ == kAdjHbmDeg4) {
-            // Within a pass only the owning lane touches a group's words
-            // (neighbours are in other classes), so a flip is an LDS XOR of
-            // the spin bit under the accept mask: no per-slot selects.
+            // Within a pass only the owning lane touches a group's own
+            // words and neighbours only toggle bond bits (they are in other
+            // classes), so a flip is an LDS XOR of the spin pair and the
+            // four bond bits, and each push an LDS XOR of one bond bit.
             const uint32_t e[8] = {a01.x, a01.y, a01.z, a01.w, a23.x, a23.y, a23.z, a23.w};
-            // push fields: the block's nibbles with each slot's old spin
-            // bit (m = -bit) XOR-ed into bit 3 of its entries' nibbles
-            // (one three-input operation per slot: B XOR (A AND C))
-            const uint32_t r01 = __builtin_amdgcn_bitop3_b32(
-                (uint32_t)m[1], __builtin_amdgcn_bitop3_b32((uint32_t)m[0], lnb.y, 0x00008888u, 0x6c),
-                0x88880000u, 0x6c);
-            const uint32_t r23 = __builtin_amdgcn_bitop3_b32(
-                (uint32_t)m[3], __builtin_amdgcn_bitop3_b32((uint32_t)m[2], lnb.z, 0x00008888u, 0x6c),
-                0x88880000u, 0x6c);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               if (acc[j]) {
-                __hip_atomic_fetch_xor(s0 + 64 * j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                dk += k[j] + m[j];
-                push_deg4_slot(st_base, e[2 * j], e[2 * j + 1], j < 2 ? r01 : r23, j);
+                __hip_atomic_fetch_xor(s0 + 64 * j, kBondFlipMask, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                dk += k[j];
+                push_bond_slot(st_base, e[2 * j], e[2 * j + 1]);
               }
             }
             if (snap) snapshot();
@@ -794,7 +806,10 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
         }
       }
       if (c == C - 1) {
-        const int s = wave_sum(dk) + (nacc - nacc_mark);
+        // degree-4 forms: 2 k = 4 (bond count + 1) - 12; others:
+        // 2 k = (x + m) + 1
+        const int s = SOA ? 4 * wave_sum(dk) - 12 * (nacc - nacc_mark)
+                          : wave_sum(dk) + (nacc - nacc_mark);
         if ((tid & 63) == 0 && s != 0) atomicAdd(&sh.eacc[t % 3][rl], s);
         dk = 0;
         nacc_mark = nacc;
@@ -817,7 +832,15 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
     for (int g = lt; g < n_grp; g += TPR) {
       int4 w4;
       if (SOA) {
-        w4 = make_int4(st[widx(g, 0)], st[widx(g, 1)], st[widx(g, 2)], st[widx(g, 3)]);
+        // bond words back to packed fields: k = 2 popc - 6, h = s k
+        int v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int x = st[widx(g, j)];
+          const int b = x & 1, kk = 2 * __popc((uint32_t)x) - 6;
+          v[j] = x == kBondPadWord ? kPadWord : (((b ? kk : -kk) << 1) | b);
+        }
+        w4 = make_int4(v[0], v[1], v[2], v[3]);
       } else {
         w4 = *reinterpret_cast<const int4*>(st + 4 * g);
       }

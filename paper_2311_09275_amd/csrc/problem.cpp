@@ -28,6 +28,96 @@ void set_error(const char* fmt, ...) {
 const char* last_error() { return g_err; }
 
 // ---------------------------------------------------------------- graph
+// Neighbour labels of a 4-regular graph (CSR deg/nb in vertex ids) such
+// that lab[4 v + e] = u implies lab[4 u + (e ^ 1)] = v: an edge carries
+// labels 2f and 2f + 1 at its two ends.  Closed walks over unused edges
+// orient every edge with two out- and two in-edges per vertex (all degrees
+// are even, so a walk can only stop where it started).  The graph that
+// joins each vertex's out side to the in side of its out-neighbours is
+// then 2-regular and bipartite, a union of even cycles; taking their edges
+// alternately gives two perfect matchings f = 0, 1, and an edge v -> u of
+// matching f is labelled 2f at v and 2f + 1 at u.  False if a check fails.
+static bool bond_labels(int32_t n, const std::vector<int32_t>& deg, const std::vector<int32_t>& nb,
+                        std::vector<int32_t>& lab) {
+  const size_t H = (size_t)deg[(size_t)n];  // half-edges
+  std::vector<int32_t> mate(H, -1), head(H, 0);
+  for (int32_t v = 0; v < n; ++v)
+    for (int32_t a = deg[(size_t)v]; a < deg[(size_t)v + 1]; ++a) {
+      head[(size_t)a] = v;
+      const int32_t u = nb[(size_t)a];
+      for (int32_t b = deg[(size_t)u]; b < deg[(size_t)u + 1]; ++b)
+        if (nb[(size_t)b] == v) mate[(size_t)a] = b;
+      if (mate[(size_t)a] < 0) return false;
+    }
+  // orientation: dir[a] = 1 when half-edge a (head[a] -> nb[a]) was walked
+  std::vector<uint8_t> used(H, 0), dir(H, 0);
+  std::vector<int32_t> next(deg.begin(), deg.end() - 1);
+  for (int32_t s0 = 0; s0 < n; ++s0) {
+    for (;;) {
+      int32_t v = s0;
+      bool moved = false;
+      for (;;) {
+        while (next[(size_t)v] < deg[(size_t)v + 1] && used[(size_t)next[(size_t)v]]) ++next[(size_t)v];
+        if (next[(size_t)v] == deg[(size_t)v + 1]) break;
+        const int32_t a = next[(size_t)v];
+        used[(size_t)a] = used[(size_t)mate[(size_t)a]] = 1;
+        dir[(size_t)a] = 1;
+        v = nb[(size_t)a];
+        moved = true;
+      }
+      if (!moved) break;
+      if (v != s0) return false;
+    }
+  }
+  // out- and in-half-edges per vertex (walked half-edges leave head[a])
+  std::vector<int32_t> outs((size_t)2 * n, -1), ins((size_t)2 * n, -1);
+  std::vector<int> n_out((size_t)n, 0), n_in((size_t)n, 0);
+  for (size_t a = 0; a < H; ++a) {
+    if (!dir[a]) continue;
+    const int32_t v = head[a], u = nb[a];
+    if (n_out[(size_t)v] > 1 || n_in[(size_t)u] > 1) return false;
+    outs[2 * (size_t)v + (size_t)n_out[(size_t)v]++] = (int32_t)a;
+    ins[2 * (size_t)u + (size_t)n_in[(size_t)u]++] = (int32_t)a;
+  }
+  for (int32_t v = 0; v < n; ++v)
+    if (n_out[(size_t)v] != 2 || n_in[(size_t)v] != 2) return false;
+  // alternate the edges of each out/in cycle between matchings 0 and 1
+  std::vector<int8_t> fac(H, -1);
+  for (size_t a0 = 0; a0 < H; ++a0) {
+    if (!dir[a0] || fac[a0] >= 0) continue;
+    int32_t a = (int32_t)a0;
+    int f = 0;
+    while (fac[(size_t)a] < 0) {
+      fac[(size_t)a] = (int8_t)f;
+      // the other in-edge of a's target, then the other out-edge of its tail
+      const int32_t u = nb[(size_t)a];
+      const int32_t b = ins[2 * (size_t)u] == a ? ins[2 * (size_t)u + 1] : ins[2 * (size_t)u];
+      if (fac[(size_t)b] >= 0) {
+        if (fac[(size_t)b] == f) return false;
+        break;
+      }
+      fac[(size_t)b] = (int8_t)(1 - f);
+      const int32_t t = head[(size_t)b];
+      a = outs[2 * (size_t)t] == b ? outs[2 * (size_t)t + 1] : outs[2 * (size_t)t];
+      if (fac[(size_t)a] >= 0 && fac[(size_t)a] != f) return false;
+    }
+  }
+  lab.assign((size_t)4 * n, -1);
+  for (size_t a = 0; a < H; ++a) {
+    if (!dir[a]) continue;
+    const int32_t v = head[a], u = nb[a], f = fac[a];
+    if (f < 0 || lab[4 * (size_t)v + 2 * f] >= 0 || lab[4 * (size_t)u + 2 * f + 1] >= 0) return false;
+    lab[4 * (size_t)v + 2 * f] = u;
+    lab[4 * (size_t)u + 2 * f + 1] = v;
+  }
+  for (int32_t v = 0; v < n; ++v)
+    for (int e = 0; e < 4; ++e) {
+      const int32_t u = lab[4 * (size_t)v + e];
+      if (u < 0 || lab[4 * (size_t)u + (e ^ 1)] != v) return false;
+    }
+  return true;
+}
+
 int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, const int32_t* w,
                   const int32_t* colour, HostGraph& g) {
   if (n < 1 || n >= (1 << 28) || m < 0) {
@@ -202,23 +292,27 @@ int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, cons
   }
   g.deg4 = n > 0;
   for (int32_t i = 0; i < n && g.deg4; ++i) g.deg4 = deg[(size_t)i + 1] - deg[(size_t)i] == 4;
-  if (g.deg4 && g.unit && field_state_words(g.n_pad) <= (1 << 16)) {
+  std::vector<int32_t> lab;
+  if (g.deg4 && g.unit && field_state_words(g.n_pad) <= (1 << 16) && bond_labels(n, deg, nb, lab)) {
     const size_t ng = (size_t)g.n_pad / 4;
     g.adj4.assign((size_t)kDeg4BlockWords * ng, 0u);
     for (size_t q = 0; q < ng; ++q) {
       uint32_t* blk = g.adj4.data() + (size_t)kDeg4BlockWords * q;
       blk[8] = (uint32_t)(g.grp[q] & kGroupLeaderMask);
-      blk[9] = blk[10] = 0xCCCCCCCCu;
       for (int j = 0; j < 4; ++j) {
-        if (g.orig[4 * q + (size_t)j] < 0) continue;  // padding slot: never pushed
-        const int32_t o = g.row[4 * q + (size_t)j];
+        const int32_t i = g.orig[4 * q + (size_t)j];
+        if (i < 0) continue;  // padding slot: never pushed
         for (int e = 0; e < 4; ++e) {
-          // the FIELD kernel keeps the state in 64-group tiles of slot
-          // planes in these forms (tile_word)
-          const uint32_t pos = (uint32_t)g.adj[(size_t)(o + e)];
+          // neighbours in label order, as words of the FIELD kernel's
+          // tiled state (tile_word), and the sign of each weight
+          const int32_t nbr = lab[4 * (size_t)i + e];
+          const uint32_t pos = (uint32_t)g.pos[(size_t)nbr];
           const uint32_t word = (uint32_t)tile_word((int)(pos >> 2), (int)(pos & 3u));
           blk[2 * j + e / 2] |= word << (16 * (e & 1));
-          if (g.wgt[(size_t)(o + e)] < 0) blk[9 + j / 2] ^= 8u << (4 * (4 * (j & 1) + e));
+          int32_t we = 0;
+          for (int32_t a = deg[(size_t)i]; a < deg[(size_t)i + 1]; ++a)
+            if (nb[(size_t)a] == nbr) we = nw[(size_t)a];
+          if (we > 0) blk[9] |= 1u << (4 * j + e);
         }
       }
     }

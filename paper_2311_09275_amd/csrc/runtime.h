@@ -148,8 +148,9 @@ struct RunBuffers {
   unsigned long long *accepts = nullptr, *argmax = nullptr;
   uint32_t* tq = nullptr;
   int32_t *tq_off = nullptr, *tq_len = nullptr;
-  uint32_t* tqp = nullptr;     // FIELD: padded rows [S][kw + 2]
-  std::vector<uint32_t> tqp_host;
+  uint32_t* tqp = nullptr;     // FIELD: key rows [S][2 kw + 2]
+  uint32_t* tqb = nullptr;     // FIELD: degree-4 rows [S][kBondRowWords]
+  std::vector<uint32_t> tqp_host, tqb_host;
   // what the last table upload wrote, so that an unchanged table on an
   // unchanged arena is not uploaded again
   uint64_t up_table = 0, up_generation = 0;
