@@ -161,7 +161,7 @@ typedef struct {
   int32_t* colour;       /* [n] */
   int32_t* class_start;  /* [C+1] into members */
   int32_t* members;      /* [n] vertices of each class, ascending id */
-  int32_t* leader;       /* [n] RNG counter word 0 for vertex v */
+  int32_t* run;          /* [n] RNG counter word 1: ordinal of v's run */
   int32_t* rank;         /* [n] which Philox output word vertex v uses */
   int64_t W;
   int64_t kmax;          /* max_v sum_j |w_vj| */
@@ -174,7 +174,7 @@ static void graph_free(or_graph* G) {
   free(G->colour);
   free(G->class_start);
   free(G->members);
-  free(G->leader);
+  free(G->run);
   free(G->rank);
 }
 
@@ -269,32 +269,35 @@ static int graph_build(const or_graph_in* in, or_graph* G) {
   for (int32_t i = 0; i < n; ++i) G->class_start[G->colour[i] + 1]++;
   for (int32_t c = 0; c < C; ++c) G->class_start[c + 1] += G->class_start[c];
   G->members = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-  G->leader = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  G->run = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
   G->rank = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
   int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * ((size_t)C + 1));
   for (int32_t c = 0; c <= C; ++c) pos[c] = G->class_start[c];
   for (int32_t i = 0; i < n; ++i) G->members[pos[G->colour[i]]++] = i;
   free(pos);
   /* Random-number groups: inside each colour class, taken in ascending id
-   * order, consecutive runs of four vertices share one Philox block.  The
-   * block's counter names the first vertex of the run (the leader); the
-   * i-th vertex of the run uses output word i. */
+   * order, consecutive runs of four vertices share one Philox block (the
+   * last run of a class may be shorter).  Runs are numbered in class order,
+   * then in id order within a class; the block's counter names the run by
+   * that ordinal, and the i-th vertex of the run uses output word i. */
+  int32_t runs_before = 0;
   for (int32_t c = 0; c < C; ++c) {
     for (int32_t idx = G->class_start[c]; idx < G->class_start[c + 1]; ++idx) {
       int32_t local = idx - G->class_start[c];
       int32_t vtx = G->members[idx];
       G->rank[vtx] = local % 4;
-      G->leader[vtx] = G->members[idx - local % 4];
+      G->run[vtx] = runs_before + local / 4;
     }
+    runs_before += (G->class_start[c + 1] - G->class_start[c] + 3) / 4;
   }
   return 0;
 }
 
 /* u32 random number for (vertex, sweep, replica, purpose): word rank(v) of
- * Philox4x32-10 with key = seed and counter = (t, leader(v), r, tag). */
+ * Philox4x32-10 with key = seed and counter = (t, run(v), r, tag). */
 static uint32_t draw(const or_graph* G, uint64_t seed, int32_t v, uint32_t t,
                      uint32_t r, uint32_t tag) {
-  uint32_t ctr[4] = {t, (uint32_t)G->leader[v], r, tag};
+  uint32_t ctr[4] = {t, (uint32_t)G->run[v], r, tag};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t out[4];
   oracle_philox4x32_10(ctr, key, out);
@@ -397,10 +400,10 @@ static void run_replica(worker_arg* A, int32_t r, int8_t* s, int64_t* h,
           uint32_t u = draw(G, run->seed, i, (uint32_t)t, (uint32_t)r, 0);
           accept = (uint64_t)u < tq[k];
           /* bookkeeping only: one Philox block serves a whole group, so
-           * count each (leader, sweep) once; a draw whose threshold is
+           * count each (run, sweep) once; a draw whose threshold is
            * 0 or 2^32 decides nothing and is not counted */
-          if (tq[k] != 0 && tq[k] != ((uint64_t)1 << 32) && drawn_at[G->leader[i]] != t) {
-            drawn_at[G->leader[i]] = t;
+          if (tq[k] != 0 && tq[k] != ((uint64_t)1 << 32) && drawn_at[G->run[i]] != t) {
+            drawn_at[G->run[i]] = t;
             ++draws;
           }
         }

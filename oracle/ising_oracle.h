@@ -60,7 +60,7 @@ typedef struct { /* per-replica arrays are indexed by r - r_begin */
   int64_t* energy_trace; /* [nr][n_sweeps] or NULL: E after every sweep */
   int64_t check_failures;/* sweeps where maintained h/E != recomputed */
   int64_t* draws;        /* [nr] or NULL: distinct Philox blocks the sweeps
-                            needed, i.e. (t, leader, r) with a draw */
+                            needed, i.e. (t, run, r) with a draw */
   int64_t* improvements; /* [nr] or NULL: sweeps that raised the best cut */
 } or_run_out;
 
