@@ -18,9 +18,9 @@
  * the updates of one class are independent), each with
  *     k = s_i h_i,  h_i = -sum_j w_ij s_j   (flipping s_i changes E by 2k)
  *     accept iff k <= 0 or u < Tq(beta_t, k),  Tq = floor(2^32 exp(-2 k beta_t))
- * where u is word j of Philox4x32-10(key = seed, counter = (t, leader, r,
- * 0)), j being the vertex's rank in its group -- see ising_create for the
- * leader/word assignment.  The best cut of a
+ * where u is word j of Philox4x32-10(key = seed, counter = (t, run, r, 0)),
+ * j being the vertex's rank in its run -- see ising_create for the runs
+ * and their numbering.  The best cut of a
  * replica is taken over its initial state and its end-of-sweep states
  * (strict improvement, earliest sweep wins).  Every step is integer
  * arithmetic on the device, so results are bit-identical across kernel
@@ -77,8 +77,10 @@ typedef struct ising_problem ising_problem;
  *            checkerboard).  Otherwise colour[i] in [0, 1024) per vertex; it
  *            must be proper.  Classes are swept in colour order 0, 1, ...
  * Random-number runs: inside each colour class, in ascending vertex id,
- * consecutive runs of four vertices share one Philox block; the first
- * vertex of a run is its leader and the i-th vertex uses output word i.
+ * consecutive runs of four vertices share one Philox block (a class's last
+ * run may be shorter).  Runs are numbered 0, 1, ... in class order, then in
+ * id order within a class; counter word 1 is that number and the i-th
+ * vertex of a run uses output word i.
  * Errors (ISING_ERR_INVALID): n out of range; m < 0; NULL arrays with
  * m > 0; an id out of range; a self loop; a repeated undirected edge;
  * w == 0 or |w| > 32768; 2 * sum_e |w_e| >= 2^30; an improper or
@@ -172,7 +174,8 @@ typedef struct {
  * call starts afresh.  `tuning` NULL = ISING_PATH_AUTO.
  * Errors: ISING_ERR_INVALID (bad schedule, R < 1, tuning out of range, a
  * threshold table over 2^26 entries); ISING_ERR_UNSUPPORTED (MSC on
- * non-unit weights, or a problem too large for the requested LDS path);
+ * non-unit weights, FIELD with more than 64 colour classes, or a problem
+ * too large for the requested LDS path);
  * ISING_ERR_NOMEM; ISING_ERR_DEVICE.
  */
 int ising_anneal(ising_problem* p, const ising_schedule* s, int32_t n_replicas,

@@ -153,7 +153,7 @@ static int row_chunk(const Table& t) {
 }
 
 // LDS of one unit: state words, a chunk of threshold rows, the class
-// bounds and the group descriptors (leader word, adjacency base, packed
+// bounds and the group descriptors (group word, adjacency base, packed
 // degrees).  The multispin kernel needs less (two rows, no class bounds).
 
 static size_t persistent_lds(const HostGraph& g, const Table& t, const PersistentConfig& c) {
@@ -274,6 +274,10 @@ int check_config(const HostGraph& g, const Table& t, int R, const PersistentConf
   }
   if ((c.adj == 1 || c.adj == 3) && !form_in_lds(staged_form(g, t, c))) {
     set_error("the adjacency cannot be staged in LDS for this problem");
+    return ISING_ERR_UNSUPPORTED;
+  }
+  if (c.path == ISING_PATH_FIELD && g.C > kMaxFieldColours) {
+    set_error("the field path supports at most %d colour classes", kMaxFieldColours);
     return ISING_ERR_UNSUPPORTED;
   }
   if (c.path == ISING_PATH_MSC) {

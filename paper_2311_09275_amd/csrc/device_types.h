@@ -24,7 +24,7 @@ constexpr int32_t kAcceptAll = -1;
 // Degree-4 group block, 12 words (48 bytes): words 0..7 hold the 16-bit LDS
 // word indices of the 16 neighbour entries (slot j's four at 16-bit index
 // 4j..4j+3, in label order: entry e of v is the neighbour u whose entry
-// e XOR 1 is v), word 8 the leader id, word 9 bit 4j+e set when entry e of
+// e XOR 1 is v), word 8 the group's first vertex, word 9 bit 4j+e set when entry e of
 // slot j has w > 0; words 10 and 11 are zero.
 constexpr int kDeg4BlockWords = 12;
 
@@ -56,6 +56,7 @@ constexpr int tile_word(int g, int j) { return ((g >> 6) << 8) + (j << 6) + (g &
 constexpr int32_t kPadWord = 0x7FFFFFFF;
 
 constexpr int kMaxReplicasPerBlock = 16;   // FIELD path
+constexpr int kMaxFieldColours = 64;       // FIELD path: colour classes
 constexpr int kMaxWordsPerBlock = 4;       // MSC path
 constexpr int kMaxThresholdRow = 1024;     // LDS paths stage <= this many
 constexpr int kMaxLdsDegree = 255;         // LDS paths pack degrees in 8 bits

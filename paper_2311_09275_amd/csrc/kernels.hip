@@ -10,8 +10,8 @@
 // over end-of-sweep states (strict improvement).
 //
 // Random numbers: word j of Philox4x32-10 with key = seed and counter =
-// (t, leader, r, tag) serves the j-th vertex of a group -- four consecutive
-// same-colour vertices.  One block call therefore feeds four attempts of one
+// (t, g, r, tag) serves the j-th vertex of group g -- four consecutive
+// same-colour vertices, groups numbered in class order.  One block call therefore feeds four attempts of one
 // replica, which lets a single replica be a unit of parallel work.
 //
 // Three kernel families compute identical results:
@@ -66,14 +66,16 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
   return make_uint4(c0, c1, c2, c3);
 }
 
-// The block of a four-vertex group: counter (sweep, leader id, replica,
-// tag), key (seed low, seed high); the group's j-th vertex uses word j.
-// Sweep, replica and tag are the same for a whole wave, so with the leader
-// in word 1 the first round's products and one product of each of the next
-// two rounds do not depend on the lane.
-__device__ __forceinline__ uint4 group_block(uint32_t leader, uint32_t t, uint32_t r,
+// The block of a four-vertex group: counter (sweep, group ordinal,
+// replica, tag), key (seed low, seed high); the group's j-th vertex uses
+// word j.  The ordinal counts runs of four same-colour vertices in class
+// order, which is the group's index in the position layout.  Sweep,
+// replica and tag are the same for a whole wave, so with the group in word
+// 1 the first round's products and one product of each of the next two
+// rounds do not depend on the lane.
+__device__ __forceinline__ uint4 group_block(uint32_t group, uint32_t t, uint32_t r,
                                              uint32_t tag, uint32_t k0, uint32_t k1) {
-  return philox10(t, leader, r, tag, k0, k1);
+  return philox10(t, group, r, tag, k0, k1);
 }
 
 // Pointers fetched from a descriptor are generic; re-qualifying them as
@@ -146,7 +148,7 @@ __global__ void k_plain_init(PlainDev P) {
     for (int j = 0; j < cnt; ++j)
       bits |= (P.init_spins[(int64_t)r * P.n_pad + 4 * g + j] > 0 ? 1u : 0u) << j;
   } else {
-    const uint4 x = group_block(gw & kGroupLeaderMask, 0, r, kTagInit, P.seed_lo, P.seed_hi);
+    const uint4 x = group_block((uint32_t)g, 0, r, kTagInit, P.seed_lo, P.seed_hi);
     bits = (x.x >> 31) | ((x.y >> 31) << 1) | ((x.z >> 31) << 2) | ((x.w >> 31) << 3);
   }
   for (int j = 0; j < 4; ++j)
@@ -201,7 +203,7 @@ __global__ void k_plain_sweep(PlainDev P, int t, int g0, int g1) {
     }
   }
   uint4 x = make_uint4(0, 0, 0, 0);
-  if (need) x = group_block(gw & kGroupLeaderMask, t, r, kTagSweep, P.seed_lo, P.seed_hi);
+  if (need) x = group_block((uint32_t)g, t, r, kTagSweep, P.seed_lo, P.seed_hi);
   int dE = 0, nacc = 0;
   for (int j = 0; j < cnt; ++j) {
     if (k[j] <= 0 || accept_pos(k[j], len, pick(x, j), row)) {
@@ -249,8 +251,8 @@ __global__ void k_plain_flush(PlainDev P, int last) {
 // own is empty.  Unit processing is entirely workgroup-local.
 //
 // LDS of a unit: the state words of its G replicas, two threshold rows
-// (current and next sweep), and the group descriptors: leader word,
-// adjacency base and four 8-bit slot degrees per group.
+// (current and next sweep), and the group descriptors: group word (first
+// vertex and slot count), adjacency base and four 8-bit slot degrees.
 
 struct FieldShared {
   int32_t unit;
@@ -529,7 +531,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           for (int j = 0; j < cnt; ++j)
             bits |= (J.init_spins[(int64_t)r * n_pad + 4 * g + j] > 0 ? 1u : 0u) << j;
         } else {
-          const uint4 x = group_block(gw & kGroupLeaderMask, 0, r, kTagInit, k0, k1);
+          const uint4 x = group_block((uint32_t)g, 0, r, kTagInit, k0, k1);
           bits = (x.x >> 31) | ((x.y >> 31) << 1) | ((x.z >> 31) << 2) | ((x.w >> 31) << 3);
         }
         w4.x = (int)(bits & 1u);
@@ -666,30 +668,36 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   int dk = 0;
   int nacc = 0;       // accepted flips of this wave (wave-uniform)
   int nacc_mark = 0;  // nacc at the start of the sweep
-  // class bounds of the next pass, read one pass ahead
-  int nb0 = U.cls[0], nb1 = U.cls[1];
+  // Class bounds (at most kMaxFieldColours classes): lane i of two
+  // registers keeps words i and 64 + i, and a pass takes its bounds with
+  // lane reads, so no LDS wait sits at the start of a pass.
+  const int cls_a = (tid & 63) < 2 * C ? U.cls[tid & 63] : 0;
+  const int cls_b = 64 + (tid & 63) < 2 * C ? U.cls[64 + (tid & 63)] : 0;
+  auto bound = [&](int i) {
+    const int a = __builtin_amdgcn_readlane(cls_a, i & 63), b = __builtin_amdgcn_readlane(cls_b, i & 63);
+    return i < 64 ? a : b;
+  };
   // Rows come in chunks of CH sweeps, one HBM copy and barrier per chunk,
   // so that the passes themselves issue no HBM loads: a wait for one would
   // also wait for the snapshot stores still in flight.
   int tc = 0;  // sweep within the staged chunk
+  // The row's bound: twice the largest acceptable k (key rows), or the
+  // largest acceptable bond count plus one (degree-4 rows).  The next
+  // sweep's is read during the last pass, so no LDS read is pending when a
+  // sweep starts.
+  int len2_next = (int)U.tq[RW - 1];
   for (int t = J.t_begin; t < J.t_end; ++t) {
     if (tc == CH) {
       stage_row_chunk(rows, t, min(CH, J.t_end - t), U.tq, RW);
       tc = 0;
       __syncthreads();
+      len2_next = (int)U.tq[RW - 1];
     }
     const uint32_t* row = U.tq + tc * RW;
-    // the row's bound: twice the largest acceptable k (key rows), or the
-    // largest acceptable bond count plus one (degree-4 rows)
-    const int len2 = (int)row[RW - 1];
+    const int len2 = len2_next;
     ++tc;
     for (int c = 0; c < C; ++c) {
-      const int g0 = nb0, g1 = nb1;
-      {
-        const int cn = c + 1 < C ? c + 1 : 0;
-        nb0 = U.cls[2 * cn];
-        nb1 = U.cls[2 * cn + 1];
-      }
+      const int g0 = bound(2 * c), g1 = bound(2 * c + 1);
       if (live) {
         for (int gi = g0 + lt; gi < g1; gi += TPR) {
           // Addresses are formed from the group index in each iteration:
@@ -710,26 +718,21 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           } else {
             w4 = *reinterpret_cast<const int4*>(st + 4 * g);
           }
-          // degree-4 form: the group's entries are fetched with its state,
-          // so their latency is covered by the Philox block
-          uint4 a01 = make_uint4(0u, 0u, 0u, 0u), a23 = a01, lnb = a01;
+          // degree-4 forms: the group's neighbour entries are fetched with
+          // its state
+          uint4 a01 = make_uint4(0u, 0u, 0u, 0u), a23 = a01;
           if (ADJ == kAdjLdsDeg4) {
             typedef __attribute__((address_space(3))) const u32x4 lds_u32x4;
             lds_u32x4* blk = (lds_u32x4*)(uintptr_t)(blk_base + __umul24((uint32_t)g, 48u));
-            const u32x4 b0 = blk[0], b1 = blk[1], b2 = blk[2];
+            const u32x4 b0 = blk[0], b1 = blk[1];
             a01 = make_uint4(b0.x, b0.y, b0.z, b0.w);
             a23 = make_uint4(b1.x, b1.y, b1.z, b1.w);
-            lnb = make_uint4(b2.x, b2.y, b2.z, b2.w);
           } else if (ADJ == kAdjHbmDeg4) {
             const GLOBAL_AS u32x4* blk = gconst(reinterpret_cast<const u32x4*>(J.adj4)) + 3 * g;
-            const u32x4 b0 = blk[0], b1 = blk[1], b2 = blk[2];
+            const u32x4 b0 = blk[0], b1 = blk[1];
             a01 = make_uint4(b0.x, b0.y, b0.z, b0.w);
             a23 = make_uint4(b1.x, b1.y, b1.z, b1.w);
-            lnb = make_uint4(b2.x, b2.y, b2.z, b2.w);
-          } else {
-            lnb.x = (uint32_t)(U.gword[g] & kGroupLeaderMask);
           }
-          const uint32_t leader = lnb.x;
           // all of the group's reads go out before any arithmetic
           __builtin_amdgcn_sched_barrier(0);
           int w[4] = {w4.x, w4.y, w4.z, w4.w};
@@ -742,12 +745,10 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             *reinterpret_cast<GLOBAL_AS uint32_t*>(best + 4 * g) = spins_to_bytes(bits);
           };
           if (!SOA && snap) snapshot();
-          // Nearly every group needs its Philox block, so it is drawn
-          // unconditionally.  The four threshold reads are issued first so
-          // that the block's arithmetic covers their latency.  Row entry 0
-          // accepts k <= 0 and k above the row's length is refused by the
-          // length test (padding slots have the key 2^31 - 2), so each
-          // slot's test is two comparisons.
+          // Row entry 0 accepts k <= 0 and k above the row's length is
+          // refused by the length test (padding slots have the key
+          // 2^31 - 2, or a bond count above every bound), so each slot's
+          // test is two comparisons.
           // k: the bond count plus one (degree-4 forms, rows indexed by
           // it directly) or field_key; m = -(spin bit)
           int k[4], m[4];
@@ -761,9 +762,11 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           }
 #pragma unroll
           for (int j = 0; j < 4; ++j) thr[j] = row[SOA ? k[j] : clamp_row_index(k[j], kw2)];
-          // keep the reads ahead of the Philox arithmetic
+          // Nearly every group needs its Philox block, so it is drawn
+          // unconditionally, after the threshold reads are issued: its
+          // arithmetic covers their latency.
           __builtin_amdgcn_sched_barrier(0);
-          const uint4 x = group_block(leader, t, r, kTagSweep, k0, k1);
+          const uint4 x = group_block((uint32_t)g, t, r, kTagSweep, k0, k1);
           bool acc[4];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
@@ -813,6 +816,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
         if ((tid & 63) == 0 && s != 0) atomicAdd(&sh.eacc[t % 3][rl], s);
         dk = 0;
         nacc_mark = nacc;
+        if (tc < CH) len2_next = (int)U.tq[tc * RW + RW - 1];
       }
       __syncthreads();
     }
@@ -1017,7 +1021,7 @@ __device__ void msc_unit(const JobDev& J, const int block, uint32_t* smem, MscSh
         } else {
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
-            const uint4 x = group_block(gw & kGroupLeaderMask, 0, rb + i, kTagInit, k0, k1);
+            const uint4 x = group_block((uint32_t)g, 0, rb + i, kTagInit, k0, k1);
             b[0] |= (x.x >> 31) << (8 * o + i);
             b[1] |= (x.y >> 31) << (8 * o + i);
             b[2] |= (x.z >> 31) << (8 * o + i);
@@ -1115,7 +1119,7 @@ __device__ void msc_unit(const JobDev& J, const int block, uint32_t* smem, MscSh
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
             uint4 x = make_uint4(0, 0, 0, 0);
-            if (draw_needed) x = group_block(gw & kGroupLeaderMask, t, rb + i, kTagSweep, k0, k1);
+            if (draw_needed) x = group_block((uint32_t)g, t, rb + i, kTagSweep, k0, k1);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               if (j < cnt) {
