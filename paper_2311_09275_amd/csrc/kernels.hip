@@ -777,15 +777,16 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           }
           if (ADJ == kAdjLdsDeg4 || ADJ == kAdjHbmDeg4) {
             // Within a pass only the owning lane touches a group's own
-            // words and neighbours only toggle bond bits (they are in other
-            // classes), so a flip is an LDS XOR of the spin pair and the
-            // four bond bits, and each push an LDS XOR of one bond bit.
+            // words (neighbours are in other classes and do not flip), so
+            // a flip is a plain LDS store of the word with its spin pair
+            // and four bond bits inverted; each push is an LDS XOR of one
+            // bond bit of a neighbour's word, which several flips of the
+            // pass may change.
             const uint32_t e[8] = {a01.x, a01.y, a01.z, a01.w, a23.x, a23.y, a23.z, a23.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               if (acc[j]) {
-                __hip_atomic_fetch_xor(s0 + 64 * j, kBondFlipMask, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                s0[64 * j] = w[j] ^ kBondFlipMask;
                 dk += k[j];
                 push_bond_slot(st_base, e[2 * j], e[2 * j + 1]);
               }
