@@ -37,6 +37,32 @@ const char* last_error() { return g_err; }
 // then 2-regular and bipartite, a union of even cycles; taking their edges
 // alternately gives two perfect matchings f = 0, 1, and an edge v -> u of
 // matching f is labelled 2f at v and 2f + 1 at u.  False if a check fails.
+// First choice: the caller's edge order, when it already is such a
+// labelling -- edge e oriented u[e] -> v[e], in matching f = the rank of e
+// among u[e]'s edges of that orientation.  A torus listed as (v, right),
+// (v, down) gives the same labels to the same directions everywhere
+// (right, left, down, up), so the pushes of one instruction land on
+// neighbours at one offset, in distinct LDS banks.
+static bool edge_order_labels(int32_t n, int64_t m, const int32_t* u, const int32_t* v,
+                              std::vector<int32_t>& lab) {
+  std::vector<int> n_out((size_t)n, 0), n_in((size_t)n, 0);
+  lab.assign((size_t)4 * n, -1);
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t a = u[e], b = v[e];
+    const int f = n_out[(size_t)a]++;
+    if (f > 1 || n_in[(size_t)b]++ > 1) return false;
+    if (lab[4 * (size_t)b + 2 * f + 1] >= 0) return false;  // two in-edges of one matching
+    lab[4 * (size_t)a + 2 * f] = b;
+    lab[4 * (size_t)b + 2 * f + 1] = a;
+  }
+  for (int32_t a = 0; a < n; ++a)
+    for (int e = 0; e < 4; ++e) {
+      const int32_t b = lab[4 * (size_t)a + e];
+      if (b < 0 || lab[4 * (size_t)b + (e ^ 1)] != a) return false;
+    }
+  return true;
+}
+
 static bool bond_labels(int32_t n, const std::vector<int32_t>& deg, const std::vector<int32_t>& nb,
                         std::vector<int32_t>& lab) {
   const size_t H = (size_t)deg[(size_t)n];  // half-edges
@@ -293,7 +319,8 @@ int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, cons
   g.deg4 = n > 0;
   for (int32_t i = 0; i < n && g.deg4; ++i) g.deg4 = deg[(size_t)i + 1] - deg[(size_t)i] == 4;
   std::vector<int32_t> lab;
-  if (g.deg4 && g.unit && field_state_words(g.n_pad) <= (1 << 16) && bond_labels(n, deg, nb, lab)) {
+  if (g.deg4 && g.unit && field_state_words(g.n_pad) <= (1 << 16) &&
+      (edge_order_labels(n, m, u, v, lab) || bond_labels(n, deg, nb, lab))) {
     const size_t ng = (size_t)g.n_pad / 4;
     g.adj4.assign((size_t)kDeg4BlockWords * ng, 0u);
     for (size_t q = 0; q < ng; ++q) {
