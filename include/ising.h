@@ -108,6 +108,16 @@ typedef struct {
 int ising_problem_info(const ising_problem* p, ising_info* out);
 /* The colour of every vertex, original order (host-only).  [n] */
 int ising_colouring(const ising_problem* p, int32_t* colour);
+/* Edge labels of the degree-4 form (host-only).  For a problem with unit
+ * weights, every vertex of degree 4 and a padded state of at most 2^16
+ * words (about 65,000 vertices), lab[4 v + e] is v's neighbour with label e, in
+ * original ids, such that lab[4 u + (e XOR 1)] == v whenever
+ * lab[4 v + e] == u: each edge carries labels 2f and 2f + 1 at its two
+ * ends.  The FIELD kernel's degree-4 forms push a flip of v into bit
+ * e XOR 1 of neighbour e's bond word, so every push of one label is an
+ * XOR of one fixed bit.  [4n], caller-owned.  ISING_ERR_UNSUPPORTED when
+ * the problem has no degree-4 form. */
+int ising_neighbour_labels(const ising_problem* p, int32_t* lab);
 /* MaxCut value of a +-1 assignment in original order (host-only). */
 int ising_eval_cut(const ising_problem* p, const int8_t* spins, int64_t* cut);
 

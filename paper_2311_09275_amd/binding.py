@@ -86,6 +86,7 @@ _sig = {
     "ising_destroy": ([P], C.c_int),
     "ising_problem_info": ([P, C.POINTER(Info)], C.c_int),
     "ising_colouring": ([P, P], C.c_int),
+    "ising_neighbour_labels": ([P, P], C.c_int),
     "ising_eval_cut": ([P, P, C.POINTER(C.c_int64)], C.c_int),
     "ising_threshold_table": ([C.POINTER(Schedule), C.c_int32, P], C.c_int),
     "ising_anneal": ([P, C.POINTER(Schedule), C.c_int32, C.c_uint64, P], C.c_int),
@@ -162,6 +163,12 @@ def ising_problem_info(h) -> Info:
 def ising_colouring(h, n) -> np.ndarray:
     out = np.zeros(n, np.int32)
     _check(_L.ising_colouring(h, _ptr(out)), "ising_colouring")
+    return out
+
+
+def ising_neighbour_labels(h, n) -> np.ndarray:
+    out = np.zeros(4 * n, np.int32)
+    _check(_L.ising_neighbour_labels(h, _ptr(out)), "ising_neighbour_labels")
     return out
 
 
@@ -367,6 +374,9 @@ class Problem:
 
     def colouring(self) -> np.ndarray:
         return ising_colouring(self.handle, self.n)
+
+    def neighbour_labels(self) -> np.ndarray:
+        return ising_neighbour_labels(self.handle, self.n)
 
     def anneal(self, sched: Schedule, n_replicas: int, seed: int, tuning: Tuning | None = None,
                stream=None) -> None:

@@ -762,6 +762,16 @@ int ising_colouring(const ising_problem* p, int32_t* colour) {
   return ISING_OK;
 }
 
+int ising_neighbour_labels(const ising_problem* p, int32_t* lab) {
+  if (!p || !lab) return ISING_ERR_INVALID;
+  if (p->g.lab4.empty()) {
+    set_error("the problem has no degree-4 form");
+    return ISING_ERR_UNSUPPORTED;
+  }
+  memcpy(lab, p->g.lab4.data(), sizeof(int32_t) * p->g.lab4.size());
+  return ISING_OK;
+}
+
 int ising_eval_cut(const ising_problem* p, const int8_t* spins, int64_t* cut) {
   if (!p || !spins || !cut) return ISING_ERR_INVALID;
   int64_t c = 0;

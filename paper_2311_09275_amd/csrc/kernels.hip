@@ -267,10 +267,8 @@ struct UnitLds {
   int32_t* gbase;   // [n_grp]
   uint32_t* gdeg;   // [n_grp]
   uint16_t* adj16;  // staged adjacency.  CSR form: [2m] entries
-                    // (position << 1) | (w > 0).  Degree-4 form: [16 n_grp]
-                    // positions, slot j of group g at 16 g + 4 j, then
-                    // (degree-4 form: [n_grp] 48-byte group blocks, see
-                    // kDeg4BlockWords)
+                    // (position << 1) | (w > 0).  Degree-4 form: [n_grp]
+                    // 48-byte group blocks (kDeg4BlockWords)
   uint32_t* flips;  // [BLOCK/64][256] per-wave lists of flipped vertices (CSR form)
 };
 

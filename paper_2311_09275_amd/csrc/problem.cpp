@@ -321,6 +321,7 @@ int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, cons
   std::vector<int32_t> lab;
   if (g.deg4 && g.unit && field_state_words(g.n_pad) <= (1 << 16) &&
       (edge_order_labels(n, m, u, v, lab) || bond_labels(n, deg, nb, lab))) {
+    g.lab4 = lab;
     const size_t ng = (size_t)g.n_pad / 4;
     g.adj4.assign((size_t)kDeg4BlockWords * ng, 0u);
     for (size_t q = 0; q < ng; ++q) {

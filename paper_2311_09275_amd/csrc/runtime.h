@@ -103,6 +103,7 @@ struct HostGraph {
   // of the FIELD kernel (kDeg4BlockWords), neighbour entries as 16-bit word
   // indices of the tiled state layout (tile_word)
   std::vector<uint32_t> adj4;
+  std::vector<int32_t> lab4;  // [4n] neighbours in label order, with adj4
 };
 
 int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, const int32_t* w,

@@ -103,6 +103,36 @@ def random_graph(n: int, m: int, seed: int, weight: int = 1) -> Instance:
                     np.asarray(vs, np.int32), w)
 
 
+def random_regular4(n: int, seed: int, weights: str = "pm1") -> Instance:
+    """Simple random 4-regular graph on n >= 5 vertices, +-1 (or all +1)
+    weights.  Pairing model: the 4n vertex stubs are shuffled and paired;
+    a pairing with a self loop or a repeated pair is drawn again.  Edges
+    are listed as (min, max) in ascending order, so the listing itself is
+    in general no orientation with two out-edges per vertex."""
+    if n < 5:
+        raise ValueError("a simple 4-regular graph needs n >= 5")
+    rng = _rng(seed)
+    stubs = np.repeat(np.arange(n, dtype=np.int64), 4)
+    for _ in range(10000):
+        rng.shuffle(stubs)
+        a, b = stubs[0::2], stubs[1::2]
+        lo, hi = np.minimum(a, b), np.maximum(a, b)
+        if np.any(lo == hi):
+            continue
+        key = lo * n + hi
+        if np.unique(key).size != key.size:
+            continue
+        order = np.argsort(key)
+        lo, hi = lo[order], hi[order]
+        if weights == "pm1":
+            w = rng.integers(0, 2, size=lo.size, dtype=np.int64) * 2 - 1
+        else:
+            w = np.ones(lo.size, dtype=np.int64)
+        return Instance(f"regular4_{n}_s{seed}", n, lo.astype(np.int32), hi.astype(np.int32),
+                        w.astype(np.int32))
+    raise RuntimeError("no simple pairing found")
+
+
 def random_weighted(n: int, m: int, seed: int, wmax: int) -> Instance:
     """Random graph with nonzero integer weights uniform in [-wmax, wmax]."""
     base = random_graph(n, m, seed)

@@ -142,3 +142,57 @@ def test_initial_state_validation():
     p.set_initial_state(np.ones((2, 16), np.int8), 2)
     p.set_initial_state(None, 0)
     p.close()
+
+
+LABEL_GRAPHS = {
+    "torus3x3": lambda: I.torus(3, 3, 1),
+    "torus7x9": lambda: I.torus(7, 9, 5),
+    "c2": lambda: I.workload_c2(),
+    "regular4_5": lambda: I.random_regular4(5, 1),
+    "regular4_101": lambda: I.random_regular4(101, 2),
+    "regular4_5000": lambda: I.random_regular4(5000, 3),
+    "two_k5": lambda: I.Instance("two_k5", 10,
+                                 np.array([5 * c + a for c in range(2) for a in range(5) for b in range(a + 1, 5)], np.int32),
+                                 np.array([5 * c + b for c in range(2) for a in range(5) for b in range(a + 1, 5)], np.int32),
+                                 np.ones(20, np.int32)),
+}
+
+
+@pytest.mark.parametrize("name", list(LABEL_GRAPHS))
+def test_degree4_labels_pair_up(name):
+    """Every edge carries labels 2f and 2f+1 at its two ends: the degree-4
+    form's pushes rely on it (a flip of v toggles bit e XOR 1 of the
+    neighbour with label e).  Tori keep their listed orientation; random
+    graphs go through the closed-walk construction."""
+    inst = LABEL_GRAPHS[name]()
+    if inst.name.startswith("torus"):
+        inst = I.Instance(inst.name, inst.n, inst.u, inst.v, np.ones_like(inst.w))
+    p = B.Problem.from_instance(inst)
+    lab = p.neighbour_labels().reshape(inst.n, 4)
+    nbrs = [set() for _ in range(inst.n)]
+    for a, b in zip(inst.u.tolist(), inst.v.tolist()):
+        nbrs[a].add(b)
+        nbrs[b].add(a)
+    for v in range(inst.n):
+        assert set(lab[v].tolist()) == nbrs[v]
+        for e in range(4):
+            assert lab[lab[v, e], e ^ 1] == v
+    if inst.name.startswith("torus"):
+        x = np.arange(inst.n) % int(inst.name[5:].split("x")[0])
+        lx = int(inst.name[5:].split("x")[0])
+        right = (np.arange(inst.n) // lx) * lx + (x + 1) % lx
+        np.testing.assert_array_equal(lab[:, 0], right)
+
+
+def test_degree4_labels_need_degree4_unit_weights():
+    for inst in (I.workload_c3(), I.torus(5, 5, 1, weights="pm1"),
+                 I.Instance("w2", 5, I.random_regular4(5, 1).u, I.random_regular4(5, 1).v,
+                            np.full(10, 2, np.int32))):
+        p = B.Problem.from_instance(inst)
+        if inst.name.startswith("torus"):
+            lab = p.neighbour_labels()  # +-1 weights are unit weights
+            assert lab.shape == (4 * inst.n,)
+            continue
+        with pytest.raises(B.IsingError) as e:
+            p.neighbour_labels()
+        assert e.value.status == B.ERR_UNSUPPORTED

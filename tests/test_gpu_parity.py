@@ -118,6 +118,14 @@ def test_degree4_non_bipartite(path):
             tuning=PATHS[path])
 
 
+@pytest.mark.parametrize("path", list(PATHS))
+def test_degree4_random_regular(path):
+    """Random 4-regular graph listed as sorted (min, max) pairs: its degree-4
+    labels come from the closed-walk construction, not the listing."""
+    compare(I.random_regular4(403, 21), 130, 20, 13, kind=O.GEOMETRIC, b0=0.1, b1=3.0,
+            tuning=PATHS[path])
+
+
 @pytest.mark.parametrize("path", ["plain", "field_g1_b256_hbmadj", "field_g4_b256_hbmadj",
                                   "field_g1_b512_auto"])
 def test_weighted_graph(path):
