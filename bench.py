@@ -91,6 +91,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-torus batch leg")
+    ap.add_argument("--no-random", action="store_true", help="skip the sparse random graph leg")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests of the Poisson serving leg (0 = skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
@@ -216,6 +217,59 @@ def main():
         for p in probs:
             p.close()
 
+    # ------------------------------------------------------------ random graph leg
+    # The sparse random graph (N = 10,000, M = 9,999, 1024 replicas, 4000
+    # sweeps linear 0.05 -> 3.0) under the library's automatic configuration,
+    # the plain form on the same seeds, and time to target against a longer
+    # reference anneal.
+    random_leg = None
+    if not args.no_random:
+        inst3 = I.workload_c3()
+        R3, S3, SEED3 = 1024, 4000, 1003
+        sched3 = B.Schedule.make(B.LINEAR, S3, 0.05, 3.0)
+        p3 = B.Problem.from_instance(inst3)
+        auto = B.Tuning(B.PATH_AUTO, 0, 0, 0)
+        p3.anneal(sched3, R3, SEED3, auto, stream=stream)
+        p3.cut()
+        walls3 = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            p3.anneal(sched3, R3, SEED3, auto, stream=stream)
+            res3 = p3.cut()
+            walls3.append(time.perf_counter() - t)
+        path3 = B.ising_last_run_info(p3.handle)[2]
+        kern3 = p3.last_anneal_ms()
+        per3 = res3.per_replica.copy()
+        t = time.perf_counter()
+        p3.anneal(sched3, R3, SEED3, B.Tuning(B.PATH_PLAIN, 1, 256, 0), stream=stream)
+        res3p = p3.cut()
+        plain3_s = time.perf_counter() - t
+        assert np.array_equal(res3p.per_replica, per3), "plain and automatic forms disagree"
+        ms3 = float(np.mean(walls3)) * 1e3
+        att3 = inst3.n * R3 * S3
+        random_leg = {"workload": "sparse random graph N=10000 M=9999 w=1, 1024 replicas, "
+                                  "4000 sweeps linear 0.05->3.0",
+                      "attempts_per_s": att3 / (ms3 / 1e3), "ms_per_anneal": ms3,
+                      "plain_ms": plain3_s * 1e3, "speedup_vs_plain": plain3_s * 1e3 / ms3,
+                      "kernel_ms": kern3, "best_cut": int(res3.best_cut),
+                      "path": {1: "plain", 2: "field", 3: "msc"}.get(path3, str(path3)),
+                      "tuning": "automatic"}
+        if not args.no_ttt:
+            ref3 = B.Problem.from_instance(inst3)
+            ref3.anneal(B.Schedule.make(B.LINEAR, 5 * S3, 0.05, 3.0), R3, 7, auto, stream=stream)
+            c_ref3 = ref3.cut().best_cut
+            ref3.close()
+            random_leg["reference_best_cut"] = int(c_ref3)
+            random_leg["ttt"] = {}
+            for q in (0.995, 0.998, 1.0):
+                target = ttt.target_cut(c_ref3, q)
+                tf = ttt.replica_ttt(per3, target, ms3 / 1e3, S3)
+                random_leg["ttt"][str(q)] = {
+                    "target": target, "ps": tf["ps"], "ttt_persistent_s": tf["ttt_s"],
+                    "ttt_plain_s": ttt.replica_ttt(per3, target, plain3_s, S3)["ttt_s"]}
+        p3.close()
+
     # ------------------------------------------------------------ serving leg
     serving = None
     if args.serve_requests > 0:
@@ -284,6 +338,7 @@ def main():
         "reference_best_cut": c_ref,
         "ttt": ttt_rows,
         "batch": batch,
+        "random_graph": random_leg,
         "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
