@@ -580,28 +580,26 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
           *wp = kBondPadWord;
           continue;
         }
-        uint32_t blk[12];
+        // the slot's two entry words and the weight-sign word of the block
+        uint32_t lo, hi, signs;
         if (ADJ == kAdjLdsDeg4) {
-          const uint4* b = reinterpret_cast<const uint4*>(U.adj16) + 3 * g;
-          *reinterpret_cast<uint4*>(blk) = b[0];
-          *reinterpret_cast<uint4*>(blk + 4) = b[1];
-          *reinterpret_cast<uint4*>(blk + 8) = b[2];
+          const uint32_t* b = reinterpret_cast<const uint32_t*>(U.adj16) + kDeg4BlockWords * g;
+          lo = b[2 * j];
+          hi = b[2 * j + 1];
+          signs = b[9];
         } else {
-          const GLOBAL_AS u32x4* b = gconst(reinterpret_cast<const u32x4*>(J.adj4)) + 3 * g;
-          for (int i = 0; i < 3; ++i) {
-            const u32x4 x = b[i];
-            blk[4 * i] = x.x;
-            blk[4 * i + 1] = x.y;
-            blk[4 * i + 2] = x.z;
-            blk[4 * i + 3] = x.w;
-          }
+          const GLOBAL_AS uint32_t* b =
+              gconst(reinterpret_cast<const uint32_t*>(J.adj4)) + kDeg4BlockWords * (int64_t)g;
+          lo = b[2 * j];
+          hi = b[2 * j + 1];
+          signs = b[9];
         }
         const uint32_t bv = (uint32_t)*wp & 1u;
         uint32_t word = bv | ((bv ^ 1u) << 1);
         for (int e = 0; e < 4; ++e) {
-          const uint32_t nw = (blk[2 * j + (e >> 1)] >> (16 * (e & 1))) & 0xFFFFu;
+          const uint32_t nw = ((e < 2 ? lo : hi) >> (16 * (e & 1))) & 0xFFFFu;
           const uint32_t bu = (uint32_t)st[nw] & 1u;
-          const uint32_t wpos = (blk[9] >> (4 * j + e)) & 1u;
+          const uint32_t wpos = (signs >> (4 * j + e)) & 1u;
           word |= (1u ^ bv ^ bu ^ wpos) << (kBondShift + e);
         }
         part += 2 * __popc(word) - 6;  // k = s h
@@ -1366,8 +1364,7 @@ hipError_t launch_msc(const LaunchPersistent& L, int block, hipStream_t s) {
   switch (block) {
     case 256: return launch_msc_t<256>(L, s);
     case 512: return launch_msc_t<512>(L, s);
-    case 1024: return launch_msc_t<1024>(L, s);
-    default: return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;  // the multispin path runs 256 or 512 threads
   }
 }
 
@@ -1382,7 +1379,6 @@ int persistent_occupancy(int path, int block, int adj, size_t lds_bytes) {
     switch (block) {
       case 256: return occupancy_of(k_msc<256>, 256, lds_bytes);
       case 512: return occupancy_of(k_msc<512>, 512, lds_bytes);
-      case 1024: return occupancy_of(k_msc<1024>, 1024, lds_bytes);
     }
   }
   return 0;
@@ -1400,8 +1396,8 @@ hipError_t set_persistent_lds_limit(int path, int block, size_t lds_bytes) {
     f = block == 256 ? field_kernel<256>(kAdjHbm)
                      : block == 512 ? field_kernel<512>(kAdjHbm) : field_kernel<1024>(kAdjHbm);
   } else {
-    f = block == 256 ? (const void*)k_msc<256> : block == 512 ? (const void*)k_msc<512>
-                                                              : (const void*)k_msc<1024>;
+    if (block != 256 && block != 512) return hipErrorInvalidValue;
+    f = block == 256 ? (const void*)k_msc<256> : (const void*)k_msc<512>;
   }
   return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
