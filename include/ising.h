@@ -148,7 +148,10 @@ int ising_threshold_table(const ising_schedule* s, int32_t kmax, uint64_t* out);
 
 /* ---------------------------------------------------------------- anneal */
 enum {
-  ISING_PATH_AUTO = 0,  /* the autotuner's (cached) choice */
+  ISING_PATH_AUTO = 0,  /* the autotuner's (cached) choice, else FIELD with
+                           one replica per block and about one thread per
+                           group of a colour class (PLAIN if that does not
+                           fit) */
   ISING_PATH_PLAIN = 1, /* state in HBM, one launch per colour pass */
   ISING_PATH_FIELD = 2, /* persistent: replica blocks resident in LDS */
   ISING_PATH_MSC = 3    /* persistent multispin: 32 replicas per word */
@@ -162,8 +165,8 @@ enum {
  *   block_threads        256, 512 or 1024 (MSC: 256 or 512); 0 = default
  *   lds_adjacency        FIELD: 0 = decide, 1 = stage a 16-bit adjacency in
  *                        LDS (unit weights, fewer than 2^15 vertices; a
- *                        fixed 32-byte-per-group form when every vertex has
- *                        degree 4, else CSR order), 2 = read the adjacency
+ *                        fixed 48-byte-per-group form with bond-word state
+ *                        when every vertex has degree 4, else CSR order), 2 = read the adjacency
  *                        from HBM, 3 = stage it in CSR order even when the
  *                        degree-4 form applies, 4 = read the degree-4 form
  *                        from HBM (unit weights, every vertex of degree 4,

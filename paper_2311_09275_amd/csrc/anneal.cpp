@@ -320,17 +320,20 @@ PersistentConfig heuristic_config(const HostGraph& g, const Table& t, int R) {
   c.G = 1;
   c.block = 1024;
   const int cus = std::max(device_cu_count(), 1);
-  // Several replicas per block only when replicas are plentiful, so that
-  // the unit count stays above the CU count.
-  while (c.G < kMaxReplicasPerBlock && (R / (2 * c.G)) >= 2 * cus) {
+  // One replica per block, with about one thread per group of a colour
+  // class: smaller blocks leave LDS for more resident blocks per CU.
+  const int per_class = std::max(1, g.n_pad / 4 / std::max(g.C, 1));
+  while (c.block > 256 && per_class * 2 <= c.block) c.block /= 2;
+  // Several replicas per block only when one replica leaves most of the
+  // block idle and replicas are plentiful, so that the unit count stays
+  // above the CU count.
+  while (c.G < kMaxReplicasPerBlock && c.block / c.G / 2 >= 64 && per_class * 2 <= c.block / c.G &&
+         (R / (2 * c.G)) >= 2 * cus) {
     PersistentConfig n = c;
     n.G *= 2;
     if (persistent_lds(g, t, n) > lds_budget(n.path)) break;
     c = n;
   }
-  // Small classes leave most of a 1024-thread block idle.
-  const int per_class = std::max(1, g.n_pad / 4 / std::max(g.C, 1));
-  while (c.block > 256 && c.block / c.G / 2 >= 64 && per_class * 2 <= c.block / c.G) c.block /= 2;
   if (check_config(g, t, R, c) != ISING_OK) c.path = ISING_PATH_PLAIN;
   return c;
 }
