@@ -89,7 +89,7 @@ int upload_graph(const HostGraph& g, DevGraph& d) {
   const size_t e2 = (size_t)(2 * g.m);
   size_t bytes = DeviceArena::span(sizeof(int32_t) * (g.n_pad + 1)) +
                  3 * DeviceArena::span(sizeof(int32_t) * e2) +
-                 DeviceArena::span(sizeof(int2) * e2) +
+                 DeviceArena::span(sizeof(int2) * (e2 + 4)) +
                  3 * DeviceArena::span(sizeof(int32_t) * g.grp.size()) +
                  DeviceArena::span(sizeof(int32_t) * g.cls.size()) +
                  DeviceArena::span(sizeof(int32_t) * g.n) +
@@ -100,7 +100,9 @@ int upload_graph(const HostGraph& g, DevGraph& d) {
   d.adj = d.arena.take<int32_t>(e2);
   d.wgt = d.arena.take<int32_t>(e2);
   d.adjm = d.arena.take<uint32_t>(e2);
-  d.aw = d.arena.take<int2>(e2);
+  // four zero entries past the end: the FIELD kernel fetches four entries
+  // per slot whatever the slot's degree
+  d.aw = d.arena.take<int2>(e2 + 4);
   d.grp = d.arena.take<int32_t>(g.grp.size());
   d.gbase = d.arena.take<int32_t>(g.grp.size());
   d.gdeg = d.arena.take<uint32_t>(g.grp.size());
@@ -115,6 +117,10 @@ int upload_graph(const HostGraph& g, DevGraph& d) {
     ICHK(hipMemcpy(d.wgt, g.wgt.data(), sizeof(int32_t) * e2, hipMemcpyHostToDevice));
     ICHK(hipMemcpy(d.adjm, g.adjm.data(), sizeof(uint32_t) * e2, hipMemcpyHostToDevice));
     ICHK(hipMemcpy(d.aw, g.aw.data(), sizeof(int2) * e2, hipMemcpyHostToDevice));
+  }
+  {
+    const int2 zero4[4] = {};
+    ICHK(hipMemcpy(d.aw + e2, zero4, sizeof zero4, hipMemcpyHostToDevice));
   }
   ICHK(hipMemcpy(d.gbase, g.gbase.data(), sizeof(int32_t) * g.grp.size(), hipMemcpyHostToDevice));
   ICHK(hipMemcpy(d.gdeg, g.gdeg.data(), sizeof(uint32_t) * g.grp.size(), hipMemcpyHostToDevice));

@@ -358,6 +358,30 @@ __device__ __forceinline__ int next_unit(const int32_t* list_off, int32_t* ctr, 
 // packed word of each neighbour.  Entries are taken four at a time; indices
 // past the slot's degree repeat its last entry and add zero, so the inner
 // body has no per-entry branch.
+// The same with the first four entries of every slot already fetched
+// (q[j][i] = aw[o[j] + i]); only slots of degree above four load more.
+__device__ __forceinline__ void push_group_prefetched(int32_t* st, const GLOBAL_AS i32x2* __restrict__ aw,
+                                                      const int (&o)[4], uint32_t dg, uint32_t fm,
+                                                      const int (&w)[4], const i32x2 (&q)[4][4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int d = (int)((dg >> (8 * j)) & 255u);
+    if ((fm >> j) & 1u) {
+      const int sgn4 = (w[j] & 1) ? -4 : 4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i < d) atomicAdd(&st[q[j][i].x], sgn4 * q[j][i].y);
+      for (int e0 = 4; e0 < d; e0 += 4) {
+        i32x2 r[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r[i] = aw[o[j] + min(e0 + i, d - 1)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) atomicAdd(&st[r[i].x], e0 + i < d ? sgn4 * r[i].y : 0);
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ void push_group_global(int32_t* st, const GLOBAL_AS i32x2* __restrict__ aw,
                                                   int base, uint32_t dg, uint32_t fm,
                                                   const int (&w)[4]) {
@@ -729,6 +753,26 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             a01 = make_uint4(b0.x, b0.y, b0.z, b0.w);
             a23 = make_uint4(b1.x, b1.y, b1.z, b1.w);
           }
+          // {position, w} form: the first four entries of every slot are
+          // fetched with the state, so that a flip's pushes do not wait for
+          // HBM; entries past a slot's degree (the next slot's, or the
+          // array's zero padding) are not used
+          int o[4] = {0, 0, 0, 0};
+          uint32_t dg = 0;
+          i32x2 q[4][4];
+          if (ADJ == kAdjHbm) {
+            dg = U.gdeg[g];
+            int base = U.gbase[g];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              o[j] = base;
+              base += (int)((dg >> (8 * j)) & 255u);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) q[j][i] = aw[o[j] + i];
+          }
           // all of the group's reads go out before any arithmetic
           __builtin_amdgcn_sched_barrier(0);
           int w[4] = {w4.x, w4.y, w4.z, w4.w};
@@ -801,7 +845,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
             if (ADJ == kAdjLds)
               push_wave_compacted(st, U.adj16, flist, U.gbase[g], U.gdeg[g], fm, w);
             else if (any)
-              push_group_global(st, aw, U.gbase[g], U.gdeg[g], fm, w);
+              push_group_prefetched(st, aw, o, dg, fm, w, q);
           }
         }
       }
