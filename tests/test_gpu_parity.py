@@ -133,6 +133,21 @@ def test_weighted_graph(path):
             tuning=PATHS[path])
 
 
+def test_field_path_colour_limit():
+    """The FIELD path keeps class bounds in two registers (at most 64
+    classes): a supplied 70-colouring is refused there, and the automatic
+    configuration falls back to the plain path with oracle-equal results."""
+    n = 140
+    inst = I.Instance("cycle140", n, np.arange(n, dtype=np.int32),
+                      ((np.arange(n) + 1) % n).astype(np.int32), np.ones(n, np.int32))
+    colour = (np.arange(n) % 70).astype(np.int32)
+    p = B.Problem.from_instance(inst, colour)
+    with pytest.raises(B.IsingError) as e:
+        p.anneal(B.Schedule.make(B.LINEAR, 10, 0.1, 1.0), 8, 1, PATHS["field_g1_b256_hbmadj"])
+    assert e.value.status == B.ERR_UNSUPPORTED
+    compare(inst, 60, 8, 3, tuning=B.Tuning(B.PATH_AUTO, 0, 0, 0), colour=colour)
+
+
 def test_unit_weight_paths_reject_weighted():
     p = B.Problem.from_instance(I.random_weighted(50, 100, 1, 3))
     for path in ("msc_g1_b256", "field_g1_b1024_ldsadj", "field_g1_b1024_csradj",
