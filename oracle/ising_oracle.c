@@ -19,7 +19,11 @@
  * 50-digit exp; colouring properness and the torus checkerboard; fields and
  * energy recomputed from scratch after every sweep; the cut identity; brute
  * force optima for n <= 20; beta = 0 and beta = infinity closed forms; planted
- * and gauge-transformed instances; a Boltzmann chi-square test.
+ * and gauge-transformed instances; a Boltzmann chi-square test.  Parallel
+ * tempering (below): reductions to the anneal (one temperature, equal
+ * temperatures), the odd-even transposition closed form, the exchange
+ * test's acceptance frequency, and the stationary energy at every
+ * temperature and exchange rate of every pair against exact enumeration.
  */
 #include "ising_oracle.h"
 
@@ -340,6 +344,54 @@ static uint64_t splitmix64(uint64_t* x) {
   return z ^ (z >> 31);
 }
 
+/* One sweep t of replica r: the colour classes in order, each class's
+ * vertices in ascending id (or, with shuf, in a random order: inside a class
+ * no two vertices are adjacent and every draw is keyed by its own vertex, so
+ * the order cannot change the result).  tq[k] for k = 1..kmax holds the
+ * sweep's thresholds.  Updates s, h, E and the counters. */
+static void sweep_once(const or_graph* G, uint64_t seed, int32_t t, int32_t r,
+                       const uint64_t* tq, int8_t* s, int64_t* h, int64_t* E,
+                       int64_t* accepts, int64_t* draws, int32_t* drawn_at,
+                       int32_t* order, uint64_t* shuf) {
+  for (int32_t c = 0; c < G->n_colours; ++c) {
+    const int32_t lo = G->class_start[c], hi = G->class_start[c + 1];
+    for (int32_t idx = lo; idx < hi; ++idx) order[idx - lo] = G->members[idx];
+    if (shuf) {
+      for (int32_t a = hi - lo - 1; a > 0; --a) {
+        int32_t b = (int32_t)(splitmix64(shuf) % (uint64_t)(a + 1));
+        int32_t tmp = order[a];
+        order[a] = order[b];
+        order[b] = tmp;
+      }
+    }
+    for (int32_t q = 0; q < hi - lo; ++q) {
+      const int32_t i = order[q];
+      const int64_t k = s[i] * h[i]; /* flipping s_i changes E by 2k */
+      int accept;
+      if (k <= 0) {
+        accept = 1;
+      } else {
+        uint32_t u = draw(G, seed, i, (uint32_t)t, (uint32_t)r, 0);
+        accept = (uint64_t)u < tq[k];
+        /* bookkeeping only: one Philox block serves a whole group, so
+         * count each (run, sweep) once; a draw whose threshold is
+         * 0 or 2^32 decides nothing and is not counted */
+        if (tq[k] != 0 && tq[k] != ((uint64_t)1 << 32) && drawn_at[G->run[i]] != t) {
+          drawn_at[G->run[i]] = t;
+          ++*draws;
+        }
+      }
+      if (accept) {
+        s[i] = (int8_t)-s[i];
+        *E += 2 * k;
+        ++*accepts;
+        for (int32_t a = G->row[i]; a < G->row[i + 1]; ++a)
+          h[G->nbr[a]] -= 2 * (int64_t)G->wt[a] * s[i];
+      }
+    }
+  }
+}
+
 typedef struct {
   const or_graph* G;
   const or_run_in* run;
@@ -379,43 +431,8 @@ static void run_replica(worker_arg* A, int32_t r, int8_t* s, int64_t* h,
   for (int32_t t = 0; t < S; ++t) {
     const double beta = A->betas[t];
     for (int64_t k = 1; k <= kmax; ++k) tq[k] = oracle_threshold(beta, k);
-    for (int32_t c = 0; c < G->n_colours; ++c) {
-      const int32_t lo = G->class_start[c], hi = G->class_start[c + 1];
-      for (int32_t idx = lo; idx < hi; ++idx) order[idx - lo] = G->members[idx];
-      if (run->shuffle_seed) { /* any order inside a class is equivalent */
-        for (int32_t a = hi - lo - 1; a > 0; --a) {
-          int32_t b = (int32_t)(splitmix64(&shuf) % (uint64_t)(a + 1));
-          int32_t tmp = order[a];
-          order[a] = order[b];
-          order[b] = tmp;
-        }
-      }
-      for (int32_t q = 0; q < hi - lo; ++q) {
-        const int32_t i = order[q];
-        const int64_t k = s[i] * h[i]; /* flipping s_i changes E by 2k */
-        int accept;
-        if (k <= 0) {
-          accept = 1;
-        } else {
-          uint32_t u = draw(G, run->seed, i, (uint32_t)t, (uint32_t)r, 0);
-          accept = (uint64_t)u < tq[k];
-          /* bookkeeping only: one Philox block serves a whole group, so
-           * count each (run, sweep) once; a draw whose threshold is
-           * 0 or 2^32 decides nothing and is not counted */
-          if (tq[k] != 0 && tq[k] != ((uint64_t)1 << 32) && drawn_at[G->run[i]] != t) {
-            drawn_at[G->run[i]] = t;
-            ++draws;
-          }
-        }
-        if (accept) {
-          s[i] = (int8_t)-s[i];
-          E += 2 * k;
-          ++accepts;
-          for (int32_t a = G->row[i]; a < G->row[i + 1]; ++a)
-            h[G->nbr[a]] -= 2 * (int64_t)G->wt[a] * s[i];
-        }
-      }
-    }
+    sweep_once(G, run->seed, t, r, tq, s, h, &E, &accepts, &draws, drawn_at, order,
+               run->shuffle_seed ? &shuf : NULL);
     /* End of sweep: the best is taken over end-of-sweep states only, strict
      * improvement, so the earliest sweep reaching a value keeps it. */
     int64_t cut = (G->W - E) / 2;
@@ -514,6 +531,190 @@ int oracle_anneal(const or_graph_in* gin, const or_run_in* run,
   free(args);
   free(th);
   free(betas);
+  graph_free(&G);
+  return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Parallel tempering                                                    */
+/* ------------------------------------------------------------------ */
+/* Exchanging the temperatures of a (at beta_k) and b (at beta_k1 >= beta_k)
+ * has Metropolis ratio exp((beta_k1 - beta_k)(E_b - E_a)) on the product of
+ * Boltzmann weights exp(-beta E).  The energies differ by an even number
+ * (every state's E has the parity of sum_e w_e), so with q = (E_a - E_b)/2
+ * the ratio is exp(-2 q dbeta): at least 1 when q <= 0, else the same
+ * quantised threshold as a flip of "k = q" at inverse temperature dbeta. */
+int oracle_swap_accept(uint64_t seed, uint32_t m, uint32_t k, uint32_t set,
+                       int64_t Ea, int64_t Eb, double beta_k, double beta_k1) {
+  const int64_t q = (Ea - Eb) / 2;
+  if (q <= 0) return 1;
+  const double dbeta = beta_k1 - beta_k;
+  uint32_t ctr[4] = {m, k, set, 3};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t x[4];
+  oracle_philox4x32_10(ctr, key, x);
+  return (uint64_t)x[0] < oracle_threshold(dbeta, q);
+}
+
+typedef struct {
+  const or_graph* G;
+  const or_temper_in* pt;
+  or_temper_out* out;
+  int32_t first, stride; /* sets first, first+stride, ... */
+  int status;
+} temper_arg;
+
+static void temper_set(const temper_arg* A, int32_t set, int8_t* s, int64_t* h,
+                       uint64_t* tq, int32_t* order, int32_t* drawn_at,
+                       int64_t* E, int64_t* best_cut, int32_t* best_sweep,
+                       int64_t* accepts, int32_t* temp, int32_t* slot) {
+  const or_graph* G = A->G;
+  const or_temper_in* pt = A->pt;
+  or_temper_out* out = A->out;
+  const int32_t n = G->n, K = pt->n_temps, S = pt->n_sweeps;
+  const int64_t kmax = G->kmax;
+  const int64_t r0 = (int64_t)set * K;
+  int64_t draws = 0;
+  for (int32_t j = 0; j < K; ++j) {
+    const int64_t r = r0 + j;
+    int8_t* sj = s + (int64_t)j * n;
+    int64_t* hj = h + (int64_t)j * n;
+    for (int32_t i = 0; i < n; ++i) {
+      if (pt->init_spins)
+        sj[i] = pt->init_spins[r * n + i];
+      else
+        sj[i] = (draw(G, pt->seed, i, 0, (uint32_t)r, 1) >> 31) ? 1 : -1;
+    }
+    fields_from_scratch(G, sj, hj);
+    E[j] = energy_from_scratch(G, sj);
+    best_cut[j] = (G->W - E[j]) / 2;
+    best_sweep[j] = -1;
+    accepts[j] = 0;
+    temp[j] = j;
+    slot[j] = j;
+    if (out->best_state) memcpy(out->best_state + r * n, sj, (size_t)n);
+  }
+  /* thresholds of every temperature, [K][kmax + 1] */
+  for (int32_t k = 0; k < K; ++k)
+    for (int64_t d = 1; d <= kmax; ++d) tq[(int64_t)k * (kmax + 1) + d] = oracle_threshold(pt->betas[k], d);
+  for (int32_t t = 0; t < S; ++t) {
+    for (int32_t j = 0; j < K; ++j) {
+      int8_t* sj = s + (int64_t)j * n;
+      for (int32_t i = 0; i < n; ++i) drawn_at[i] = -1;
+      sweep_once(G, pt->seed, t, (int32_t)(r0 + j), tq + (int64_t)temp[j] * (kmax + 1), sj,
+                 h + (int64_t)j * n, &E[j], &accepts[j], &draws, drawn_at, order, NULL);
+      const int64_t cut = (G->W - E[j]) / 2;
+      if (cut > best_cut[j]) {
+        best_cut[j] = cut;
+        best_sweep[j] = t;
+        if (out->best_state) memcpy(out->best_state + (r0 + j) * n, sj, (size_t)n);
+      }
+    }
+    if ((t + 1) % pt->swap_every == 0) {
+      const int32_t m = (t + 1) / pt->swap_every - 1;
+      for (int32_t k = m & 1; k + 1 < K; k += 2) {
+        const int32_t a = slot[k], b = slot[k + 1];
+        if (oracle_swap_accept(pt->seed, (uint32_t)m, (uint32_t)k, (uint32_t)set, E[a], E[b],
+                               pt->betas[k], pt->betas[k + 1])) {
+          slot[k] = b;
+          slot[k + 1] = a;
+          temp[a] = k + 1;
+          temp[b] = k;
+          out->swaps[(int64_t)set * (K - 1) + k]++;
+        }
+      }
+    }
+    if (out->temp_energy)
+      for (int32_t k = 0; k < K; ++k)
+        out->temp_energy[((int64_t)set * S + t) * K + k] = E[slot[k]];
+  }
+  for (int32_t j = 0; j < K; ++j) {
+    const int64_t r = r0 + j;
+    out->best_cut[r] = best_cut[j];
+    out->best_sweep[r] = best_sweep[j];
+    out->accepts[r] = accepts[j];
+    out->final_energy[r] = E[j];
+    out->final_temp[r] = temp[j];
+    if (out->final_state) memcpy(out->final_state + r * n, s + (int64_t)j * n, (size_t)n);
+  }
+}
+
+static void* temper_worker(void* p) {
+  temper_arg* A = (temper_arg*)p;
+  const int32_t n = A->G->n, K = A->pt->n_temps;
+  const int64_t kmax = A->G->kmax;
+  int8_t* s = (int8_t*)malloc((size_t)K * (size_t)n);
+  int64_t* h = (int64_t*)malloc(sizeof(int64_t) * (size_t)K * (size_t)n);
+  uint64_t* tq = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)K * (size_t)(kmax + 1));
+  int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* drawn_at = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int64_t* E = (int64_t*)malloc(sizeof(int64_t) * (size_t)K);
+  int64_t* best_cut = (int64_t*)malloc(sizeof(int64_t) * (size_t)K);
+  int32_t* best_sweep = (int32_t*)malloc(sizeof(int32_t) * (size_t)K);
+  int64_t* accepts = (int64_t*)malloc(sizeof(int64_t) * (size_t)K);
+  int32_t* temp = (int32_t*)malloc(sizeof(int32_t) * (size_t)K);
+  int32_t* slot = (int32_t*)malloc(sizeof(int32_t) * (size_t)K);
+  if (!s || !h || !tq || !order || !drawn_at || !E || !best_cut || !best_sweep || !accepts ||
+      !temp || !slot) {
+    A->status = -1;
+  } else {
+    for (int32_t set = A->first; set < A->pt->n_sets; set += A->stride)
+      temper_set(A, set, s, h, tq, order, drawn_at, E, best_cut, best_sweep, accepts, temp,
+                 slot);
+  }
+  free(s);
+  free(h);
+  free(tq);
+  free(order);
+  free(drawn_at);
+  free(E);
+  free(best_cut);
+  free(best_sweep);
+  free(accepts);
+  free(temp);
+  free(slot);
+  return NULL;
+}
+
+int oracle_temper(const or_graph_in* gin, const or_temper_in* pt, or_temper_out* out) {
+  if (!gin || !pt || !out || !out->best_cut || !out->best_sweep || !out->accepts ||
+      !out->final_energy || !out->final_temp || !out->swaps)
+    return -1;
+  if (pt->n_temps < 1 || pt->n_sets < 1 || pt->n_sweeps < 1 || pt->swap_every < 1 || !pt->betas)
+    return -1;
+  if ((int64_t)pt->n_temps * pt->n_sets > 0x7FFFFFFF) return -1;
+  for (int32_t k = 0; k < pt->n_temps; ++k) {
+    if (!isfinite(pt->betas[k]) || pt->betas[k] < 0) return -1;
+    if (k > 0 && pt->betas[k] < pt->betas[k - 1]) return -1;
+  }
+  or_graph G;
+  if (graph_build(gin, &G) != 0) {
+    graph_free(&G);
+    return -1;
+  }
+  memset(out->swaps, 0, sizeof(int64_t) * (size_t)pt->n_sets * (size_t)(pt->n_temps - 1));
+  int32_t nt = pt->n_threads < 1 ? 1 : pt->n_threads;
+  if (nt > pt->n_sets) nt = pt->n_sets;
+  temper_arg* args = (temper_arg*)calloc((size_t)nt, sizeof(temper_arg));
+  pthread_t* th = (pthread_t*)calloc((size_t)nt, sizeof(pthread_t));
+  for (int32_t i = 0; i < nt; ++i) {
+    args[i].G = &G;
+    args[i].pt = pt;
+    args[i].out = out;
+    args[i].first = i;
+    args[i].stride = nt;
+  }
+  if (nt == 1) {
+    temper_worker(&args[0]);
+  } else {
+    for (int32_t i = 0; i < nt; ++i) pthread_create(&th[i], NULL, temper_worker, &args[i]);
+    for (int32_t i = 0; i < nt; ++i) pthread_join(th[i], NULL);
+  }
+  int status = 0;
+  for (int32_t i = 0; i < nt; ++i)
+    if (args[i].status) status = -1;
+  free(args);
+  free(th);
   graph_free(&G);
   return status;
 }

@@ -85,6 +85,54 @@ int oracle_validate(const or_graph_in* g);
 /* Run the anneal.  Returns 0, or -1 on invalid input. */
 int oracle_anneal(const or_graph_in* g, const or_run_in* run, or_run_out* out);
 
+/*
+ * Parallel tempering (replica exchange): the paper names it among the
+ * contenders for sparse Ising optimisation (Sec. II.C): replicas simulated at
+ * different temperatures exchange their temperatures.  Here a ladder of K
+ * inverse temperatures betas[0] <= ... <= betas[K-1] is run by each of
+ * n_sets independent sets of K replicas (R = n_sets K; replica r is in set
+ * r / K and starts at temperature r % K).  Every sweep is the annealing
+ * sweep above at the replica's current beta; after every swap_every-th
+ * sweep, swap round m (m = 0, 1, ...) tries the pairs (k, k+1) with k of
+ * the parity of m, in every set, as a Metropolis move on the product of the
+ * K Boltzmann distributions:
+ *     a = replica at k, b = replica at k+1, q = cut(b) - cut(a) = (E_a - E_b)/2
+ *     exchange iff q <= 0, or u < Tq(betas[k+1] - betas[k], q)
+ * with u word 0 of Philox(counter (m, k, set, 3), key seed) and Tq the
+ * threshold function above (exp(-2 q dbeta) = exp(-dbeta (E_a - E_b))).
+ * Best cuts and states are tracked per replica as in the anneal.
+ */
+typedef struct {
+  int32_t n_temps;          /* K >= 1 */
+  const double* betas;      /* [K], finite, >= 0, non-decreasing */
+  int32_t n_sets;           /* >= 1 */
+  int32_t n_sweeps;         /* S >= 1 */
+  int32_t swap_every;       /* P >= 1 */
+  uint64_t seed;
+  const int8_t* init_spins; /* NULL, or [R][n] +-1 */
+  int32_t n_threads;        /* host threads over sets (>= 1) */
+} or_temper_in;
+
+typedef struct {
+  int64_t* best_cut;     /* [R] */
+  int32_t* best_sweep;   /* [R]; -1 = the initial state */
+  int64_t* accepts;      /* [R] accepted flips */
+  int64_t* final_energy; /* [R] */
+  int32_t* final_temp;   /* [R] temperature index at the end */
+  int64_t* swaps;        /* [n_sets][K-1] accepted exchanges of pair (k, k+1) */
+  int8_t* best_state;    /* [R][n] or NULL */
+  int8_t* final_state;   /* [R][n] or NULL */
+  int64_t* temp_energy;  /* [n_sets][S][K] or NULL: E of the replica at
+                            temperature k after sweep t and its swap round */
+} or_temper_out;
+
+/* Run parallel tempering.  Returns 0, or -1 on invalid input. */
+int oracle_temper(const or_graph_in* g, const or_temper_in* pt, or_temper_out* out);
+/* The exchange test of one pair: 1 = exchange.  Ea, Eb are the energies of
+ * the replicas at betas[k] and betas[k+1]. */
+int oracle_swap_accept(uint64_t seed, uint32_t m, uint32_t k, uint32_t set,
+                       int64_t Ea, int64_t Eb, double beta_k, double beta_k1);
+
 #ifdef __cplusplus
 }
 #endif

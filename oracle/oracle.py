@@ -45,6 +45,20 @@ class _RunIn(C.Structure):
                 ("shuffle_seed", C.c_uint64)]
 
 
+class _TemperIn(C.Structure):
+    _fields_ = [("n_temps", C.c_int32), ("betas", C.c_void_p), ("n_sets", C.c_int32),
+                ("n_sweeps", C.c_int32), ("swap_every", C.c_int32), ("seed", C.c_uint64),
+                ("init_spins", C.c_void_p), ("n_threads", C.c_int32)]
+
+
+class _TemperOut(C.Structure):
+    _fields_ = [("best_cut", C.c_void_p), ("best_sweep", C.c_void_p),
+                ("accepts", C.c_void_p), ("final_energy", C.c_void_p),
+                ("final_temp", C.c_void_p), ("swaps", C.c_void_p),
+                ("best_state", C.c_void_p), ("final_state", C.c_void_p),
+                ("temp_energy", C.c_void_p)]
+
+
 class _RunOut(C.Structure):
     _fields_ = [("best_cut", C.c_void_p), ("best_sweep", C.c_void_p),
                 ("accepts", C.c_void_p), ("final_energy", C.c_void_p),
@@ -75,6 +89,9 @@ def lib():
         L.oracle_cut.restype = C.c_int64
         L.oracle_validate.argtypes = [C.c_void_p]
         L.oracle_anneal.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oracle_temper.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oracle_swap_accept.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                         C.c_int64, C.c_int64, C.c_double, C.c_double]
         _lib = L
     return _lib
 
@@ -186,3 +203,54 @@ def anneal(inst, n_sweeps, n_replicas, seed, kind=LINEAR, beta0=0.1,
     return Result(best_cut, best_sweep, accepts, energy, best_state,
                   final_state, final_field, trace, int(out.check_failures),
                   r_begin, draws, impr)
+
+
+@dataclass
+class TemperResult:
+    best_cut: np.ndarray      # int64 [R]
+    best_sweep: np.ndarray    # int32 [R]
+    accepts: np.ndarray       # int64 [R]
+    final_energy: np.ndarray  # int64 [R]
+    final_temp: np.ndarray    # int32 [R] temperature index at the end
+    swaps: np.ndarray         # int64 [n_sets, K-1] accepted exchanges
+    best_state: np.ndarray | None
+    final_state: np.ndarray | None
+    temp_energy: np.ndarray | None  # int64 [n_sets, S, K]
+
+    def argmax(self) -> int:
+        return int(np.argmax(self.best_cut))
+
+
+def temper(inst, betas, n_sets, n_sweeps, swap_every, seed, colour=None,
+           init_spins=None, n_threads=1, want_states=True,
+           want_temp_energy=False) -> TemperResult:
+    """Parallel tempering over the ladder ``betas`` (see oracle_temper)."""
+    b = np.ascontiguousarray(betas, np.float64)
+    K = int(b.shape[0])
+    R = K * n_sets
+    n = inst.n
+    g, keep = _graph(inst, colour)
+    init = None if init_spins is None else np.ascontiguousarray(init_spins, np.int8)
+    pin = _TemperIn(K, _p(b), n_sets, n_sweeps, swap_every,
+                    int(seed) & 0xFFFFFFFFFFFFFFFF, _p(init), n_threads)
+    best_cut = np.zeros(R, np.int64)
+    best_sweep = np.zeros(R, np.int32)
+    accepts = np.zeros(R, np.int64)
+    energy = np.zeros(R, np.int64)
+    temp = np.zeros(R, np.int32)
+    swaps = np.zeros((n_sets, max(K - 1, 1)), np.int64)
+    best_state = np.zeros((R, n), np.int8) if want_states else None
+    final_state = np.zeros((R, n), np.int8) if want_states else None
+    te = np.zeros((n_sets, n_sweeps, K), np.int64) if want_temp_energy else None
+    out = _TemperOut(_p(best_cut), _p(best_sweep), _p(accepts), _p(energy), _p(temp),
+                     _p(swaps), _p(best_state), _p(final_state), _p(te))
+    rc = lib().oracle_temper(C.byref(g), C.byref(pin), C.byref(out))
+    if rc != 0:
+        raise ValueError("oracle rejected the input")
+    return TemperResult(best_cut, best_sweep, accepts, energy, temp,
+                        swaps[:, :K - 1], best_state, final_state, te)
+
+
+def swap_accept(seed, m, k, set_, Ea, Eb, beta_k, beta_k1) -> bool:
+    return bool(lib().oracle_swap_accept(int(seed) & 0xFFFFFFFFFFFFFFFF, m, k, set_,
+                                         int(Ea), int(Eb), float(beta_k), float(beta_k1)))
