@@ -245,6 +245,63 @@ int ising_last_anneal_ms(ising_problem* p, double* ms);
 int ising_last_run_info(const ising_problem* p, int32_t* n_replicas, int32_t* n_sweeps,
                         int32_t* path);
 
+/* ------------------------------------------------------ parallel tempering */
+/*
+ * Parallel tempering (replica exchange), which the paper names among the
+ * contenders for sparse Ising optimisation (Sec. II.C): replicas run at
+ * different temperatures and exchange them.
+ *   n_temps     K >= 1 temperatures per set
+ *   betas       [K] inverse temperatures, finite, >= 0, non-decreasing
+ *               (copied; the caller keeps ownership)
+ *   n_sets      independent sets of K replicas; R = n_sets * K, replica r
+ *               is in set r / K and starts at temperature r % K
+ *   n_sweeps    S >= 1
+ *   swap_every  P >= 1: after sweeps P-1, 2P-1, ... exchange round m
+ *               (m = 0, 1, ...) tries the pairs (k, k+1) with k of m's
+ *               parity in every set
+ * Each sweep is the annealing sweep at the replica's current beta (its
+ * Philox counters as in ising_anneal, (t, run, r, 0)).  The pair with the
+ * replica a at k and b at k+1 exchanges temperatures with the Metropolis
+ * probability of the product of Boltzmann weights: always when
+ * q = cut(b) - cut(a) <= 0, else when word 0 of Philox(counter
+ * (m, k, set, 3), key seed) is below floor(2^32 exp(-2 q (beta_k+1 -
+ * beta_k))).
+ */
+typedef struct {
+  int32_t n_temps;
+  const double* betas;
+  int32_t n_sets;
+  int32_t n_sweeps;
+  int32_t swap_every;
+} ising_tempering;
+
+/*
+ * Run parallel tempering on p, enqueued on `stream` (returns without
+ * waiting).  Best cuts and states are tracked per replica as in an anneal
+ * and read with ising_cut, ising_best_state, ising_replica_results and
+ * ising_replica_state; the exchange state with ising_temper_results.
+ * `tuning` NULL = automatic (FIELD, else PLAIN when it does not fit); the
+ * FIELD path runs a launch per P sweeps and an exchange kernel after each,
+ * captured into one hipGraph.  Initial states given with
+ * ising_set_initial_state apply (for R = n_sets * K replicas).
+ * Errors: ISING_ERR_INVALID (bad ladder or sizes, tuning out of range);
+ * ISING_ERR_UNSUPPORTED (the MSC path, energy tracing enabled, FIELD with
+ * more replicas per block than the rows it can stage, or what ising_anneal
+ * rejects); ISING_ERR_STATE (initial states for another R); ISING_ERR_NOMEM;
+ * ISING_ERR_DEVICE.
+ */
+int ising_temper(ising_problem* p, const ising_tempering* pt, uint64_t seed,
+                 const ising_tuning* tuning, void* stream);
+
+/*
+ * Exchange state after the last ising_temper of p (synchronises).  Either
+ * pointer may be NULL.
+ *   final_temp  [R] temperature index of every replica at the end
+ *   swaps       [n_sets][K-1] accepted exchanges of each pair (k, k+1)
+ * ISING_ERR_STATE when the last run of p was not tempering.
+ */
+int ising_temper_results(ising_problem* p, int32_t* final_temp, int64_t* swaps);
+
 /* --------------------------------------------------------------- batching */
 /*
  * Anneal `count` problems in one persistent launch (captured once into a

@@ -560,7 +560,8 @@ typedef struct {
   const or_graph* G;
   const or_temper_in* pt;
   or_temper_out* out;
-  int32_t first, stride; /* sets first, first+stride, ... */
+  int32_t first, stride; /* sets first, first+stride, ... below end */
+  int32_t end;
   int status;
 } temper_arg;
 
@@ -658,7 +659,7 @@ static void* temper_worker(void* p) {
       !temp || !slot) {
     A->status = -1;
   } else {
-    for (int32_t set = A->first; set < A->pt->n_sets; set += A->stride)
+    for (int32_t set = A->first; set < A->end; set += A->stride)
       temper_set(A, set, s, h, tq, order, drawn_at, E, best_cut, best_sweep, accepts, temp,
                  slot);
   }
@@ -692,17 +693,24 @@ int oracle_temper(const or_graph_in* gin, const or_temper_in* pt, or_temper_out*
     graph_free(&G);
     return -1;
   }
+  int32_t s0 = pt->set_begin, s1 = pt->set_end;
+  if (s0 == 0 && s1 == 0) s1 = pt->n_sets;
+  if (s0 < 0 || s1 > pt->n_sets || s0 >= s1) {
+    graph_free(&G);
+    return -1;
+  }
   memset(out->swaps, 0, sizeof(int64_t) * (size_t)pt->n_sets * (size_t)(pt->n_temps - 1));
   int32_t nt = pt->n_threads < 1 ? 1 : pt->n_threads;
-  if (nt > pt->n_sets) nt = pt->n_sets;
+  if (nt > s1 - s0) nt = s1 - s0;
   temper_arg* args = (temper_arg*)calloc((size_t)nt, sizeof(temper_arg));
   pthread_t* th = (pthread_t*)calloc((size_t)nt, sizeof(pthread_t));
   for (int32_t i = 0; i < nt; ++i) {
     args[i].G = &G;
     args[i].pt = pt;
     args[i].out = out;
-    args[i].first = i;
+    args[i].first = s0 + i;
     args[i].stride = nt;
+    args[i].end = s1;
   }
   if (nt == 1) {
     temper_worker(&args[0]);

@@ -111,6 +111,8 @@ typedef struct {
   uint64_t seed;
   const int8_t* init_spins; /* NULL, or [R][n] +-1 */
   int32_t n_threads;        /* host threads over sets (>= 1) */
+  int32_t set_begin, set_end; /* simulate sets set_begin .. set_end-1 (both
+                                 0: all); outputs stay indexed by replica */
 } or_temper_in;
 
 typedef struct {

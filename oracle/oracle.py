@@ -48,7 +48,8 @@ class _RunIn(C.Structure):
 class _TemperIn(C.Structure):
     _fields_ = [("n_temps", C.c_int32), ("betas", C.c_void_p), ("n_sets", C.c_int32),
                 ("n_sweeps", C.c_int32), ("swap_every", C.c_int32), ("seed", C.c_uint64),
-                ("init_spins", C.c_void_p), ("n_threads", C.c_int32)]
+                ("init_spins", C.c_void_p), ("n_threads", C.c_int32),
+                ("set_begin", C.c_int32), ("set_end", C.c_int32)]
 
 
 class _TemperOut(C.Structure):
@@ -223,8 +224,10 @@ class TemperResult:
 
 def temper(inst, betas, n_sets, n_sweeps, swap_every, seed, colour=None,
            init_spins=None, n_threads=1, want_states=True,
-           want_temp_energy=False) -> TemperResult:
-    """Parallel tempering over the ladder ``betas`` (see oracle_temper)."""
+           want_temp_energy=False, sets=None) -> TemperResult:
+    """Parallel tempering over the ladder ``betas`` (see oracle_temper).
+    ``sets`` = (begin, end) simulates only those sets (the others' entries
+    stay zero)."""
     b = np.ascontiguousarray(betas, np.float64)
     K = int(b.shape[0])
     R = K * n_sets
@@ -232,7 +235,8 @@ def temper(inst, betas, n_sets, n_sweeps, swap_every, seed, colour=None,
     g, keep = _graph(inst, colour)
     init = None if init_spins is None else np.ascontiguousarray(init_spins, np.int8)
     pin = _TemperIn(K, _p(b), n_sets, n_sweeps, swap_every,
-                    int(seed) & 0xFFFFFFFFFFFFFFFF, _p(init), n_threads)
+                    int(seed) & 0xFFFFFFFFFFFFFFFF, _p(init), n_threads,
+                    *((0, 0) if sets is None else sets))
     best_cut = np.zeros(R, np.int64)
     best_sweep = np.zeros(R, np.int32)
     accepts = np.zeros(R, np.int64)

@@ -65,6 +65,18 @@ class Tuning(C.Structure):
                 ("block_threads", C.c_int32), ("lds_adjacency", C.c_int32)]
 
 
+class Tempering(C.Structure):
+    _fields_ = [("n_temps", C.c_int32), ("betas", C.c_void_p), ("n_sets", C.c_int32),
+                ("n_sweeps", C.c_int32), ("swap_every", C.c_int32)]
+
+    @staticmethod
+    def make(betas, n_sets, n_sweeps, swap_every) -> "Tempering":
+        b = np.ascontiguousarray(betas, np.float64)
+        t = Tempering(int(b.shape[0]), b.ctypes.data, int(n_sets), int(n_sweeps), int(swap_every))
+        t._keep = b  # the struct points into this array
+        return t
+
+
 class Info(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_colours", C.c_int32), ("m", C.c_int64),
                 ("total_weight", C.c_int64), ("kmax", C.c_int32), ("max_degree", C.c_int32),
@@ -101,6 +113,8 @@ _sig = {
     "ising_energy_trace": ([P, P], C.c_int),
     "ising_last_anneal_ms": ([P, C.POINTER(C.c_double)], C.c_int),
     "ising_last_run_info": ([P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "ising_temper": ([P, C.POINTER(Tempering), C.c_uint64, C.POINTER(Tuning), P], C.c_int),
+    "ising_temper_results": ([P, P, P], C.c_int),
     "ising_anneal_batch": ([P, C.c_int32, C.POINTER(Schedule), C.c_int32, P, C.POINTER(Tuning), P], C.c_int),
     "ising_last_batch_ms": ([C.POINTER(C.c_double)], C.c_int),
     "ising_autotune": ([P, C.c_int32, C.POINTER(Schedule), C.c_int32, C.c_int32, C.POINTER(Tuning), P], C.c_int),
@@ -260,6 +274,20 @@ def ising_last_anneal_ms(h) -> float:
     return out.value
 
 
+# ------------------------------------------------------------------ tempering
+def ising_temper(h, pt: Tempering, seed: int, tuning: Tuning | None = None, stream=None) -> None:
+    _check(_L.ising_temper(h, C.byref(pt), seed & (2**64 - 1),
+                           None if tuning is None else C.byref(tuning), _stream(stream)),
+           "ising_temper")
+
+
+def ising_temper_results(h, n_temps: int, n_sets: int):
+    temp = np.zeros(n_temps * n_sets, np.int32)
+    swaps = np.zeros((n_sets, max(n_temps - 1, 1)), np.int64)
+    _check(_L.ising_temper_results(h, _ptr(temp), _ptr(swaps)), "ising_temper_results")
+    return temp, swaps[:, :n_temps - 1]
+
+
 # ------------------------------------------------------------------ batching
 def ising_anneal_batch(handles, sched: Schedule, n_replicas, seeds, tuning: Tuning | None = None,
                        stream=None) -> None:
@@ -381,6 +409,18 @@ class Problem:
     def anneal(self, sched: Schedule, n_replicas: int, seed: int, tuning: Tuning | None = None,
                stream=None) -> None:
         ising_anneal_tuned(self.handle, sched, n_replicas, seed, tuning, stream)
+
+    def temper(self, betas, n_sets: int, n_sweeps: int, swap_every: int, seed: int,
+               tuning: Tuning | None = None, stream=None) -> None:
+        """Parallel tempering over the ladder ``betas`` (see ``ising_temper``)."""
+        self._ladder = (len(betas), int(n_sets))
+        ising_temper(self.handle, Tempering.make(betas, n_sets, n_sweeps, swap_every), seed,
+                     tuning, stream)
+
+    def temper_results(self):
+        """(final temperature index [R], accepted exchanges [n_sets, K-1])."""
+        K, n_sets = getattr(self, "_ladder", (1, 1))
+        return ising_temper_results(self.handle, K, n_sets)
 
     @property
     def R(self) -> int:

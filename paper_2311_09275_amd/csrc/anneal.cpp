@@ -523,9 +523,25 @@ JobDev make_job(const HostGraph& g, const DevGraph& d, const RunBuffers& b, int 
 }
 
 // ---------------------------------------------------------------- persistent
+int temper_max_group(const Table& t) { return row_chunk(t); }
+
 int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const PersistentConfig& cfg,
-                   hipStream_t stream, bool use_graph) {
+                   hipStream_t stream, bool use_graph, const TemperPlan* pt) {
   const int n_jobs = (int)specs.size();
+  if (pt && (n_jobs != 1 || cfg.path != ISING_PATH_FIELD || cfg.G > row_chunk(specs[0].b->table))) {
+    set_error("tempering runs one FIELD job with at most %d replicas per block",
+              n_jobs == 1 ? row_chunk(specs[0].b->table) : 0);
+    return ISING_ERR_UNSUPPORTED;
+  }
+  // segments of the sweeps: one launch each (tempering: up to every
+  // exchange round), else the jobs' own ranges in one launch
+  std::vector<int2> segs;
+  if (pt) {
+    for (int t0 = 0; t0 < pt->S; t0 += pt->P) segs.push_back(make_int2(t0, std::min(pt->S, t0 + pt->P)));
+  } else {
+    segs.push_back(make_int2(-1, -1));
+  }
+  const int n_segs = (int)segs.size();
   std::vector<JobDev> jobs((size_t)n_jobs);
   struct U {
     double cost;
@@ -606,10 +622,21 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   }
   if (staged) lds = lds_staged;
   for (int j = 0; j < n_jobs; ++j) jobs[(size_t)j].adj_form = forms[(size_t)j];
+  if (pt) {
+    // one copy of the job per segment
+    JobDev base = jobs[0];
+    base.temp = pt->swap->temp;
+    jobs.assign((size_t)n_segs, base);
+    for (int i = 0; i < n_segs; ++i) {
+      jobs[(size_t)i].t_begin = segs[(size_t)i].x;
+      jobs[(size_t)i].t_end = segs[(size_t)i].y;
+    }
+  }
+  const int n_dev_jobs = (int)jobs.size();
 
   // device and pinned staging buffers
-  if (L.jobs_cap < (size_t)n_jobs || L.units_cap < (size_t)n_units || !L.arena.base) {
-    L.jobs_cap = std::max<size_t>(n_jobs, 16);
+  if (L.jobs_cap < (size_t)n_dev_jobs || L.units_cap < (size_t)n_units || !L.arena.base) {
+    L.jobs_cap = std::max<size_t>(n_dev_jobs, 16);
     L.units_cap = std::max<size_t>(n_units, 1024);
     size_t bytes = DeviceArena::span(sizeof(JobDev) * L.jobs_cap) +
                    DeviceArena::span(sizeof(int2) * L.units_cap) + 2 * DeviceArena::span(64);
@@ -619,7 +646,7 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
     L.list_off_d = L.arena.take<int32_t>(16);
     L.ctr_d = L.arena.take<int32_t>(16);
   }
-  const size_t stage_bytes = sizeof(JobDev) * n_jobs + sizeof(int2) * n_units + sizeof(list_off);
+  const size_t stage_bytes = sizeof(JobDev) * n_dev_jobs + sizeof(int2) * n_units + sizeof(list_off);
   if (!L.staged) ICHK(hipEventCreateWithFlags(&L.staged, hipEventDisableTiming));
   (void)hipEventSynchronize(L.staged);  // the previous upload has left the buffer
   if (L.staging_cap < stage_bytes) {
@@ -629,14 +656,14 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
     ICHK(hipHostMalloc((void**)&L.staging, L.staging_cap, hipHostMallocDefault));
   }
   char* sp = L.staging;
-  memcpy(sp, jobs.data(), sizeof(JobDev) * n_jobs);
-  memcpy(sp + sizeof(JobDev) * n_jobs, units.data(), sizeof(int2) * n_units);
-  memcpy(sp + sizeof(JobDev) * n_jobs + sizeof(int2) * n_units, list_off, sizeof(list_off));
-  ICHK(hipMemcpyAsync(L.jobs_d, sp, sizeof(JobDev) * n_jobs, hipMemcpyHostToDevice, stream));
-  ICHK(hipMemcpyAsync(L.units_d, sp + sizeof(JobDev) * n_jobs, sizeof(int2) * n_units,
+  const size_t jb = sizeof(JobDev) * n_dev_jobs;
+  memcpy(sp, jobs.data(), jb);
+  memcpy(sp + jb, units.data(), sizeof(int2) * n_units);
+  memcpy(sp + jb + sizeof(int2) * n_units, list_off, sizeof(list_off));
+  ICHK(hipMemcpyAsync(L.jobs_d, sp, jb, hipMemcpyHostToDevice, stream));
+  ICHK(hipMemcpyAsync(L.units_d, sp + jb, sizeof(int2) * n_units, hipMemcpyHostToDevice, stream));
+  ICHK(hipMemcpyAsync(L.list_off_d, sp + jb + sizeof(int2) * n_units, sizeof(list_off),
                       hipMemcpyHostToDevice, stream));
-  ICHK(hipMemcpyAsync(L.list_off_d, sp + sizeof(JobDev) * n_jobs + sizeof(int2) * n_units,
-                      sizeof(list_off), hipMemcpyHostToDevice, stream));
   ICHK(hipEventRecord(L.staged, stream));
 
   // raising the dynamic LDS limit is advisory on this runtime
@@ -657,10 +684,18 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   lp.adj = form;
 
   auto enqueue = [&](hipStream_t s) -> hipError_t {
-    hipError_t e = launch_fill_i32(L.ctr_d, 0, 8, s);
-    if (e != hipSuccess) return e;
-    e = cfg.path == ISING_PATH_MSC ? launch_msc(lp, cfg.block, s) : launch_field(lp, cfg.block, s);
-    if (e != hipSuccess) return e;
+    for (int i = 0; i < n_segs; ++i) {
+      hipError_t e = launch_fill_i32(L.ctr_d, 0, 8, s);
+      if (e != hipSuccess) return e;
+      LaunchPersistent li = lp;
+      li.jobs = L.jobs_d + (pt ? i : 0);
+      e = cfg.path == ISING_PATH_MSC ? launch_msc(li, cfg.block, s) : launch_field(li, cfg.block, s);
+      if (e != hipSuccess) return e;
+      if (pt && segs[(size_t)i].y % pt->P == 0) {
+        e = launch_swap(*pt->swap, segs[(size_t)i].y / pt->P - 1, s);
+        if (e != hipSuccess) return e;
+      }
+    }
     return launch_argmax(L.jobs_d, n_jobs, s);
   };
 
@@ -668,9 +703,17 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   if (!L.ev1) ICHK(hipEventCreate(&L.ev1));
   ICHK(hipEventRecord(L.ev0, stream));
   if (use_graph && stream) {
-    char key[256];
-    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%zu/%d/%d/%d/%p", cfg.path, cfg.block, cfg.G, planes,
-             form, lds, lp.grid, n_jobs, n_units, (void*)L.arena.base);
+    char key[512];
+    int kl = snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%zu/%d/%d/%d/%p", cfg.path, cfg.block, cfg.G,
+                      planes, form, lds, lp.grid, n_jobs, n_units, (void*)L.arena.base);
+    if (pt) {
+      // the exchange launches carry their arguments by value
+      const SwapDev& X = *pt->swap;
+      snprintf(key + kl, sizeof key - (size_t)kl, "/pt/%d/%d/%d/%d/%u/%u/%p/%p/%p/%p/%p/%p/%p", pt->S,
+               pt->P, X.K, X.n_sets, X.seed_lo, X.seed_hi, (const void*)X.energy, (void*)X.temp,
+               (void*)X.slot, (void*)X.swaps, (const void*)X.tq, (const void*)X.off,
+               (const void*)X.len);
+    }
     if (!L.exec || L.graph_key != key) {
       if (L.exec) (void)hipGraphExecDestroy(L.exec);
       if (L.graph) (void)hipGraphDestroy(L.graph);
@@ -700,6 +743,37 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
 }  // namespace ising
 
 using namespace ising;
+
+// Arguments of the per-pass kernels for a run of p in b.
+PlainDev make_plain(const ising_problem* p, const RunBuffers& b, int R, uint64_t seed) {
+  PlainDev P;
+  memset(&P, 0, sizeof P);
+  P.row = p->dg.row;
+  P.adj = p->dg.adj;
+  P.wgt = p->dg.wgt;
+  P.grp = p->dg.grp;
+  P.n_pad = p->g.n_pad;
+  P.R = R;
+  P.W = (int32_t)p->g.W;
+  P.flags = (b.trace ? kJobTrace : 0);
+  P.tq = b.tq;
+  P.tq_off = b.tq_off;
+  P.tq_len = b.tq_len;
+  P.seed_lo = (uint32_t)seed;
+  P.seed_hi = (uint32_t)(seed >> 32);
+  P.init_spins = b.init_dev;
+  P.spins = b.spins;
+  P.field = b.field;
+  P.best = static_cast<int8_t*>(b.best);
+  P.energy = b.energy;
+  P.eacc = b.eacc;
+  P.best_cut = b.best_cut;
+  P.best_sweep = b.best_sweep;
+  P.snap = b.snap;
+  P.accepts = b.accepts;
+  P.trace = b.trace_buf;
+  return P;
+}
 
 // ================================================================ C ABI
 extern "C" {
@@ -834,8 +908,6 @@ int ising_set_trace(ising_problem* p, int32_t enable) {
   return ISING_OK;
 }
 
-static int resolve_config(ising_problem* p, const Table& table, int R, const ising_tuning* t,
-                          PersistentConfig& cfg);
 
 // Thresholds of schedule s for p, rebuilt only when s differs from the last
 // schedule p annealed with (the table costs S * kmax exponentials).
@@ -873,33 +945,9 @@ int ising_anneal_tuned(ising_problem* p, const ising_schedule* s, int32_t n_repl
   hipStream_t st = static_cast<hipStream_t>(stream);
   IRET(prepare_run(p, table, n_replicas, cfg, st));
   RunBuffers& b = p->run;
+  p->temper.valid = false;
   if (cfg.path == ISING_PATH_PLAIN) {
-    PlainDev P;
-    memset(&P, 0, sizeof P);
-    P.row = p->dg.row;
-    P.adj = p->dg.adj;
-    P.wgt = p->dg.wgt;
-    P.grp = p->dg.grp;
-    P.n_pad = p->g.n_pad;
-    P.R = n_replicas;
-    P.W = (int32_t)p->g.W;
-    P.flags = (b.trace ? kJobTrace : 0);
-    P.tq = b.tq;
-    P.tq_off = b.tq_off;
-    P.tq_len = b.tq_len;
-    P.seed_lo = (uint32_t)seed;
-    P.seed_hi = (uint32_t)(seed >> 32);
-    P.init_spins = b.init_dev;
-    P.spins = b.spins;
-    P.field = b.field;
-    P.best = static_cast<int8_t*>(b.best);
-    P.energy = b.energy;
-    P.eacc = b.eacc;
-    P.best_cut = b.best_cut;
-    P.best_sweep = b.best_sweep;
-    P.snap = b.snap;
-    P.accepts = b.accepts;
-    P.trace = b.trace_buf;
+    PlainDev P = make_plain(p, b, n_replicas, seed);
     static thread_local JobDev hjob;
     hjob = make_job(p->g, p->dg, b, n_replicas, seed, 0, table.S, cfg);
     ICHK(hipMemcpy(b.job_dev, &hjob, sizeof(JobDev), hipMemcpyHostToDevice));
@@ -1069,8 +1117,8 @@ int ising_last_anneal_ms(ising_problem* p, double* ms) {
 // ---------------------------------------------------------------- config
 int tune_lookup(const ising::HostGraph& g, const ising::Table& t, int R, ising::PersistentConfig& c);
 
-static int resolve_config(ising_problem* p, const Table& table, int R, const ising_tuning* t,
-                          PersistentConfig& cfg) {
+int resolve_config(ising_problem* p, const Table& table, int R, const ising_tuning* t,
+                   PersistentConfig& cfg) {
   const int path = t ? t->path : ISING_PATH_AUTO;
   if (path == ISING_PATH_AUTO) {
     if (tune_lookup(p->g, table, R, cfg) != ISING_OK) cfg = heuristic_config(p->g, table, R);

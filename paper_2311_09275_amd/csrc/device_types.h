@@ -17,6 +17,7 @@ constexpr int kGroupCountShift = 28;
 // Philox counter word 3 ("tag") of each purpose.
 constexpr uint32_t kTagSweep = 0;
 constexpr uint32_t kTagInit = 1;
+constexpr uint32_t kTagSwap = 3;  // parallel tempering: (round, pair, set, 3)
 
 // Threshold row length meaning "beta_t == 0: accept every move".
 constexpr int32_t kAcceptAll = -1;
@@ -96,6 +97,9 @@ struct JobDev {
   const uint32_t* tqp;   // [S][2 kw + 2]
   const uint32_t* tqb;   // FIELD degree-4 forms: [S][kBondRowWords]
   int32_t row_chunk;     // FIELD: sweeps whose rows are staged in LDS at once
+  // parallel tempering: row of replica r is temp[r] for every sweep (the
+  // rows are then one per temperature); null = row t for sweep t
+  const int32_t* temp;
   int32_t S, t_begin, t_end, flags;
   int32_t kw;            // longest row (LDS row capacity)
   // run
@@ -125,6 +129,7 @@ struct PlainDev {
   const uint32_t* tq;
   const int32_t* tq_off;
   const int32_t* tq_len;
+  const int32_t* temp;   // parallel tempering: row of replica r; null = row t
   uint32_t seed_lo, seed_hi;
   const int8_t* init_spins;  // [R][n_pad] or null
   int8_t* spins;         // [n_pad][R]
@@ -137,6 +142,25 @@ struct PlainDev {
   int32_t* snap;         // [R] last improving sweep (-1 = initial state)
   unsigned long long* accepts;  // [R]
   int32_t* trace;        // [S][R]
+};
+
+// Parallel tempering: the ladders of all sets and their exchange state.
+// Replica r is in set r / K; slot[set K + k] is the replica at temperature
+// k of its set and temp its inverse.  The exchange thresholds of pair
+// (k, k+1) are a row of the flip-threshold form, for inverse temperature
+// betas[k+1] - betas[k] and indexed by the cut difference q >= 1:
+// tq[off[k] + q - 1] = Tq - 1 for q <= len[k] (Tq = 0 beyond), len[k] =
+// kAcceptAll when the two betas are equal.
+struct SwapDev {
+  int32_t K, n_sets;
+  uint32_t seed_lo, seed_hi;
+  const int32_t* energy;   // [R] the run's current energies
+  int32_t* temp;           // [R]
+  int32_t* slot;           // [n_sets][K]
+  long long* swaps;        // [n_sets][K-1] accepted exchanges
+  const uint32_t* tq;
+  const int32_t* off;      // [K-1]
+  const int32_t* len;      // [K-1]
 };
 
 // Layouts understood by the state gather kernel.

@@ -188,8 +188,9 @@ __global__ void k_plain_sweep(PlainDev P, int t, int g0, int g1) {
   const int g = g0 + gl;
   const int gw = P.grp[g];
   const int cnt = (gw >> kGroupCountShift) + 1;
-  const int len = P.tq_len[t];
-  const uint32_t* row = P.tq + P.tq_off[t];
+  const int ri = P.temp ? P.temp[r] : t;  // parallel tempering: its temperature's row
+  const int len = P.tq_len[ri];
+  const uint32_t* row = P.tq + P.tq_off[ri];
   const bool snap = P.snap[r] == t - 1;
   int s[4], k[4];
   bool need = false;
@@ -382,27 +383,6 @@ __device__ __forceinline__ void push_group_prefetched(int32_t* st, const GLOBAL_
   }
 }
 
-__device__ __forceinline__ void push_group_global(int32_t* st, const GLOBAL_AS i32x2* __restrict__ aw,
-                                                  int base, uint32_t dg, uint32_t fm,
-                                                  const int (&w)[4]) {
-  int o = base;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int d = (int)((dg >> (8 * j)) & 255u);
-    if ((fm >> j) & 1u) {
-      const int sgn4 = (w[j] & 1) ? -4 : 4;
-      for (int e0 = 0; e0 < d; e0 += 4) {
-        i32x2 q[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) q[i] = aw[o + min(e0 + i, d - 1)];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) atomicAdd(&st[q[i].x], e0 + i < d ? sgn4 * q[i].y : 0);
-      }
-    }
-    o += d;
-  }
-}
-
 // Pushes of one flipped vertex described by a flip-list entry:
 // bits 0..16 = first adjacency entry, 17..24 = degree, 25 = new spin is +1.
 __device__ __forceinline__ void push_entry(int32_t* st, const uint16_t* adj16, uint32_t e) {
@@ -573,8 +553,19 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
       }
     }
   }
-  const int CH = J.row_chunk;
-  stage_row_chunk(rows, J.t_begin, min(CH, J.t_end - J.t_begin), U.tq, RW);
+  // Parallel tempering: replica rl's row is its temperature's for the
+  // whole launch (the exchanges happen between launches), staged once at
+  // U.tq + rl RW; the chunk is never restaged.
+  const bool pt = J.temp != nullptr;
+  const int CH = pt ? 0x7FFFFFFF : J.row_chunk;
+  if (pt) {
+    for (int i = tid; i < G * RW; i += BLOCK) {
+      const int q = i / RW, rq = block * G + q;
+      U.tq[i] = rq < J.R ? rows[(int64_t)J.temp[rq] * RW + (i - q * RW)] : 0u;
+    }
+  } else {
+    stage_row_chunk(rows, J.t_begin, min(CH, J.t_end - J.t_begin), U.tq, RW);
+  }
   for (int i = tid; i < 2 * C; i += BLOCK) U.cls[i] = gconst(J.cls)[i];
   stage_groups(J, U);
   if (ADJ == kAdjLds) {
@@ -705,7 +696,8 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   // largest acceptable bond count plus one (degree-4 rows).  The next
   // sweep's is read during the last pass, so no LDS read is pending when a
   // sweep starts.
-  int len2_next = (int)U.tq[RW - 1];
+  const int row_of_replica = pt ? rl : 0;
+  int len2_next = (int)U.tq[row_of_replica * RW + RW - 1];
   for (int t = J.t_begin; t < J.t_end; ++t) {
     if (tc == CH) {
       stage_row_chunk(rows, t, min(CH, J.t_end - t), U.tq, RW);
@@ -713,7 +705,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
       __syncthreads();
       len2_next = (int)U.tq[RW - 1];
     }
-    const uint32_t* row = U.tq + tc * RW;
+    const uint32_t* row = U.tq + (pt ? row_of_replica : tc) * RW;
     const int len2 = len2_next;
     ++tc;
     for (int c = 0; c < C; ++c) {
@@ -857,7 +849,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
         if ((tid & 63) == 0 && s != 0) atomicAdd(&sh.eacc[t % 3][rl], s);
         dk = 0;
         nacc_mark = nacc;
-        if (tc < CH) len2_next = (int)U.tq[tc * RW + RW - 1];
+        if (tc < CH) len2_next = (int)U.tq[(pt ? row_of_replica : tc) * RW + RW - 1];
       }
       __syncthreads();
     }
@@ -1317,6 +1309,50 @@ __global__ void k_fill_i32(int32_t* p, int32_t value, int64_t count) {
   if (i < count) p[i] = value;
 }
 
+// ================================================================ tempering
+// Start of a tempering run: replica set K + k at temperature k, no
+// exchanges yet.
+__global__ void k_pt_init(SwapDev X) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int R = X.K * X.n_sets;
+  if (i < R) {
+    X.temp[i] = i % X.K;
+    X.slot[i] = i;
+  }
+  if (i < X.n_sets * (X.K - 1)) X.swaps[i] = 0;
+}
+
+// Exchange round m: pairs (k, k+1) with k of m's parity, one lane per pair
+// and set (the pairs of a round are disjoint).  The replicas a (at k) and b
+// (at k+1) exchange temperatures with the Metropolis probability of the
+// product of Boltzmann weights, min(1, exp(-(beta_k+1 - beta_k)(E_a - E_b))):
+// always when q = (E_a - E_b) / 2 <= 0 (energies of one problem differ by an
+// even number), else when the round's draw is below the quantised
+// threshold of q.
+__global__ void k_swap(SwapDev X, int m) {
+  const int per_set = (X.K - (m & 1)) / 2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (per_set <= 0 || i >= X.n_sets * per_set) return;
+  const int set = i / per_set;
+  const int k = (m & 1) + 2 * (i - set * per_set);
+  int32_t* sl = X.slot + set * X.K;
+  const int a = sl[k], b = sl[k + 1];
+  const int q = (X.energy[a] - X.energy[b]) / 2;
+  bool accept = q <= 0;
+  if (!accept) {
+    const int len = X.len[k];
+    const uint4 x = philox10((uint32_t)m, (uint32_t)k, (uint32_t)set, kTagSwap, X.seed_lo, X.seed_hi);
+    accept = len < 0 || (q <= len && x.x <= X.tq[X.off[k] + q - 1]);
+  }
+  if (accept) {
+    sl[k] = b;
+    sl[k + 1] = a;
+    X.temp[a] = k + 1;
+    X.temp[b] = k;
+    ++X.swaps[set * (X.K - 1) + k];
+  }
+}
+
 template <int BLOCK>
 hipError_t launch_field_t(const LaunchPersistent& L, hipStream_t s) {
   switch (L.adj) {
@@ -1389,6 +1425,10 @@ hipError_t launch_plain_anneal(const PlainDev& P, const PlainPlan& plan, hipStre
                            s, P, t, g0, g1);
     }
     hipLaunchKernelGGL(k_plain_eos, dim3(blocks_for(P.R, B)), dim3(B), 0, s, P, t, plan.S);
+    if (plan.swap && (t + 1) % plan.swap_every == 0) {
+      const hipError_t e = launch_swap(*plan.swap, (t + 1) / plan.swap_every - 1, s);
+      if (e != hipSuccess) return e;
+    }
   }
   hipLaunchKernelGGL(k_plain_flush, dim3(blocks_for((int64_t)P.n_pad * P.R, B)), dim3(B), 0, s, P,
                      plan.S - 1);
@@ -1455,6 +1495,19 @@ hipError_t launch_gather(const void* buf, int layout, int R, int n_pad, int r, c
                          int n, int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, 256)), dim3(256), 0, s, buf, layout, R, n_pad, r,
                      pos, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pt_init(const SwapDev& X, hipStream_t s) {
+  const int n = X.K * X.n_sets;
+  hipLaunchKernelGGL(k_pt_init, dim3(blocks_for(n, 256)), dim3(256), 0, s, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_swap(const SwapDev& X, int m, hipStream_t s) {
+  const int pairs = X.n_sets * ((X.K - (m & 1)) / 2);
+  if (pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_swap, dim3(blocks_for(pairs, 256)), dim3(256), 0, s, X, m);
   return hipGetLastError();
 }
 

@@ -201,8 +201,18 @@ struct JobSpec {
   int t_begin, t_end;
 };
 
+// Parallel tempering of a single job: sweeps [0, S) in segments that end
+// at every P-th sweep, each followed by exchange round t_end / P - 1.
+struct TemperPlan {
+  int S, P;
+  const SwapDev* swap;
+};
+
 int run_persistent(Launcher& L, const std::vector<JobSpec>& jobs, const PersistentConfig& cfg,
-                   hipStream_t stream, bool use_graph);
+                   hipStream_t stream, bool use_graph, const TemperPlan* pt = nullptr);
+// Largest replicas_per_block whose rows a FIELD tempering launch can stage
+// (one row per replica of a block).
+int temper_max_group(const Table& t);
 int prepare_run(ising_problem* p, const Table& table, int R, const PersistentConfig& cfg,
                 hipStream_t stream);
 // Device bytes of one run's buffers.
@@ -224,11 +234,26 @@ int msc_planes(int max_deg);
 
 }  // namespace ising
 
+// Parallel tempering state of a problem: the ladder's tables and the
+// exchange arrays of the last run.
+struct TemperState {
+  ising::DeviceArena arena;
+  std::vector<double> betas;      // ladder the tables were built for
+  ising::Table rows;              // flip thresholds, one row per temperature
+  ising::Table swap;              // exchange thresholds, one row per pair
+  std::vector<uint32_t> swap_tq;  // host copies behind the async uploads
+  std::vector<int32_t> swap_off, swap_len;
+  ising::SwapDev dev{};
+  int32_t K = 0, n_sets = 0, S = 0, P = 0;
+  bool valid = false;             // the last run of the problem was tempering
+};
+
 struct ising_problem {
   ising::HostGraph g;
   ising::DevGraph dg;
   ising::RunBuffers run;
   ising::Launcher launcher;
+  TemperState temper;
   std::vector<int8_t> init;  // [init_R][n] original order
   int32_t init_R = 0;
   bool trace = false;
@@ -240,3 +265,10 @@ struct ising_problem {
     ising::Table table;
   } sched;
 };
+
+// Arguments of the per-pass kernels for a run of p in b (anneal.cpp).
+ising::PlainDev make_plain(const ising_problem* p, const ising::RunBuffers& b, int R, uint64_t seed);
+// Launch configuration of tuning t (NULL or ISING_PATH_AUTO: the tuned or
+// heuristic choice), checked against the problem.
+int resolve_config(ising_problem* p, const ising::Table& table, int R, const ising_tuning* t,
+                   ising::PersistentConfig& cfg);

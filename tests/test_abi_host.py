@@ -196,3 +196,18 @@ def test_degree4_labels_need_degree4_unit_weights():
         with pytest.raises(B.IsingError) as e:
             p.neighbour_labels()
         assert e.value.status == B.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("betas,n_sets,S,P", [([], 1, 10, 1), ([0.5, 0.4], 1, 10, 1),
+                                               ([0.1, float("nan")], 1, 10, 1), ([-0.1], 1, 10, 1),
+                                               ([0.1], 0, 10, 1), ([0.1], 1, 0, 1), ([0.1], 1, 10, 0)])
+def test_temper_rejects_bad_ladders(betas, n_sets, S, P):
+    """Tempering arguments are checked before any device work."""
+    p = B.Problem.from_instance(I.torus(6, 6, 1))
+    with pytest.raises(B.IsingError) as e:
+        p.temper(betas, n_sets, S, P, 1)
+    assert e.value.status == B.ERR_INVALID
+    with pytest.raises(B.IsingError) as e:
+        p.temper_results()
+    assert e.value.status == B.ERR_STATE
+    p.close()
