@@ -92,6 +92,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-torus batch leg")
     ap.add_argument("--no-random", action="store_true", help="skip the sparse random graph leg")
+    ap.add_argument("--no-temper", action="store_true", help="skip the parallel tempering leg")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests of the Poisson serving leg (0 = skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
@@ -270,6 +271,59 @@ def main():
                     "ttt_plain_s": ttt.replica_ttt(per3, target, plain3_s, S3)["ttt_s"]}
         p3.close()
 
+    # ------------------------------------------------------------ tempering leg
+    # Parallel tempering on the benchmark torus: 8 sets of 32 temperatures
+    # (geometric 0.2 -> 3.0, 256 replicas), 4000 sweeps, an exchange round
+    # every 10 sweeps (and every 100, for the cost of the segment launches),
+    # the plain form on the same seeds; trial = one set for time to target.
+    temper_leg = None
+    if not args.no_temper:
+        K, n_sets, P = 32, 8, 10
+        ladder = list(np.geomspace(0.2, 3.0, K))
+        pt_att = inst.n * K * n_sets * S
+
+        def temper_run(P_, tuning=None, reps=2):
+            prob.temper(ladder, n_sets, S, P_, SEED, tuning, stream=stream)  # warm (captures)
+            prob.cut()
+            walls_t = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                prob.temper(ladder, n_sets, S, P_, SEED, tuning, stream=stream)
+                r_ = prob.cut()
+                walls_t.append(time.perf_counter() - t)
+            return r_, float(np.mean(walls_t)) * 1e3, prob.last_anneal_ms()
+
+        res_t, ms_t, kern_t = temper_run(P)
+        temp_t, swaps_t = prob.temper_results()
+        per_t = res_t.per_replica.copy()
+        path_t = B.ising_last_run_info(prob.handle)[2]
+        _, ms_t100, kern_t100 = temper_run(100)
+        t = time.perf_counter()
+        prob.temper(ladder, n_sets, S, P, SEED, B.Tuning(B.PATH_PLAIN, 1, 256, 0), stream=stream)
+        res_tp = prob.cut()
+        plain_t_ms = (time.perf_counter() - t) * 1e3
+        assert np.array_equal(res_tp.per_replica, per_t), "plain and persistent tempering disagree"
+        tries = np.array([len(range(k % 2, S // P, 2)) for k in range(K - 1)], np.float64)
+        rate = swaps_t.sum(axis=0) / (tries * n_sets)
+        temper_leg = {"workload": f"torus 100x80, {n_sets} sets x {K} temperatures geometric 0.2->3.0, "
+                                  f"{S} sweeps, exchange every {P}",
+                      "attempts_per_s": pt_att / (ms_t / 1e3), "ms_per_run": ms_t, "kernel_ms": kern_t,
+                      "ms_per_run_exchange_every_100": ms_t100, "kernel_ms_exchange_every_100": kern_t100,
+                      "plain_ms": plain_t_ms, "speedup_vs_plain": plain_t_ms / ms_t,
+                      "path": {1: "plain", 2: "field", 3: "msc"}.get(path_t, str(path_t)),
+                      "best_cut": int(res_t.best_cut),
+                      "exchange_rate": {"min": float(rate.min()), "mean": float(rate.mean()),
+                                        "max": float(rate.max())}}
+        if c_ref is not None:
+            set_best = per_t.reshape(n_sets, K).max(axis=1)
+            temper_leg["ttt"] = {}
+            for q in (0.995, 0.998, 1.0):
+                target = ttt.target_cut(c_ref, q)
+                tf = ttt.replica_ttt(set_best, target, ms_t / 1e3, S)
+                temper_leg["ttt"][str(q)] = {"target": target, "ps_sets": tf["ps"],
+                                             "ttt_s": tf["ttt_s"]}
+
     # ------------------------------------------------------------ serving leg
     serving = None
     if args.serve_requests > 0:
@@ -339,6 +393,7 @@ def main():
         "ttt": ttt_rows,
         "batch": batch,
         "random_graph": random_leg,
+        "tempering": temper_leg,
         "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -683,17 +683,22 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   lp.planes = planes;
   lp.adj = form;
 
+  // An exchange round also clears the list cursors for the next segment.
   auto enqueue = [&](hipStream_t s) -> hipError_t {
+    bool cleared = false;
     for (int i = 0; i < n_segs; ++i) {
-      hipError_t e = launch_fill_i32(L.ctr_d, 0, 8, s);
+      hipError_t e = hipSuccess;
+      if (!cleared) e = launch_fill_i32(L.ctr_d, 0, 8, s);
       if (e != hipSuccess) return e;
       LaunchPersistent li = lp;
       li.jobs = L.jobs_d + (pt ? i : 0);
       e = cfg.path == ISING_PATH_MSC ? launch_msc(li, cfg.block, s) : launch_field(li, cfg.block, s);
       if (e != hipSuccess) return e;
+      cleared = false;
       if (pt && segs[(size_t)i].y % pt->P == 0) {
-        e = launch_swap(*pt->swap, segs[(size_t)i].y / pt->P - 1, s);
+        e = launch_swap(*pt->swap, segs[(size_t)i].y / pt->P - 1, L.ctr_d, s);
         if (e != hipSuccess) return e;
+        cleared = true;
       }
     }
     return launch_argmax(L.jobs_d, n_jobs, s);

@@ -47,9 +47,10 @@ hipError_t launch_argmax(const JobDev* jobs, int n_jobs, hipStream_t s);
 hipError_t launch_gather(const void* buf, int layout, int R, int n_pad, int r, const int32_t* pos,
                          int n, int32_t* out, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t s);
-// Parallel tempering: initial ladders, and exchange round m.
+// Parallel tempering: initial ladders, and exchange round m (which also
+// zeroes clear8[0..7] when given).
 hipError_t launch_pt_init(const SwapDev& X, hipStream_t s);
-hipError_t launch_swap(const SwapDev& X, int m, hipStream_t s);
+hipError_t launch_swap(const SwapDev& X, int m, int32_t* clear8, hipStream_t s);
 
 // Static LDS of the persistent kernels (bytes), for the LDS budget.
 constexpr size_t kFieldStaticLds = 512;

@@ -302,19 +302,39 @@ __device__ __forceinline__ void place_flip_lists(UnitLds& u, int m) {
 }
 
 // Compact adjacency of a unit-weight graph with fewer than 2^15 positions.
+// Global -> LDS copy of n elements, dst[i] = f(src[i]), with eight loads of
+// every thread in flight at a time: a plain strided loop waits for each
+// load before it issues the next, and a unit's staging would then cost one
+// memory latency per element per thread.
+template <class T, class D, class F>
+__device__ __forceinline__ void copy_in(D* dst, const T* src, int n, F f) {
+  const GLOBAL_AS T* s = gconst(src);
+  const int nt = (int)blockDim.x;
+  for (int i0 = (int)threadIdx.x; i0 < n; i0 += 8 * nt) {
+    // indices past the end re-read the last element (every load is
+    // unconditional, so the values stay in registers)
+    T v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = s[min(i0 + k * nt, n - 1)];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (i0 + k * nt < n) dst[i0 + k * nt] = f(v[k]);
+  }
+}
+template <class T>
+__device__ __forceinline__ void copy_in(T* dst, const T* src, int n) {
+  copy_in(dst, src, n, [](const T& x) { return x; });
+}
+
 __device__ __forceinline__ void stage_adjacency(const JobDev& J, const UnitLds& u) {
-  const GLOBAL_AS uint32_t* adjm = gconst(J.adjm);
-  const int n = 2 * J.M;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) u.adj16[i] = (uint16_t)adjm[i];
+  copy_in(u.adj16, J.adjm, 2 * J.M, [](uint32_t x) { return (uint16_t)x; });
 }
 
 // Degree-4 form: the unit's copy of the 48-byte group blocks
 // (kDeg4BlockWords), built on the host.
 __device__ __forceinline__ void stage_adjacency_deg4(const JobDev& J, UnitLds& u) {
-  const GLOBAL_AS u32x4* src = gconst(reinterpret_cast<const u32x4*>(J.adj4));
-  u32x4* dst = reinterpret_cast<u32x4*>(u.adj16);
-  const int n = 3 * (J.n_pad >> 2);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  copy_in(reinterpret_cast<u32x4*>(u.adj16), reinterpret_cast<const u32x4*>(J.adj4),
+          3 * (J.n_pad >> 2));
 }
 
 __device__ __forceinline__ void stage_row(const JobDev& J, int t, uint32_t* buf) {
@@ -328,8 +348,7 @@ __device__ __forceinline__ void stage_row(const JobDev& J, int t, uint32_t* buf)
 // t .. t+n-1, one contiguous copy.
 __device__ __forceinline__ void stage_row_chunk(const uint32_t* rows, int t, int n, uint32_t* buf,
                                                 int rw) {
-  const GLOBAL_AS uint32_t* src = gconst(rows) + (int64_t)t * rw;
-  for (int i = threadIdx.x; i < n * rw; i += blockDim.x) buf[i] = src[i];
+  copy_in(buf, rows + (int64_t)t * rw, n * rw);
 }
 
 __device__ __forceinline__ void stage_groups(const JobDev& J, const UnitLds& u) {
@@ -337,20 +356,50 @@ __device__ __forceinline__ void stage_groups(const JobDev& J, const UnitLds& u) 
   const GLOBAL_AS int32_t* grp = gconst(J.grp);
   const GLOBAL_AS int32_t* gbase = gconst(J.gbase);
   const GLOBAL_AS uint32_t* gdeg = gconst(J.gdeg);
-  for (int i = threadIdx.x; i < n_grp; i += blockDim.x) {
-    u.gword[i] = grp[i];
-    u.gbase[i] = gbase[i];
-    u.gdeg[i] = gdeg[i];
+  const int nt = (int)blockDim.x;
+  for (int i0 = (int)threadIdx.x; i0 < n_grp; i0 += 4 * nt) {
+    int32_t a[4], b[4];
+    uint32_t c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = min(i0 + k * nt, n_grp - 1);
+      a[k] = grp[i];
+      b[k] = gbase[i];
+      c[k] = gdeg[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i0 + k * nt < n_grp) {
+        u.gword[i0 + k * nt] = a[k];
+        u.gbase[i0 + k * nt] = b[k];
+        u.gdeg[i0 + k * nt] = c[k];
+      }
   }
 }
 
 __device__ __forceinline__ int next_unit(const int32_t* list_off, int32_t* ctr, int& tried) {
   const int home = blockIdx.x & 7;
-  while (tried < 8) {
+  if (tried == 0) {
+    const int i = atomicAdd(&ctr[home], 1);
+    if (list_off[home] + i < list_off[home + 1]) return list_off[home] + i;
+    tried = 1;
+  }
+  // The other lists' cursors, read together: a cursor that has passed its
+  // list's end stays there (cursors only grow), so such a list needs no
+  // claim.  At the end of a launch this costs one memory round trip instead
+  // of one atomic per list.
+  int c[7];
+#pragma unroll
+  for (int k = 1; k < 8; ++k)
+    c[k - 1] = __hip_atomic_load(&ctr[(home + k) & 7], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (; tried < 8; ++tried) {
     const int L = (home + tried) & 7;
+    int seen = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) seen = k == tried ? c[k - 1] : seen;
+    if (list_off[L] + seen >= list_off[L + 1]) continue;
     const int i = atomicAdd(&ctr[L], 1);
     if (list_off[L] + i < list_off[L + 1]) return list_off[L] + i;
-    ++tried;
   }
   return -1;
 }
@@ -521,7 +570,39 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
 
   // ---- state in: initial draw, or the words saved by the previous chunk
   const bool fresh = J.t_begin == 0;
-  if (live) {
+  auto put_group = [&](int g, const int4& w4) {
+    if (SOA) {
+      st[widx(g, 0)] = w4.x;
+      st[widx(g, 1)] = w4.y;
+      st[widx(g, 2)] = w4.z;
+      st[widx(g, 3)] = w4.w;
+    } else {
+      *reinterpret_cast<int4*>(st + 4 * g) = w4;
+    }
+  };
+  // a resumed chunk's per-replica scalars, loaded with its state
+  int E_in = 0, best_cut_in = 0, best_sweep_in = 0;
+  unsigned long long acc_in = 0;
+  if (live && !fresh) {
+    E_in = J.energy[r];
+    best_cut_in = J.best_cut[r];
+    best_sweep_in = J.best_sweep[r];
+    acc_in = J.accepts[r];
+  }
+  if (live && !fresh) {
+    // four loads of each lane in flight at a time
+    const GLOBAL_AS u32x4* sv = gconst(reinterpret_cast<const u32x4*>(J.save + (int64_t)r * n_pad));
+    for (int g0 = lt; g0 < n_grp; g0 += 4 * TPR) {
+      u32x4 v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = sv[min(g0 + k * TPR, n_grp - 1)];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (g0 + k * TPR < n_grp)
+          put_group(g0 + k * TPR, make_int4((int)v[k].x, (int)v[k].y, (int)v[k].z, (int)v[k].w));
+    }
+  }
+  if (live && fresh) {
     for (int g = lt; g < n_grp; g += TPR) {
       int4 w4;
       if (fresh) {
@@ -540,17 +621,8 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
         w4.y = cnt > 1 ? (int)((bits >> 1) & 1u) : kPadWord;
         w4.z = cnt > 2 ? (int)((bits >> 2) & 1u) : kPadWord;
         w4.w = cnt > 3 ? (int)((bits >> 3) & 1u) : kPadWord;
-      } else {
-        w4 = *reinterpret_cast<const int4*>(J.save + (int64_t)r * n_pad + 4 * g);
       }
-      if (SOA) {
-        st[widx(g, 0)] = w4.x;
-        st[widx(g, 1)] = w4.y;
-        st[widx(g, 2)] = w4.z;
-        st[widx(g, 3)] = w4.w;
-      } else {
-        *reinterpret_cast<int4*>(st + 4 * g) = w4;
-      }
+      put_group(g, w4);
     }
   }
   // Parallel tempering: replica rl's row is its temperature's for the
@@ -566,7 +638,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   } else {
     stage_row_chunk(rows, J.t_begin, min(CH, J.t_end - J.t_begin), U.tq, RW);
   }
-  for (int i = tid; i < 2 * C; i += BLOCK) U.cls[i] = gconst(J.cls)[i];
+  copy_in(U.cls, J.cls, 2 * C);
   stage_groups(J, U);
   if (ADJ == kAdjLds) {
     stage_adjacency(J, U);
@@ -663,13 +735,10 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
     best_sweep = -1;
     snap = true;  // the initial state is written during sweep 0
   } else {
-    E = live ? J.energy[r] : 0;
-    best_cut = live ? J.best_cut[r] : 0;
-    best_sweep = live ? J.best_sweep[r] : 0;
+    E = E_in;
+    best_cut = best_cut_in;
+    best_sweep = best_sweep_in;
     snap = false;
-    // drain these loads here: left pending, their wait would sit inside the
-    // sweep loop and also wait for the snapshot stores of every sweep
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   }
 
   GLOBAL_AS int8_t* best = gmut(static_cast<int8_t*>(J.best)) + (int64_t)r * n_pad;
@@ -893,8 +962,7 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   if ((tid & 63) == 0 && nacc != 0) atomicAdd(&sh.nacc[rl], nacc);
   __syncthreads();
   if (lt == 0 && live) {
-    const unsigned long long prev = fresh ? 0ull : J.accepts[r];
-    J.accepts[r] = prev + (unsigned long long)sh.nacc[rl];
+    J.accepts[r] = acc_in + (unsigned long long)sh.nacc[rl];
     J.energy[r] = E;
     J.best_cut[r] = best_cut;
     J.best_sweep[r] = best_sweep;
@@ -1329,9 +1397,12 @@ __global__ void k_pt_init(SwapDev X) {
 // always when q = (E_a - E_b) / 2 <= 0 (energies of one problem differ by an
 // even number), else when the round's draw is below the quantised
 // threshold of q.
-__global__ void k_swap(SwapDev X, int m) {
+// (Also zeroes clear8[0..7] when given: the persistent launch's list
+// cursors, for the next segment.)
+__global__ void k_swap(SwapDev X, int m, int32_t* clear8) {
   const int per_set = (X.K - (m & 1)) / 2;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (clear8 && i < 8) clear8[i] = 0;
   if (per_set <= 0 || i >= X.n_sets * per_set) return;
   const int set = i / per_set;
   const int k = (m & 1) + 2 * (i - set * per_set);
@@ -1426,7 +1497,7 @@ hipError_t launch_plain_anneal(const PlainDev& P, const PlainPlan& plan, hipStre
     }
     hipLaunchKernelGGL(k_plain_eos, dim3(blocks_for(P.R, B)), dim3(B), 0, s, P, t, plan.S);
     if (plan.swap && (t + 1) % plan.swap_every == 0) {
-      const hipError_t e = launch_swap(*plan.swap, (t + 1) / plan.swap_every - 1, s);
+      const hipError_t e = launch_swap(*plan.swap, (t + 1) / plan.swap_every - 1, nullptr, s);
       if (e != hipSuccess) return e;
     }
   }
@@ -1504,10 +1575,11 @@ hipError_t launch_pt_init(const SwapDev& X, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_swap(const SwapDev& X, int m, hipStream_t s) {
-  const int pairs = X.n_sets * ((X.K - (m & 1)) / 2);
-  if (pairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_swap, dim3(blocks_for(pairs, 256)), dim3(256), 0, s, X, m);
+hipError_t launch_swap(const SwapDev& X, int m, int32_t* clear8, hipStream_t s) {
+  int n = X.n_sets * ((X.K - (m & 1)) / 2);
+  if (clear8 && n < 8) n = 8;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_swap, dim3(blocks_for(n, 256)), dim3(256), 0, s, X, m, clear8);
   return hipGetLastError();
 }
 
