@@ -556,54 +556,153 @@ int oracle_swap_accept(uint64_t seed, uint32_t m, uint32_t k, uint32_t set,
   return (uint64_t)x[0] < oracle_threshold(dbeta, q);
 }
 
+/* Houdayer cluster move (a replica cluster move of the kind the paper
+ * names beside parallel tempering, Sec. II.C): two replicas a and b at the
+ * same temperature disagree on the sites D = {v : s_a(v) != s_b(v)}.  The
+ * connected component of a seed site in the subgraph of the problem graph
+ * induced by D is flipped in both replicas.  Along the cluster's boundary
+ * every edge ends in a site where the two replicas agree, so the boundary
+ * terms of E_a + E_b cancel before and after the flip, and interior edges
+ * keep their terms: E_a + E_b is unchanged, and the move (a symmetric
+ * proposal) is always accepted. */
+static int64_t cluster_bfs(const or_graph* G, const int8_t* sa, const int8_t* sb, int32_t i0,
+                           uint8_t* mark, int32_t* queue) {
+  if (sa[i0] == sb[i0]) return 0;
+  int64_t head = 0, tail = 0;
+  queue[tail++] = i0;
+  mark[i0] = 1;
+  while (head < tail) {
+    const int32_t v = queue[head++];
+    for (int32_t a = G->row[v]; a < G->row[v + 1]; ++a) {
+      const int32_t u = G->nbr[a];
+      if (!mark[u] && sa[u] != sb[u]) {
+        mark[u] = 1;
+        queue[tail++] = u;
+      }
+    }
+  }
+  return tail;
+}
+
+int64_t oracle_cluster(const or_graph_in* gin, const int8_t* sa, const int8_t* sb, int32_t i0,
+                       uint8_t* in_cluster) {
+  if (!gin || !sa || !sb || !in_cluster) return -1;
+  or_graph G;
+  if (graph_build(gin, &G) != 0) {
+    graph_free(&G);
+    return -1;
+  }
+  if (i0 < 0 || i0 >= G.n) {
+    graph_free(&G);
+    return -1;
+  }
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)G.n);
+  memset(in_cluster, 0, (size_t)G.n);
+  const int64_t size = cluster_bfs(&G, sa, sb, i0, in_cluster, queue);
+  free(queue);
+  graph_free(&G);
+  return size;
+}
+
+/* One move on the replica pair (sa, sb) at temperature k of pair p in
+ * round m: the seed is the (u mod |D|)-th site of D in ascending id, u word
+ * 0 of Philox(counter (m, k, p, 4)).  Returns the cluster size (0 when the
+ * replicas agree everywhere: no move).  Fields and energies are recomputed
+ * from scratch. */
+static int64_t houdayer_move(const or_graph* G, uint64_t seed, uint32_t m, uint32_t k, uint32_t p,
+                             int8_t* sa, int8_t* sb, int64_t* ha, int64_t* hb, int64_t* Ea,
+                             int64_t* Eb, uint8_t* mark, int32_t* queue, int64_t* failures) {
+  const int32_t n = G->n;
+  int64_t count = 0;
+  for (int32_t v = 0; v < n; ++v) count += sa[v] != sb[v];
+  if (count == 0) return 0;
+  uint32_t ctr[4] = {m, k, p, 4};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t x[4];
+  oracle_philox4x32_10(ctr, key, x);
+  int64_t j = (int64_t)((uint64_t)x[0] % (uint64_t)count);
+  int32_t i0 = 0;
+  for (int32_t v = 0; v < n; ++v)
+    if (sa[v] != sb[v] && j-- == 0) {
+      i0 = v;
+      break;
+    }
+  const int64_t size = cluster_bfs(G, sa, sb, i0, mark, queue);
+  for (int32_t v = 0; v < n; ++v)
+    if (mark[v]) {
+      sa[v] = (int8_t)-sa[v];
+      sb[v] = (int8_t)-sb[v];
+      mark[v] = 0;
+    }
+  const int64_t before = *Ea + *Eb;
+  fields_from_scratch(G, sa, ha);
+  fields_from_scratch(G, sb, hb);
+  *Ea = energy_from_scratch(G, sa);
+  *Eb = energy_from_scratch(G, sb);
+  if (*Ea + *Eb != before) ++*failures;  /* the move keeps E_a + E_b */
+  return size;
+}
+
 typedef struct {
   const or_graph* G;
   const or_temper_in* pt;
   or_temper_out* out;
-  int32_t first, stride; /* sets first, first+stride, ... below end */
+  int32_t first, stride; /* groups first, first+stride, ... below end */
   int32_t end;
+  int32_t per_group;     /* sets per group: 2 with cluster moves, else 1 */
+  int64_t failures;      /* cluster moves that changed E_a + E_b */
   int status;
 } temper_arg;
 
-static void temper_set(const temper_arg* A, int32_t set, int8_t* s, int64_t* h,
-                       uint64_t* tq, int32_t* order, int32_t* drawn_at,
-                       int64_t* E, int64_t* best_cut, int32_t* best_sweep,
-                       int64_t* accepts, int32_t* temp, int32_t* slot) {
+typedef struct { /* scratch of one worker, for groups of up to gK replicas */
+  int8_t* s;
+  int64_t* h;
+  uint64_t* tq;
+  int32_t *order, *drawn_at, *best_sweep, *temp, *slot, *queue;
+  int64_t *E, *best_cut, *accepts;
+  uint8_t* mark;
+} temper_scratch;
+
+/* Sets set0 .. set0+ns-1 (ns = 1, or 2 for a cluster-move pair), replicas
+ * j = 0 .. ns K - 1 of the group (global replica set0 K + j). */
+static void temper_group(temper_arg* A, int32_t set0, int32_t ns, const temper_scratch* W) {
   const or_graph* G = A->G;
   const or_temper_in* pt = A->pt;
   or_temper_out* out = A->out;
   const int32_t n = G->n, K = pt->n_temps, S = pt->n_sweeps;
+  const int32_t nr = ns * K;
   const int64_t kmax = G->kmax;
-  const int64_t r0 = (int64_t)set * K;
+  const int64_t r0 = (int64_t)set0 * K;
+  int8_t* s = W->s;
+  int64_t *h = W->h, *E = W->E, *best_cut = W->best_cut, *accepts = W->accepts;
+  int32_t *temp = W->temp, *slot = W->slot, *best_sweep = W->best_sweep;
   int64_t draws = 0;
-  for (int32_t j = 0; j < K; ++j) {
+  for (int32_t j = 0; j < nr; ++j) {
     const int64_t r = r0 + j;
     int8_t* sj = s + (int64_t)j * n;
-    int64_t* hj = h + (int64_t)j * n;
     for (int32_t i = 0; i < n; ++i) {
       if (pt->init_spins)
         sj[i] = pt->init_spins[r * n + i];
       else
         sj[i] = (draw(G, pt->seed, i, 0, (uint32_t)r, 1) >> 31) ? 1 : -1;
     }
-    fields_from_scratch(G, sj, hj);
+    fields_from_scratch(G, sj, h + (int64_t)j * n);
     E[j] = energy_from_scratch(G, sj);
     best_cut[j] = (G->W - E[j]) / 2;
     best_sweep[j] = -1;
     accepts[j] = 0;
-    temp[j] = j;
+    temp[j] = j % K;  /* slot[q K + k]: replica of set q of the group at k */
     slot[j] = j;
     if (out->best_state) memcpy(out->best_state + r * n, sj, (size_t)n);
   }
-  /* thresholds of every temperature, [K][kmax + 1] */
   for (int32_t k = 0; k < K; ++k)
-    for (int64_t d = 1; d <= kmax; ++d) tq[(int64_t)k * (kmax + 1) + d] = oracle_threshold(pt->betas[k], d);
+    for (int64_t d = 1; d <= kmax; ++d) W->tq[(int64_t)k * (kmax + 1) + d] = oracle_threshold(pt->betas[k], d);
   for (int32_t t = 0; t < S; ++t) {
-    for (int32_t j = 0; j < K; ++j) {
+    for (int32_t j = 0; j < nr; ++j) {
       int8_t* sj = s + (int64_t)j * n;
-      for (int32_t i = 0; i < n; ++i) drawn_at[i] = -1;
-      sweep_once(G, pt->seed, t, (int32_t)(r0 + j), tq + (int64_t)temp[j] * (kmax + 1), sj,
-                 h + (int64_t)j * n, &E[j], &accepts[j], &draws, drawn_at, order, NULL);
+      for (int32_t i = 0; i < n; ++i) W->drawn_at[i] = -1;
+      sweep_once(G, pt->seed, t, (int32_t)(r0 + j), W->tq + (int64_t)temp[j] * (kmax + 1), sj,
+                 h + (int64_t)j * n, &E[j], &accepts[j], &draws, W->drawn_at, W->order, NULL);
       const int64_t cut = (G->W - E[j]) / 2;
       if (cut > best_cut[j]) {
         best_cut[j] = cut;
@@ -613,23 +712,43 @@ static void temper_set(const temper_arg* A, int32_t set, int8_t* s, int64_t* h,
     }
     if ((t + 1) % pt->swap_every == 0) {
       const int32_t m = (t + 1) / pt->swap_every - 1;
-      for (int32_t k = m & 1; k + 1 < K; k += 2) {
-        const int32_t a = slot[k], b = slot[k + 1];
-        if (oracle_swap_accept(pt->seed, (uint32_t)m, (uint32_t)k, (uint32_t)set, E[a], E[b],
-                               pt->betas[k], pt->betas[k + 1])) {
-          slot[k] = b;
-          slot[k + 1] = a;
-          temp[a] = k + 1;
-          temp[b] = k;
-          out->swaps[(int64_t)set * (K - 1) + k]++;
+      /* cluster moves between the two sets of a pair, then the exchanges */
+      if (pt->cluster_moves && ns == 2) {
+        const int32_t pair = set0 / 2;
+        for (int32_t k = pt->cluster_from; k < K; ++k) {
+          const int32_t a = slot[k], b = slot[K + k];
+          const int64_t size = houdayer_move(G, pt->seed, (uint32_t)m, (uint32_t)k, (uint32_t)pair,
+                                             s + (int64_t)a * n, s + (int64_t)b * n, h + (int64_t)a * n,
+                                             h + (int64_t)b * n, &E[a], &E[b], W->mark, W->queue,
+                                             &A->failures);
+          if (size > 0) {
+            out->cluster_moves[(int64_t)pair * K + k]++;
+            out->cluster_sites[(int64_t)pair * K + k] += size;
+          }
+        }
+      }
+      for (int32_t q = 0; q < ns; ++q) {
+        int32_t* sl = slot + q * K;
+        const int32_t set = set0 + q;
+        for (int32_t k = m & 1; k + 1 < K; k += 2) {
+          const int32_t a = sl[k], b = sl[k + 1];
+          if (oracle_swap_accept(pt->seed, (uint32_t)m, (uint32_t)k, (uint32_t)set, E[a], E[b],
+                                 pt->betas[k], pt->betas[k + 1])) {
+            sl[k] = b;
+            sl[k + 1] = a;
+            temp[a] = k + 1;
+            temp[b] = k;
+            out->swaps[(int64_t)set * (K - 1) + k]++;
+          }
         }
       }
     }
     if (out->temp_energy)
-      for (int32_t k = 0; k < K; ++k)
-        out->temp_energy[((int64_t)set * S + t) * K + k] = E[slot[k]];
+      for (int32_t q = 0; q < ns; ++q)
+        for (int32_t k = 0; k < K; ++k)
+          out->temp_energy[((int64_t)(set0 + q) * S + t) * K + k] = E[slot[q * K + k]];
   }
-  for (int32_t j = 0; j < K; ++j) {
+  for (int32_t j = 0; j < nr; ++j) {
     const int64_t r = r0 + j;
     out->best_cut[r] = best_cut[j];
     out->best_sweep[r] = best_sweep[j];
@@ -642,38 +761,46 @@ static void temper_set(const temper_arg* A, int32_t set, int8_t* s, int64_t* h,
 
 static void* temper_worker(void* p) {
   temper_arg* A = (temper_arg*)p;
-  const int32_t n = A->G->n, K = A->pt->n_temps;
+  const int32_t n = A->G->n, K = A->pt->n_temps, g = A->per_group;
   const int64_t kmax = A->G->kmax;
-  int8_t* s = (int8_t*)malloc((size_t)K * (size_t)n);
-  int64_t* h = (int64_t*)malloc(sizeof(int64_t) * (size_t)K * (size_t)n);
-  uint64_t* tq = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)K * (size_t)(kmax + 1));
-  int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-  int32_t* drawn_at = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-  int64_t* E = (int64_t*)malloc(sizeof(int64_t) * (size_t)K);
-  int64_t* best_cut = (int64_t*)malloc(sizeof(int64_t) * (size_t)K);
-  int32_t* best_sweep = (int32_t*)malloc(sizeof(int32_t) * (size_t)K);
-  int64_t* accepts = (int64_t*)malloc(sizeof(int64_t) * (size_t)K);
-  int32_t* temp = (int32_t*)malloc(sizeof(int32_t) * (size_t)K);
-  int32_t* slot = (int32_t*)malloc(sizeof(int32_t) * (size_t)K);
-  if (!s || !h || !tq || !order || !drawn_at || !E || !best_cut || !best_sweep || !accepts ||
-      !temp || !slot) {
+  const size_t nr = (size_t)g * (size_t)K;
+  temper_scratch W;
+  W.s = (int8_t*)malloc(nr * (size_t)n);
+  W.h = (int64_t*)malloc(sizeof(int64_t) * nr * (size_t)n);
+  W.tq = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)K * (size_t)(kmax + 1));
+  W.order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  W.drawn_at = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  W.queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  W.mark = (uint8_t*)calloc((size_t)n, 1);
+  W.E = (int64_t*)malloc(sizeof(int64_t) * nr);
+  W.best_cut = (int64_t*)malloc(sizeof(int64_t) * nr);
+  W.accepts = (int64_t*)malloc(sizeof(int64_t) * nr);
+  W.best_sweep = (int32_t*)malloc(sizeof(int32_t) * nr);
+  W.temp = (int32_t*)malloc(sizeof(int32_t) * nr);
+  W.slot = (int32_t*)malloc(sizeof(int32_t) * nr);
+  if (!W.s || !W.h || !W.tq || !W.order || !W.drawn_at || !W.queue || !W.mark || !W.E ||
+      !W.best_cut || !W.accepts || !W.best_sweep || !W.temp || !W.slot) {
     A->status = -1;
   } else {
-    for (int32_t set = A->first; set < A->end; set += A->stride)
-      temper_set(A, set, s, h, tq, order, drawn_at, E, best_cut, best_sweep, accepts, temp,
-                 slot);
+    for (int32_t grp = A->first; grp < A->end; grp += A->stride) {
+      const int32_t set0 = grp * g;
+      const int32_t ns = set0 + g <= A->pt->n_sets ? g : A->pt->n_sets - set0;
+      temper_group(A, set0, ns, &W);
+    }
   }
-  free(s);
-  free(h);
-  free(tq);
-  free(order);
-  free(drawn_at);
-  free(E);
-  free(best_cut);
-  free(best_sweep);
-  free(accepts);
-  free(temp);
-  free(slot);
+  free(W.s);
+  free(W.h);
+  free(W.tq);
+  free(W.order);
+  free(W.drawn_at);
+  free(W.queue);
+  free(W.mark);
+  free(W.E);
+  free(W.best_cut);
+  free(W.accepts);
+  free(W.best_sweep);
+  free(W.temp);
+  free(W.slot);
   return NULL;
 }
 
@@ -688,29 +815,40 @@ int oracle_temper(const or_graph_in* gin, const or_temper_in* pt, or_temper_out*
     if (!isfinite(pt->betas[k]) || pt->betas[k] < 0) return -1;
     if (k > 0 && pt->betas[k] < pt->betas[k - 1]) return -1;
   }
+  const int32_t g = pt->cluster_moves ? 2 : 1;
+  if (pt->cluster_moves &&
+      (pt->cluster_from < 0 || pt->cluster_from > pt->n_temps || !out->cluster_moves ||
+       !out->cluster_sites))
+    return -1;
+  int32_t s0 = pt->set_begin, s1 = pt->set_end;
+  if (s0 == 0 && s1 == 0) s1 = pt->n_sets;
+  if (s0 < 0 || s1 > pt->n_sets || s0 >= s1) return -1;
+  /* a cluster-move pair is simulated whole */
+  if (g == 2 && (s0 % 2 != 0 || (s1 % 2 != 0 && s1 != pt->n_sets))) return -1;
   or_graph G;
   if (graph_build(gin, &G) != 0) {
     graph_free(&G);
     return -1;
   }
-  int32_t s0 = pt->set_begin, s1 = pt->set_end;
-  if (s0 == 0 && s1 == 0) s1 = pt->n_sets;
-  if (s0 < 0 || s1 > pt->n_sets || s0 >= s1) {
-    graph_free(&G);
-    return -1;
-  }
   memset(out->swaps, 0, sizeof(int64_t) * (size_t)pt->n_sets * (size_t)(pt->n_temps - 1));
+  if (pt->cluster_moves) {
+    const size_t np = (size_t)(pt->n_sets / 2) * (size_t)pt->n_temps;
+    memset(out->cluster_moves, 0, sizeof(int64_t) * np);
+    memset(out->cluster_sites, 0, sizeof(int64_t) * np);
+  }
+  const int32_t g0 = s0 / g, g1 = (s1 + g - 1) / g;
   int32_t nt = pt->n_threads < 1 ? 1 : pt->n_threads;
-  if (nt > s1 - s0) nt = s1 - s0;
+  if (nt > g1 - g0) nt = g1 - g0;
   temper_arg* args = (temper_arg*)calloc((size_t)nt, sizeof(temper_arg));
   pthread_t* th = (pthread_t*)calloc((size_t)nt, sizeof(pthread_t));
   for (int32_t i = 0; i < nt; ++i) {
     args[i].G = &G;
     args[i].pt = pt;
     args[i].out = out;
-    args[i].first = s0 + i;
+    args[i].first = g0 + i;
     args[i].stride = nt;
-    args[i].end = s1;
+    args[i].end = g1;
+    args[i].per_group = g;
   }
   if (nt == 1) {
     temper_worker(&args[0]);
@@ -719,8 +857,11 @@ int oracle_temper(const or_graph_in* gin, const or_temper_in* pt, or_temper_out*
     for (int32_t i = 0; i < nt; ++i) pthread_join(th[i], NULL);
   }
   int status = 0;
-  for (int32_t i = 0; i < nt; ++i)
+  out->check_failures = 0;
+  for (int32_t i = 0; i < nt; ++i) {
     if (args[i].status) status = -1;
+    out->check_failures += args[i].failures;
+  }
   free(args);
   free(th);
   graph_free(&G);

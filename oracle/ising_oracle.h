@@ -113,6 +113,8 @@ typedef struct {
   int32_t n_threads;        /* host threads over sets (>= 1) */
   int32_t set_begin, set_end; /* simulate sets set_begin .. set_end-1 (both
                                  0: all); outputs stay indexed by replica */
+  int32_t cluster_moves;    /* 1: Houdayer cluster moves (below) */
+  int32_t cluster_from;     /* ... at temperatures k >= cluster_from */
 } or_temper_in;
 
 typedef struct {
@@ -126,8 +128,28 @@ typedef struct {
   int8_t* final_state;   /* [R][n] or NULL */
   int64_t* temp_energy;  /* [n_sets][S][K] or NULL: E of the replica at
                             temperature k after sweep t and its swap round */
+  int64_t* cluster_moves; /* [n_sets/2][K] moves made (with cluster moves) */
+  int64_t* cluster_sites; /* [n_sets/2][K] sites flipped, summed over moves */
+  int64_t check_failures; /* cluster moves after which E_a + E_b differed */
 } or_temper_out;
 
+/*
+ * Houdayer cluster moves (replica cluster moves, which the paper names as
+ * combinable with parallel tempering, Sec. II.C).  With cluster_moves set,
+ * sets 2p and 2p+1 form pair p (an odd last set has no partner).  At every
+ * exchange point, before the exchange round m, each pair makes one move at
+ * each temperature k >= cluster_from between its two replicas there: D is
+ * the set of sites where they disagree; if D is empty there is no move;
+ * else the seed is the (u mod |D|)-th site of D in ascending id, u word 0 of
+ * Philox(counter (m, k, p, 4), key seed), and the connected component of
+ * the seed in the subgraph induced by D is flipped in both replicas.  The
+ * move keeps E_a + E_b and is always accepted.  A set range (set_begin,
+ * set_end) must then keep pairs whole.
+ */
+/* The cluster of seed i0 (in_cluster[v] = 1 for its sites, [n]); returns
+ * its size, 0 when the replicas agree at i0, -1 on invalid input. */
+int64_t oracle_cluster(const or_graph_in* g, const int8_t* sa, const int8_t* sb, int32_t i0,
+                       uint8_t* in_cluster);
 /* Run parallel tempering.  Returns 0, or -1 on invalid input. */
 int oracle_temper(const or_graph_in* g, const or_temper_in* pt, or_temper_out* out);
 /* The exchange test of one pair: 1 = exchange.  Ea, Eb are the energies of

@@ -49,7 +49,8 @@ class _TemperIn(C.Structure):
     _fields_ = [("n_temps", C.c_int32), ("betas", C.c_void_p), ("n_sets", C.c_int32),
                 ("n_sweeps", C.c_int32), ("swap_every", C.c_int32), ("seed", C.c_uint64),
                 ("init_spins", C.c_void_p), ("n_threads", C.c_int32),
-                ("set_begin", C.c_int32), ("set_end", C.c_int32)]
+                ("set_begin", C.c_int32), ("set_end", C.c_int32),
+                ("cluster_moves", C.c_int32), ("cluster_from", C.c_int32)]
 
 
 class _TemperOut(C.Structure):
@@ -57,7 +58,8 @@ class _TemperOut(C.Structure):
                 ("accepts", C.c_void_p), ("final_energy", C.c_void_p),
                 ("final_temp", C.c_void_p), ("swaps", C.c_void_p),
                 ("best_state", C.c_void_p), ("final_state", C.c_void_p),
-                ("temp_energy", C.c_void_p)]
+                ("temp_energy", C.c_void_p), ("cluster_moves", C.c_void_p),
+                ("cluster_sites", C.c_void_p), ("check_failures", C.c_int64)]
 
 
 class _RunOut(C.Structure):
@@ -91,6 +93,8 @@ def lib():
         L.oracle_validate.argtypes = [C.c_void_p]
         L.oracle_anneal.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_temper.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oracle_cluster.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+        L.oracle_cluster.restype = C.c_int64
         L.oracle_swap_accept.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                          C.c_int64, C.c_int64, C.c_double, C.c_double]
         _lib = L
@@ -217,6 +221,9 @@ class TemperResult:
     best_state: np.ndarray | None
     final_state: np.ndarray | None
     temp_energy: np.ndarray | None  # int64 [n_sets, S, K]
+    cluster_moves: np.ndarray | None  # int64 [n_sets // 2, K]
+    cluster_sites: np.ndarray | None  # int64 [n_sets // 2, K]
+    check_failures: int = 0           # cluster moves that changed E_a + E_b
 
     def argmax(self) -> int:
         return int(np.argmax(self.best_cut))
@@ -224,19 +231,22 @@ class TemperResult:
 
 def temper(inst, betas, n_sets, n_sweeps, swap_every, seed, colour=None,
            init_spins=None, n_threads=1, want_states=True,
-           want_temp_energy=False, sets=None) -> TemperResult:
+           want_temp_energy=False, sets=None, cluster_from=None) -> TemperResult:
     """Parallel tempering over the ladder ``betas`` (see oracle_temper).
     ``sets`` = (begin, end) simulates only those sets (the others' entries
-    stay zero)."""
+    stay zero).  ``cluster_from`` = k enables Houdayer cluster moves at
+    temperatures k and above."""
     b = np.ascontiguousarray(betas, np.float64)
     K = int(b.shape[0])
     R = K * n_sets
     n = inst.n
     g, keep = _graph(inst, colour)
     init = None if init_spins is None else np.ascontiguousarray(init_spins, np.int8)
+    cm = cluster_from is not None
     pin = _TemperIn(K, _p(b), n_sets, n_sweeps, swap_every,
                     int(seed) & 0xFFFFFFFFFFFFFFFF, _p(init), n_threads,
-                    *((0, 0) if sets is None else sets))
+                    *((0, 0) if sets is None else sets), 1 if cm else 0,
+                    int(cluster_from) if cm else 0)
     best_cut = np.zeros(R, np.int64)
     best_sweep = np.zeros(R, np.int32)
     accepts = np.zeros(R, np.int64)
@@ -246,13 +256,30 @@ def temper(inst, betas, n_sets, n_sweeps, swap_every, seed, colour=None,
     best_state = np.zeros((R, n), np.int8) if want_states else None
     final_state = np.zeros((R, n), np.int8) if want_states else None
     te = np.zeros((n_sets, n_sweeps, K), np.int64) if want_temp_energy else None
+    cmoves = np.zeros((max(n_sets // 2, 1), K), np.int64) if cm else None
+    csites = np.zeros((max(n_sets // 2, 1), K), np.int64) if cm else None
     out = _TemperOut(_p(best_cut), _p(best_sweep), _p(accepts), _p(energy), _p(temp),
-                     _p(swaps), _p(best_state), _p(final_state), _p(te))
+                     _p(swaps), _p(best_state), _p(final_state), _p(te), _p(cmoves), _p(csites), 0)
     rc = lib().oracle_temper(C.byref(g), C.byref(pin), C.byref(out))
     if rc != 0:
         raise ValueError("oracle rejected the input")
     return TemperResult(best_cut, best_sweep, accepts, energy, temp,
-                        swaps[:, :K - 1], best_state, final_state, te)
+                        swaps[:, :K - 1], best_state, final_state, te,
+                        None if cmoves is None else cmoves[:n_sets // 2],
+                        None if csites is None else csites[:n_sets // 2], int(out.check_failures))
+
+
+def cluster(inst, sa, sb, i0):
+    """Houdayer cluster of seed i0 between states sa and sb: a uint8 mask."""
+    g, keep = _graph(inst)
+    a = np.ascontiguousarray(sa, np.int8)
+    b = np.ascontiguousarray(sb, np.int8)
+    mask = np.zeros(inst.n, np.uint8)
+    size = lib().oracle_cluster(C.byref(g), _p(a), _p(b), int(i0), _p(mask))
+    if size < 0:
+        raise ValueError("invalid input")
+    assert size == int(mask.sum())
+    return mask
 
 
 def swap_accept(seed, m, k, set_, Ea, Eb, beta_k, beta_k1) -> bool:

@@ -164,3 +164,95 @@ def test_rejects(oracle_lib, betas, n_sets, S, P):
     with pytest.raises(ValueError):
         O.temper(I.torus(4, 4, 1), np.array(betas, np.float64), n_sets=n_sets, n_sweeps=S,
                  swap_every=P, seed=1)
+
+
+# ---------------------------------------------------------------- cluster moves
+def _component(inst, sa, sb, i0):
+    """The component of i0 in the subgraph induced by the disagreeing sites,
+    by scipy's connected components."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    d = sa != sb
+    keep = d[inst.u] & d[inst.v]
+    n = inst.n
+    A = coo_matrix((np.ones(int(keep.sum())), (inst.u[keep], inst.v[keep])), shape=(n, n))
+    _, lab = connected_components(A, directed=False)
+    if not d[i0]:
+        return np.zeros(n, np.uint8)
+    return ((lab == lab[i0]) & d).astype(np.uint8)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_cluster_is_the_induced_component(oracle_lib, seed):
+    O = oracle_lib
+    rng = np.random.Generator(np.random.PCG64(seed))
+    inst = [I.torus(12, 9, seed), I.random_graph(200, 260, seed), I.random_weighted(150, 300, seed, 3)][seed % 3]
+    for trial in range(8):
+        sa = (rng.integers(0, 2, inst.n) * 2 - 1).astype(np.int8)
+        sb = sa.copy()
+        flip = rng.random(inst.n) < [0.2, 0.5, 0.8, 1.0][trial % 4]
+        sb[flip] = -sb[flip]
+        i0 = int(rng.integers(0, inst.n))
+        np.testing.assert_array_equal(O.cluster(inst, sa, sb, i0), _component(inst, sa, sb, i0))
+    # opposite states on a connected graph: the cluster is every site
+    sa = np.ones(inst.n, np.int8) if seed % 3 == 0 else None
+    if sa is not None:
+        assert O.cluster(inst, sa, -sa, 5).all()
+
+
+def test_cluster_moves_keep_pair_energy_and_count(oracle_lib):
+    """Every move keeps E_a + E_b (checked by the oracle after each move);
+    moves happen at temperatures >= cluster_from only, at most one per
+    pair, temperature and round."""
+    O = oracle_lib
+    inst = I.random_weighted(80, 160, 4, 3)
+    betas = [0.1, 0.3, 0.7, 1.5]
+    S, P, n_sets = 90, 3, 5  # an odd last set has no partner
+    pt = O.temper(inst, betas, n_sets, S, P, seed=9, cluster_from=1)
+    assert pt.check_failures == 0
+    assert pt.cluster_moves.shape == (2, 4)
+    assert (pt.cluster_moves[:, 0] == 0).all()
+    assert (pt.cluster_moves[:, 1:] > 0).all() and (pt.cluster_moves <= S // P).all()
+    assert (pt.cluster_sites >= pt.cluster_moves).all()
+    assert (pt.cluster_sites <= inst.n * pt.cluster_moves).all()
+    for s in range(n_sets):
+        assert sorted(pt.final_temp[4 * s:4 * s + 4]) == [0, 1, 2, 3]
+    for r in range(n_sets * 4):
+        assert O.cut(inst, pt.best_state[r]) == pt.best_cut[r]
+        assert O.cut(inst, pt.final_state[r]) == (inst.w.sum() - pt.final_energy[r]) // 2
+    # the unpaired last set runs exactly as without cluster moves
+    plain = O.temper(inst, betas, n_sets, S, P, seed=9)
+    np.testing.assert_array_equal(pt.best_cut[16:], plain.best_cut[16:])
+    np.testing.assert_array_equal(pt.swaps[4], plain.swaps[4])
+    assert (pt.best_cut[:16] != plain.best_cut[:16]).any() or \
+           (pt.final_energy[:16] != plain.final_energy[:16]).any()
+
+
+def test_stationary_energies_with_cluster_moves(oracle_lib):
+    """Cluster moves keep the product of the Boltzmann distributions at each
+    temperature invariant (a symmetric proposal that keeps E_a + E_b): the
+    long-run mean energy at every temperature still equals exact
+    enumeration."""
+    O = oracle_lib
+    inst = I.random_weighted(9, 16, 51, 3)
+    betas = np.array([0.1, 0.3, 0.6])
+    K, n_sets, S, burn = len(betas), 8, 40000, 500
+    pt = O.temper(inst, betas, n_sets=n_sets, n_sweeps=S, swap_every=1, seed=98, n_threads=4,
+                  want_states=False, want_temp_energy=True, cluster_from=0)
+    assert pt.check_failures == 0 and (pt.cluster_moves > 0).all()
+    E = _levels(inst)
+    x = pt.temp_energy[:, burn:, :].astype(np.float64)
+    for k, b in enumerate(betas):
+        wgt = np.exp(-b * (E - E.min()))
+        exact = float((wgt * E).sum() / wgt.sum())
+        per_batch = x[:, :, k].reshape(n_sets, 50, -1).mean(axis=2).ravel()
+        se = per_batch.std(ddof=1) / math.sqrt(per_batch.size)
+        assert abs(per_batch.mean() - exact) < 5 * se, (k, per_batch.mean(), exact, se)
+
+
+def test_cluster_moves_need_whole_pairs(oracle_lib):
+    O = oracle_lib
+    with pytest.raises(ValueError):
+        O.temper(I.torus(6, 6, 1), [0.2, 0.5], 4, 10, 2, 1, sets=(1, 3), cluster_from=0)
+    with pytest.raises(ValueError):
+        O.temper(I.torus(6, 6, 1), [0.2, 0.5], 4, 10, 2, 1, cluster_from=3)
