@@ -273,6 +273,8 @@ typedef struct {
   int32_t n_sets;
   int32_t n_sweeps;
   int32_t swap_every;
+  int32_t cluster_moves;  /* nonzero: Houdayer cluster moves (below) */
+  int32_t cluster_from;   /* ... at temperatures k >= cluster_from (0..K) */
 } ising_tempering;
 
 /*
@@ -292,15 +294,33 @@ typedef struct {
  */
 int ising_temper(ising_problem* p, const ising_tempering* pt, uint64_t seed,
                  const ising_tuning* tuning, void* stream);
+/*
+ * Houdayer cluster moves (replica cluster moves, which the paper names as
+ * combinable with parallel tempering, Sec. II.C).  With cluster_moves set,
+ * sets 2p and 2p+1 form pair p (an odd last set has no partner).  At every
+ * exchange point, before exchange round m, pair p makes one move at each
+ * temperature k >= cluster_from between its two replicas a and b there: D
+ * = the sites where they disagree (no move when D is empty); the seed is
+ * the (u mod |D|)-th site of D in ascending vertex id, u word 0 of
+ * Philox(counter (m, k, p, 4), key seed); the connected component of the
+ * seed in the subgraph induced by D flips in both replicas.  The move keeps
+ * E_a + E_b and is always accepted.  Problems of more than 2^18 padded
+ * positions are refused (ISING_ERR_UNSUPPORTED); cluster_from outside
+ * 0..K is ISING_ERR_INVALID.
+ */
 
 /*
- * Exchange state after the last ising_temper of p (synchronises).  Either
+ * Exchange state after the last ising_temper of p (synchronises).  Any
  * pointer may be NULL.
- *   final_temp  [R] temperature index of every replica at the end
- *   swaps       [n_sets][K-1] accepted exchanges of each pair (k, k+1)
- * ISING_ERR_STATE when the last run of p was not tempering.
+ *   final_temp     [R] temperature index of every replica at the end
+ *   swaps          [n_sets][K-1] accepted exchanges of each pair (k, k+1)
+ *   cluster_moves  [n_sets/2][K] cluster moves made at each temperature
+ *   cluster_sites  [n_sets/2][K] sites flipped by them, summed
+ * ISING_ERR_STATE when the last run of p was not tempering, or asks for
+ * cluster counts of a run without cluster moves.
  */
-int ising_temper_results(ising_problem* p, int32_t* final_temp, int64_t* swaps);
+int ising_temper_results(ising_problem* p, int32_t* final_temp, int64_t* swaps,
+                         int64_t* cluster_moves, int64_t* cluster_sites);
 
 /* --------------------------------------------------------------- batching */
 /*

@@ -67,12 +67,15 @@ class Tuning(C.Structure):
 
 class Tempering(C.Structure):
     _fields_ = [("n_temps", C.c_int32), ("betas", C.c_void_p), ("n_sets", C.c_int32),
-                ("n_sweeps", C.c_int32), ("swap_every", C.c_int32)]
+                ("n_sweeps", C.c_int32), ("swap_every", C.c_int32),
+                ("cluster_moves", C.c_int32), ("cluster_from", C.c_int32)]
 
     @staticmethod
-    def make(betas, n_sets, n_sweeps, swap_every) -> "Tempering":
+    def make(betas, n_sets, n_sweeps, swap_every, cluster_from=None) -> "Tempering":
         b = np.ascontiguousarray(betas, np.float64)
-        t = Tempering(int(b.shape[0]), b.ctypes.data, int(n_sets), int(n_sweeps), int(swap_every))
+        cm = cluster_from is not None
+        t = Tempering(int(b.shape[0]), b.ctypes.data, int(n_sets), int(n_sweeps), int(swap_every),
+                      1 if cm else 0, int(cluster_from) if cm else 0)
         t._keep = b  # the struct points into this array
         return t
 
@@ -114,7 +117,7 @@ _sig = {
     "ising_last_anneal_ms": ([P, C.POINTER(C.c_double)], C.c_int),
     "ising_last_run_info": ([P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "ising_temper": ([P, C.POINTER(Tempering), C.c_uint64, C.POINTER(Tuning), P], C.c_int),
-    "ising_temper_results": ([P, P, P], C.c_int),
+    "ising_temper_results": ([P, P, P, P, P], C.c_int),
     "ising_anneal_batch": ([P, C.c_int32, C.POINTER(Schedule), C.c_int32, P, C.POINTER(Tuning), P], C.c_int),
     "ising_last_batch_ms": ([C.POINTER(C.c_double)], C.c_int),
     "ising_autotune": ([P, C.c_int32, C.POINTER(Schedule), C.c_int32, C.c_int32, C.POINTER(Tuning), P], C.c_int),
@@ -281,10 +284,17 @@ def ising_temper(h, pt: Tempering, seed: int, tuning: Tuning | None = None, stre
            "ising_temper")
 
 
-def ising_temper_results(h, n_temps: int, n_sets: int):
+def ising_temper_results(h, n_temps: int, n_sets: int, clusters: bool = False):
+    """(final temperatures, exchanges) or, with clusters, also the cluster
+    move and flipped-site counts [n_sets // 2, K]."""
     temp = np.zeros(n_temps * n_sets, np.int32)
     swaps = np.zeros((n_sets, max(n_temps - 1, 1)), np.int64)
-    _check(_L.ising_temper_results(h, _ptr(temp), _ptr(swaps)), "ising_temper_results")
+    cm = np.zeros((max(n_sets // 2, 1), n_temps), np.int64) if clusters else None
+    cs = np.zeros((max(n_sets // 2, 1), n_temps), np.int64) if clusters else None
+    _check(_L.ising_temper_results(h, _ptr(temp), _ptr(swaps), _ptr(cm), _ptr(cs)),
+           "ising_temper_results")
+    if clusters:
+        return temp, swaps[:, :n_temps - 1], cm[:n_sets // 2], cs[:n_sets // 2]
     return temp, swaps[:, :n_temps - 1]
 
 
@@ -411,16 +421,18 @@ class Problem:
         ising_anneal_tuned(self.handle, sched, n_replicas, seed, tuning, stream)
 
     def temper(self, betas, n_sets: int, n_sweeps: int, swap_every: int, seed: int,
-               tuning: Tuning | None = None, stream=None) -> None:
-        """Parallel tempering over the ladder ``betas`` (see ``ising_temper``)."""
-        self._ladder = (len(betas), int(n_sets))
-        ising_temper(self.handle, Tempering.make(betas, n_sets, n_sweeps, swap_every), seed,
-                     tuning, stream)
+               tuning: Tuning | None = None, stream=None, cluster_from=None) -> None:
+        """Parallel tempering over the ladder ``betas`` (see ``ising_temper``);
+        ``cluster_from`` = k adds Houdayer cluster moves at temperatures >= k."""
+        self._ladder = (len(betas), int(n_sets), cluster_from is not None)
+        ising_temper(self.handle, Tempering.make(betas, n_sets, n_sweeps, swap_every, cluster_from),
+                     seed, tuning, stream)
 
     def temper_results(self):
-        """(final temperature index [R], accepted exchanges [n_sets, K-1])."""
-        K, n_sets = getattr(self, "_ladder", (1, 1))
-        return ising_temper_results(self.handle, K, n_sets)
+        """(final temperature index [R], accepted exchanges [n_sets, K-1]),
+        plus the cluster move and site counts after a run with cluster moves."""
+        K, n_sets, cl = getattr(self, "_ladder", (1, 1, False))
+        return ising_temper_results(self.handle, K, n_sets, cl)
 
     @property
     def R(self) -> int:

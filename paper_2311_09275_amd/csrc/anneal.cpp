@@ -696,7 +696,12 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
       if (e != hipSuccess) return e;
       cleared = false;
       if (pt && segs[(size_t)i].y % pt->P == 0) {
-        e = launch_swap(*pt->swap, segs[(size_t)i].y / pt->P - 1, L.ctr_d, s);
+        const int m = segs[(size_t)i].y / pt->P - 1;
+        if (pt->cluster) {
+          e = launch_houdayer(*pt->cluster, m, segs[(size_t)i].y - 1, s);
+          if (e != hipSuccess) return e;
+        }
+        e = launch_swap(*pt->swap, m, L.ctr_d, s);
         if (e != hipSuccess) return e;
         cleared = true;
       }
@@ -714,10 +719,15 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
     if (pt) {
       // the exchange launches carry their arguments by value
       const SwapDev& X = *pt->swap;
-      snprintf(key + kl, sizeof key - (size_t)kl, "/pt/%d/%d/%d/%d/%u/%u/%p/%p/%p/%p/%p/%p/%p", pt->S,
-               pt->P, X.K, X.n_sets, X.seed_lo, X.seed_hi, (const void*)X.energy, (void*)X.temp,
-               (void*)X.slot, (void*)X.swaps, (const void*)X.tq, (const void*)X.off,
-               (const void*)X.len);
+      kl += snprintf(key + kl, sizeof key - (size_t)kl, "/pt/%d/%d/%d/%d/%u/%u/%p/%p/%p/%p/%p/%p/%p",
+                     pt->S, pt->P, X.K, X.n_sets, X.seed_lo, X.seed_hi, (const void*)X.energy,
+                     (void*)X.temp, (void*)X.slot, (void*)X.swaps, (const void*)X.tq,
+                     (const void*)X.off, (const void*)X.len);
+      if (pt->cluster) {
+        const ClusterDev& Y = *pt->cluster;
+        snprintf(key + kl, sizeof key - (size_t)kl, "/cl/%d/%d/%p/%p/%p/%p/%p", Y.from, Y.n_pairs,
+                 (void*)Y.mark, (void*)Y.queue, (void*)Y.moves, (void*)Y.sites, (void*)Y.packed);
+      }
     }
     if (!L.exec || L.graph_key != key) {
       if (L.exec) (void)hipGraphExecDestroy(L.exec);

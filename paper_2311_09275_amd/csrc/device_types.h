@@ -18,6 +18,7 @@ constexpr int kGroupCountShift = 28;
 constexpr uint32_t kTagSweep = 0;
 constexpr uint32_t kTagInit = 1;
 constexpr uint32_t kTagSwap = 3;  // parallel tempering: (round, pair, set, 3)
+constexpr uint32_t kTagCluster = 4;  // cluster moves: (round, temperature, set pair, 4)
 
 // Threshold row length meaning "beta_t == 0: accept every move".
 constexpr int32_t kAcceptAll = -1;
@@ -161,6 +162,32 @@ struct SwapDev {
   const uint32_t* tq;
   const int32_t* off;      // [K-1]
   const int32_t* len;      // [K-1]
+};
+
+// Houdayer cluster moves of a tempering run (sets 2p and 2p+1 form pair
+// p): one workgroup per (pair, temperature k >= from).  The replicas' state
+// is either the FIELD save area (packed words (h << 1) | spin bit, [R][n_pad])
+// or the PLAIN arrays (spins int8 and fields int32, [n_pad][R]).
+struct ClusterDev {
+  int32_t K, n_pairs, from;
+  int32_t n, n_pad, R;
+  uint32_t seed_lo, seed_hi;
+  const int32_t* row;    // CSR over positions
+  const int32_t* adj;
+  const int32_t* wgt;
+  const int32_t* grp;    // group words (real slots of a group)
+  const int32_t* pos;    // [n] original id -> position
+  const int32_t* slot;   // [n_sets][K] replica at each temperature
+  int32_t* energy;       // [R]
+  int32_t* packed;       // FIELD: [R][n_pad]; null on the plain path
+  int8_t* spins;         // PLAIN: [n_pad][R]
+  int32_t* field;        // PLAIN: [n_pad][R]
+  int8_t* best;          // PLAIN: [n_pad][R] (pending lazy snapshots)
+  int32_t* snap;         // PLAIN: [R] last improving sweep
+  int32_t* mark;         // [workgroups][n_pad] scratch, zeroed by the kernel
+  int32_t* queue;        // [workgroups][n_pad] scratch
+  long long* moves;      // [n_pairs][K]
+  long long* sites;      // [n_pairs][K]
 };
 
 // Layouts understood by the state gather kernel.

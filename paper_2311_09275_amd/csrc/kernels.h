@@ -17,6 +17,7 @@ struct PlainPlan {
   // (null = none)
   const SwapDev* swap = nullptr;
   int swap_every = 0;
+  const ClusterDev* cluster = nullptr;  // cluster moves before each round
 };
 
 // One persistent launch (FIELD or MSC) over a unit list.
@@ -51,6 +52,9 @@ hipError_t launch_fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t
 // zeroes clear8[0..7] when given).
 hipError_t launch_pt_init(const SwapDev& X, hipStream_t s);
 hipError_t launch_swap(const SwapDev& X, int m, int32_t* clear8, hipStream_t s);
+// Houdayer cluster moves of round m, after sweep t (one workgroup per pair
+// and temperature from X.from up).
+hipError_t launch_houdayer(const ClusterDev& X, int m, int t, hipStream_t s);
 
 // Static LDS of the persistent kernels (bytes), for the LDS budget.
 constexpr size_t kFieldStaticLds = 512;

@@ -1399,6 +1399,149 @@ __global__ void k_pt_init(SwapDev X) {
 // threshold of q.
 // (Also zeroes clear8[0..7] when given: the persistent launch's list
 // cursors, for the next segment.)
+// Houdayer cluster move of pair p at temperature k in round m (after sweep
+// t): the replicas a (set 2p) and b (set 2p+1) at k disagree on the sites
+// D; the seed is the (u mod |D|)-th site of D in ascending original id, u
+// word 0 of Philox(m, k, p, 4); its connected component in the subgraph
+// induced by D flips in both replicas (which keeps E_a + E_b), and both
+// replicas' fields and energies are recomputed.  One workgroup per (p, k);
+// D is a bitmask over positions in LDS, the BFS queue and the claim marks
+// are the workgroup's global scratch.
+__global__ void __launch_bounds__(256) k_houdayer(ClusterDev X, int m, int t) {
+  extern __shared__ uint32_t dmask[];  // [n_pad / 32]
+  __shared__ int scan[256];
+  __shared__ int sh_i0, sh_tail, sh_total;
+  __shared__ int esum[2];
+  const int nk = X.K - X.from;
+  const int p = blockIdx.x / nk, k = X.from + (int)(blockIdx.x - p * nk);
+  const int tid = threadIdx.x;
+  const int a = X.slot[(2 * p) * X.K + k], b = X.slot[(2 * p + 1) * X.K + k];
+  const int n_pad = X.n_pad, n = X.n;
+  int32_t* mark = X.mark + (int64_t)blockIdx.x * n_pad;
+  int32_t* queue = X.queue + (int64_t)blockIdx.x * n_pad;
+  const bool plain = X.packed == nullptr;
+  auto bit_of = [&](int r, int q) -> int {
+    return plain ? (X.spins[(int64_t)q * X.R + r] > 0) : (X.packed[(int64_t)r * n_pad + q] & 1);
+  };
+  auto real = [&](int q) { return (q & 3) <= (X.grp[q >> 2] >> kGroupCountShift); };
+  // pending lazy snapshots of the plain path: the last sweep improved, so
+  // its end state is the best state; take it before the move changes it
+  if (plain && (X.snap[a] == t || X.snap[b] == t)) {
+    for (int q = tid; q < n_pad; q += 256) {
+      if (X.snap[a] == t) X.best[(int64_t)q * X.R + a] = X.spins[(int64_t)q * X.R + a];
+      if (X.snap[b] == t) X.best[(int64_t)q * X.R + b] = X.spins[(int64_t)q * X.R + b];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      if (X.snap[a] == t) X.snap[a] = -2;
+      if (X.snap[b] == t) X.snap[b] = -2;
+    }
+  }
+  for (int i = tid; i < (n_pad + 31) / 32; i += 256) dmask[i] = 0u;
+  for (int q = tid; q < n_pad; q += 256) mark[q] = 0;
+  if (tid == 0) sh_tail = 0;
+  __syncthreads();
+  for (int q = tid; q < n_pad; q += 256)
+    if (real(q) && bit_of(a, q) != bit_of(b, q)) atomicOr(&dmask[q >> 5], 1u << (q & 31));
+  __syncthreads();
+  auto in_d = [&](int q) { return (dmask[q >> 5] >> (q & 31)) & 1u; };
+  // |D| and the seed: ids in contiguous chunks per lane, an exclusive scan
+  const int chunk = (n + 255) / 256;
+  const int v0 = min(n, tid * chunk), v1 = min(n, v0 + chunk);
+  int cnt = 0;
+  for (int v = v0; v < v1; ++v) cnt += (int)in_d(X.pos[v]);
+  scan[tid] = cnt;
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int i = 0; i < 256; ++i) {
+      const int c = scan[i];
+      scan[i] = acc;
+      acc += c;
+    }
+    sh_total = acc;
+    sh_i0 = -1;
+  }
+  __syncthreads();
+  const int total = sh_total;
+  if (total == 0) return;  // uniform: the replicas agree everywhere
+  const uint4 x = philox10((uint32_t)m, (uint32_t)k, (uint32_t)p, kTagCluster, X.seed_lo, X.seed_hi);
+  const int j = (int)(x.x % (uint32_t)total);
+  if (j >= scan[tid] && j < scan[tid] + cnt) {
+    int left = j - scan[tid];
+    for (int v = v0; v < v1; ++v)
+      if (in_d(X.pos[v]) && left-- == 0) {
+        sh_i0 = X.pos[v];
+        break;
+      }
+  }
+  __syncthreads();
+  if (sh_i0 < 0) return;  // (uniform; cannot happen: j < |D|)
+  // level-synchronous BFS over D from the seed
+  if (tid == 0) {
+    mark[sh_i0] = 1;
+    queue[0] = sh_i0;
+    sh_tail = 1;
+  }
+  __syncthreads();
+  int lo = 0, hi = 1;
+  while (lo < hi) {
+    for (int i = lo + tid; i < hi; i += 256) {
+      const int v = queue[i];
+      for (int e = X.row[v]; e < X.row[v + 1]; ++e) {
+        const int u = X.adj[e];
+        if (in_d(u) && atomicExch(&mark[u], 1) == 0) queue[atomicAdd(&sh_tail, 1)] = u;
+      }
+    }
+    __syncthreads();
+    lo = hi;
+    hi = sh_tail;
+    __syncthreads();
+  }
+  const int size = hi;
+  // flip the cluster in both replicas
+  for (int i = tid; i < size; i += 256) {
+    const int q = queue[i];
+    if (plain) {
+      X.spins[(int64_t)q * X.R + a] = (int8_t)-X.spins[(int64_t)q * X.R + a];
+      X.spins[(int64_t)q * X.R + b] = (int8_t)-X.spins[(int64_t)q * X.R + b];
+    } else {
+      X.packed[(int64_t)a * n_pad + q] ^= 1;
+      X.packed[(int64_t)b * n_pad + q] ^= 1;
+    }
+  }
+  if (tid < 2) esum[tid] = 0;
+  __syncthreads();
+  // fields and energies from scratch: h = -sum w s, E = -1/2 sum s h
+  int part[2] = {0, 0};
+  for (int q = tid; q < n_pad; q += 256) {
+    if (!real(q)) continue;
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+      const int r = z ? b : a;
+      int h = 0;
+      for (int e = X.row[q]; e < X.row[q + 1]; ++e) h -= X.wgt[e] * (bit_of(r, X.adj[e]) ? 1 : -1);
+      const int sb = bit_of(r, q);
+      part[z] += sb ? h : -h;
+      // (bit 0 of a packed word, read by other lanes, is unchanged here)
+      if (plain) X.field[(int64_t)q * X.R + r] = h;
+      else X.packed[(int64_t)r * n_pad + q] = (h << 1) | sb;
+    }
+  }
+#pragma unroll
+  for (int z = 0; z < 2; ++z) {
+    const int s = wave_sum(part[z]);
+    if ((tid & 63) == 0 && s != 0) atomicAdd(&esum[z], s);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    X.energy[a] = -esum[0] / 2;
+    X.energy[b] = -esum[1] / 2;
+    X.moves[p * X.K + k] += 1;
+    X.sites[p * X.K + k] += size;
+  }
+}
+
 __global__ void k_swap(SwapDev X, int m, int32_t* clear8) {
   const int per_set = (X.K - (m & 1)) / 2;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1497,7 +1640,10 @@ hipError_t launch_plain_anneal(const PlainDev& P, const PlainPlan& plan, hipStre
     }
     hipLaunchKernelGGL(k_plain_eos, dim3(blocks_for(P.R, B)), dim3(B), 0, s, P, t, plan.S);
     if (plan.swap && (t + 1) % plan.swap_every == 0) {
-      const hipError_t e = launch_swap(*plan.swap, (t + 1) / plan.swap_every - 1, nullptr, s);
+      const int m = (t + 1) / plan.swap_every - 1;
+      hipError_t e = plan.cluster ? launch_houdayer(*plan.cluster, m, t, s) : hipSuccess;
+      if (e != hipSuccess) return e;
+      e = launch_swap(*plan.swap, m, nullptr, s);
       if (e != hipSuccess) return e;
     }
   }
@@ -1580,6 +1726,14 @@ hipError_t launch_swap(const SwapDev& X, int m, int32_t* clear8, hipStream_t s) 
   if (clear8 && n < 8) n = 8;
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_swap, dim3(blocks_for(n, 256)), dim3(256), 0, s, X, m, clear8);
+  return hipGetLastError();
+}
+
+hipError_t launch_houdayer(const ClusterDev& X, int m, int t, hipStream_t s) {
+  const int wgs = X.n_pairs * (X.K - X.from);
+  if (wgs <= 0) return hipSuccess;
+  const size_t lds = sizeof(uint32_t) * (size_t)((X.n_pad + 31) / 32);
+  hipLaunchKernelGGL(k_houdayer, dim3(wgs), dim3(256), lds, s, X, m, t);
   return hipGetLastError();
 }
 

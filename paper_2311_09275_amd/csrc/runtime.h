@@ -206,6 +206,7 @@ struct JobSpec {
 struct TemperPlan {
   int S, P;
   const SwapDev* swap;
+  const ClusterDev* cluster;  // cluster moves before each round, or null
 };
 
 int run_persistent(Launcher& L, const std::vector<JobSpec>& jobs, const PersistentConfig& cfg,
@@ -244,6 +245,8 @@ struct TemperState {
   std::vector<uint32_t> swap_tq;  // host copies behind the async uploads
   std::vector<int32_t> swap_off, swap_len;
   ising::SwapDev dev{};
+  ising::ClusterDev cluster{};
+  bool cluster_on = false;
   int32_t K = 0, n_sets = 0, S = 0, P = 0;
   bool valid = false;             // the last run of the problem was tempering
 };

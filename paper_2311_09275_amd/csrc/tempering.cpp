@@ -56,6 +56,15 @@ int ising_temper(ising_problem* p, const ising_tempering* x, uint64_t seed,
     set_error("energy tracing is not available for tempering");
     return ISING_ERR_UNSUPPORTED;
   }
+  const bool cm = x->cluster_moves != 0;
+  if (cm && (x->cluster_from < 0 || x->cluster_from > K)) {
+    set_error("cluster_from must lie in 0..n_temps");
+    return ISING_ERR_INVALID;
+  }
+  if (cm && p->g.n_pad > (1 << 18)) {
+    set_error("cluster moves keep a bitmask of the positions in LDS: at most 2^18 positions");
+    return ISING_ERR_UNSUPPORTED;
+  }
   const int R = K * n_sets;
   IRET(ladder_tables(p, betas));
   TemperState& T = p->temper;
@@ -84,10 +93,17 @@ int ising_temper(ising_problem* p, const ising_tempering* x, uint64_t seed,
 
   // exchange state and thresholds
   const size_t pairs = (size_t)n_sets * (size_t)(K - 1);
+  // cluster moves: one workgroup per (set pair, temperature >= from)
+  const int n_pairs = cm ? n_sets / 2 : 0;
+  const int wgs = n_pairs * (K - (cm ? x->cluster_from : K));
+  const size_t cl_stats = (size_t)n_pairs * (size_t)K;
+  const size_t cl_scratch = (size_t)wgs * (size_t)p->g.n_pad;
   const size_t bytes = 2 * DeviceArena::span(sizeof(int32_t) * (size_t)R) +
                        DeviceArena::span(sizeof(long long) * pairs) +
                        DeviceArena::span(sizeof(uint32_t) * T.swap.tq.size()) +
-                       2 * DeviceArena::span(sizeof(int32_t) * (size_t)T.swap.S);
+                       2 * DeviceArena::span(sizeof(int32_t) * (size_t)T.swap.S) +
+                       2 * DeviceArena::span(sizeof(long long) * cl_stats) +
+                       2 * DeviceArena::span(sizeof(int32_t) * cl_scratch);
   IRET(T.arena.reserve(bytes));
   SwapDev X;
   memset(&X, 0, sizeof X);
@@ -112,6 +128,37 @@ int ising_temper(ising_problem* p, const ising_tempering* x, uint64_t seed,
   X.off = off;
   X.len = len;
   T.dev = X;
+  ClusterDev Y;
+  memset(&Y, 0, sizeof Y);
+  Y.K = K;
+  Y.n_pairs = n_pairs;
+  Y.from = cm ? x->cluster_from : K;
+  Y.n = p->g.n;
+  Y.n_pad = p->g.n_pad;
+  Y.R = R;
+  Y.seed_lo = X.seed_lo;
+  Y.seed_hi = X.seed_hi;
+  Y.row = p->dg.row;
+  Y.adj = p->dg.adj;
+  Y.wgt = p->dg.wgt;
+  Y.grp = p->dg.grp;
+  Y.pos = p->dg.pos;
+  Y.slot = X.slot;
+  Y.energy = b.energy;
+  if (cfg.path == ISING_PATH_PLAIN) {
+    Y.spins = b.spins;
+    Y.field = b.field;
+    Y.best = static_cast<int8_t*>(b.best);
+    Y.snap = b.snap;
+  } else {
+    Y.packed = b.save;
+  }
+  Y.moves = T.arena.take<long long>(cl_stats);
+  Y.sites = T.arena.take<long long>(cl_stats);
+  Y.mark = T.arena.take<int32_t>(cl_scratch);
+  Y.queue = T.arena.take<int32_t>(cl_scratch);
+  T.cluster = Y;
+  T.cluster_on = cm;
   T.K = K;
   T.n_sets = n_sets;
   T.S = S;
@@ -120,18 +167,20 @@ int ising_temper(ising_problem* p, const ising_tempering* x, uint64_t seed,
 
   ICHK(hipEventRecord(b.ev0, st));
   ICHK(launch_pt_init(T.dev, st));
+  if (cl_stats) ICHK(launch_fill_i32(reinterpret_cast<int32_t*>(Y.moves), 0, 2 * (int64_t)cl_stats, st));
+  if (cl_stats) ICHK(launch_fill_i32(reinterpret_cast<int32_t*>(Y.sites), 0, 2 * (int64_t)cl_stats, st));
   if (cfg.path == ISING_PATH_PLAIN) {
     PlainDev Pd = make_plain(p, b, R, seed);
     Pd.temp = T.dev.temp;
     static thread_local JobDev hjob;
     hjob = make_job(p->g, p->dg, b, R, seed, 0, S, cfg);
     ICHK(hipMemcpy(b.job_dev, &hjob, sizeof(JobDev), hipMemcpyHostToDevice));
-    PlainPlan plan{S, p->g.C, p->g.cls.data(), &T.dev, P};
+    PlainPlan plan{S, p->g.C, p->g.cls.data(), &T.dev, P, cm ? &T.cluster : nullptr};
     ICHK(launch_plain_anneal(Pd, plan, st));
     ICHK(launch_argmax(b.job_dev, 1, st));
   } else {
     std::vector<JobSpec> js{JobSpec{&p->g, &p->dg, &b, R, seed, 0, S}};
-    TemperPlan plan{S, P, &T.dev};
+    TemperPlan plan{S, P, &T.dev, cm ? &T.cluster : nullptr};
     IRET(run_persistent(p->launcher, js, cfg, st, st != nullptr, &plan));
   }
   ICHK(hipEventRecord(b.ev1, st));
@@ -141,7 +190,8 @@ int ising_temper(ising_problem* p, const ising_tempering* x, uint64_t seed,
   return ISING_OK;
 }
 
-int ising_temper_results(ising_problem* p, int32_t* final_temp, int64_t* swaps) {
+int ising_temper_results(ising_problem* p, int32_t* final_temp, int64_t* swaps,
+                         int64_t* cluster_moves, int64_t* cluster_sites) {
   if (!p) return ISING_ERR_INVALID;
   TemperState& T = p->temper;
   if (!T.valid || !p->run.valid) {
@@ -158,6 +208,22 @@ int ising_temper_results(ising_problem* p, int32_t* final_temp, int64_t* swaps) 
     std::vector<long long> tmp(pairs);
     ICHK(hipMemcpy(tmp.data(), T.dev.swaps, sizeof(long long) * pairs, hipMemcpyDeviceToHost));
     for (size_t i = 0; i < pairs; ++i) swaps[i] = (int64_t)tmp[i];
+  }
+  const size_t cl = T.cluster_on ? (size_t)(T.n_sets / 2) * (size_t)T.K : 0;
+  if ((cluster_moves || cluster_sites) && !T.cluster_on) {
+    set_error("the last tempering run made no cluster moves");
+    return ISING_ERR_STATE;
+  }
+  if (cl) {
+    std::vector<long long> tmp(cl);
+    if (cluster_moves) {
+      ICHK(hipMemcpy(tmp.data(), T.cluster.moves, sizeof(long long) * cl, hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < cl; ++i) cluster_moves[i] = (int64_t)tmp[i];
+    }
+    if (cluster_sites) {
+      ICHK(hipMemcpy(tmp.data(), T.cluster.sites, sizeof(long long) * cl, hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < cl; ++i) cluster_sites[i] = (int64_t)tmp[i];
+    }
   }
   return ISING_OK;
 }

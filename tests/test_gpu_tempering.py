@@ -27,26 +27,36 @@ PATHS = {
 }
 
 
-def compare(inst, betas, n_sets, S, P, seed, tuning=None, sets=None, states=True, init=None):
+def compare(inst, betas, n_sets, S, P, seed, tuning=None, sets=None, states=True, init=None,
+            cluster_from=None):
     """Run tempering on the GPU and check it against the oracle (on the
     sets (begin, end) when given, else on all)."""
     if tuning is not None and tuning.lds_adjacency == 4:
         deg = np.bincount(np.concatenate([inst.u, inst.v]), minlength=inst.n)
         if not (deg == 4).all() or not (np.abs(inst.w) == 1).all():
             pytest.skip("the degree-4 form needs a 4-regular unit-weight graph")
+    if tuning is not None and tuning.lds_adjacency in (1, 3) and not (np.abs(inst.w) == 1).all():
+        pytest.skip("the adjacency staged in LDS needs unit weights")
     K = len(betas)
     R = K * n_sets
     p = B.Problem.from_instance(inst)
     if init is not None:
         p.set_initial_state(init, R)
-    p.temper(betas, n_sets, S, P, seed, tuning)
+    p.temper(betas, n_sets, S, P, seed, tuning, cluster_from=cluster_from)
     best, arg, per = B.ising_cut(p.handle, R)
     bs, acc, en = p.replica_results()
-    temp, swaps = p.temper_results()
+    if cluster_from is None:
+        temp, swaps = p.temper_results()
+    else:
+        temp, swaps, cmoves, csites = p.temper_results()
     assert p.R == R and p.S == S
     s0, s1 = (0, n_sets) if sets is None else sets
     o = O.temper(inst, betas, n_sets, S, P, seed, init_spins=init, n_threads=4,
-                 want_states=states, sets=None if sets is None else sets)
+                 want_states=states, sets=None if sets is None else sets,
+                 cluster_from=cluster_from)
+    if cluster_from is not None:
+        assert o.check_failures == 0
+        ps = slice(s0 // 2, s1 // 2)  # the pairs inside the checked sets
     rs = slice(s0 * K, s1 * K)
     np.testing.assert_array_equal(per[rs], o.best_cut[rs])
     np.testing.assert_array_equal(bs[rs], o.best_sweep[rs])
@@ -54,6 +64,9 @@ def compare(inst, betas, n_sets, S, P, seed, tuning=None, sets=None, states=True
     np.testing.assert_array_equal(en[rs], o.final_energy[rs])
     np.testing.assert_array_equal(temp[rs], o.final_temp[rs])
     np.testing.assert_array_equal(swaps[s0:s1], o.swaps[s0:s1])
+    if cluster_from is not None:
+        np.testing.assert_array_equal(cmoves[ps], o.cluster_moves[ps])
+        np.testing.assert_array_equal(csites[ps], o.cluster_sites[ps])
     if states:
         for r in list(range(s0 * K, s1 * K))[:: max(1, (s1 - s0) * K // 12)]:
             gb, gf = p.replica_state(r)
@@ -146,3 +159,40 @@ def test_errors_and_state():
         p.temper_results()
     assert e.value.status == B.ERR_STATE
     p.close()
+
+
+# ---------------------------------------------------------------- cluster moves
+CLUSTER_PATHS = ["auto", "plain", "field_g1_b256_hbmadj", "field_g1_b1024_ldsadj",
+                 "field_g1_b512_csradj", "field_g4_b256_ldsadj", "field_g2_b512_hbmadj"]
+
+
+@pytest.mark.parametrize("path", CLUSTER_PATHS)
+def test_cluster_moves_torus(path):
+    """Houdayer moves at the four coldest of 8 temperatures, 6 sets (3
+    pairs), a round every 4 sweeps (the moves change the replicas' states,
+    fields and energies between launches)."""
+    o = compare(I.torus(14, 10, 41), list(np.geomspace(0.2, 2.5, 8)), 6, 120, 4, 51, PATHS[path],
+                cluster_from=4)
+    assert (o.cluster_moves[:, 4:] > 0).all()
+
+
+@pytest.mark.parametrize("path", CLUSTER_PATHS)
+def test_cluster_moves_every_temperature_odd_sets(path):
+    """Moves at every temperature and after every sweep, on a weighted
+    random graph with isolated vertices and on a unit-weight one; 5 sets,
+    the last without a partner."""
+    compare(I.random_weighted(300, 330, 17, 4), [0.1, 0.3, 0.7, 1.4], 5, 60, 1, 52, PATHS[path],
+            cluster_from=0)
+
+
+@pytest.mark.parametrize("path", CLUSTER_PATHS)
+def test_cluster_moves_unit_random_graph(path):
+    compare(I.random_graph(300, 330, 18), [0.1, 0.3, 0.7, 1.4], 5, 60, 1, 53, PATHS[path],
+            cluster_from=1)
+
+
+def test_cluster_moves_full_size_sampled_pairs():
+    """The benchmark torus shape with moves at the 16 coldest of 32
+    temperatures: the oracle checks one pair of sets over 400 sweeps."""
+    compare(I.workload_c2(), list(np.geomspace(0.2, 3.0, 32)), 8, 400, 10, 1002, None,
+            sets=(2, 4), states=False, cluster_from=16)
