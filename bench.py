@@ -282,14 +282,16 @@ def main():
         ladder = list(np.geomspace(0.2, 3.0, K))
         pt_att = inst.n * K * n_sets * S
 
-        def temper_run(P_, tuning=None, reps=2):
-            prob.temper(ladder, n_sets, S, P_, SEED, tuning, stream=stream)  # warm (captures)
+        def temper_run(P_, tuning=None, reps=2, cluster_from=None):
+            prob.temper(ladder, n_sets, S, P_, SEED, tuning, stream=stream,
+                        cluster_from=cluster_from)  # warm (captures)
             prob.cut()
             walls_t = []
             for _ in range(reps):
                 torch.cuda.synchronize()
                 t = time.perf_counter()
-                prob.temper(ladder, n_sets, S, P_, SEED, tuning, stream=stream)
+                prob.temper(ladder, n_sets, S, P_, SEED, tuning, stream=stream,
+                            cluster_from=cluster_from)
                 r_ = prob.cut()
                 walls_t.append(time.perf_counter() - t)
             return r_, float(np.mean(walls_t)) * 1e3, prob.last_anneal_ms()
@@ -299,6 +301,9 @@ def main():
         per_t = res_t.per_replica.copy()
         path_t = B.ising_last_run_info(prob.handle)[2]
         _, ms_t100, kern_t100 = temper_run(100)
+        # Houdayer cluster moves at the colder half of the ladder
+        res_c, ms_c, kern_c = temper_run(P, cluster_from=K // 2)
+        _, _, cm_c, cs_c = prob.temper_results()
         t = time.perf_counter()
         prob.temper(ladder, n_sets, S, P, SEED, B.Tuning(B.PATH_PLAIN, 1, 256, 0), stream=stream)
         res_tp = prob.cut()
@@ -314,15 +319,20 @@ def main():
                       "path": {1: "plain", 2: "field", 3: "msc"}.get(path_t, str(path_t)),
                       "best_cut": int(res_t.best_cut),
                       "exchange_rate": {"min": float(rate.min()), "mean": float(rate.mean()),
-                                        "max": float(rate.max())}}
+                                        "max": float(rate.max())},
+                      "cluster_moves": {"from_temperature": K // 2, "ms_per_run": ms_c, "kernel_ms": kern_c,
+                                        "moves": int(cm_c.sum()),
+                                        "mean_cluster_sites": float(cs_c.sum() / max(cm_c.sum(), 1)),
+                                        "best_cut": int(res_c.best_cut)}}
         if c_ref is not None:
-            set_best = per_t.reshape(n_sets, K).max(axis=1)
             temper_leg["ttt"] = {}
+            temper_leg["cluster_moves"]["ttt"] = {}
             for q in (0.995, 0.998, 1.0):
                 target = ttt.target_cut(c_ref, q)
-                tf = ttt.replica_ttt(set_best, target, ms_t / 1e3, S)
-                temper_leg["ttt"][str(q)] = {"target": target, "ps_sets": tf["ps"],
-                                             "ttt_s": tf["ttt_s"]}
+                for per_, ms_, dst in ((per_t, ms_t, temper_leg["ttt"]),
+                                       (res_c.per_replica, ms_c, temper_leg["cluster_moves"]["ttt"])):
+                    tf = ttt.replica_ttt(per_.reshape(n_sets, K).max(axis=1), target, ms_ / 1e3, S)
+                    dst[str(q)] = {"target": target, "ps_sets": tf["ps"], "ttt_s": tf["ttt_s"]}
 
     # ------------------------------------------------------------ serving leg
     serving = None

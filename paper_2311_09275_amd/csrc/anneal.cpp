@@ -725,8 +725,8 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
                      (const void*)X.off, (const void*)X.len);
       if (pt->cluster) {
         const ClusterDev& Y = *pt->cluster;
-        snprintf(key + kl, sizeof key - (size_t)kl, "/cl/%d/%d/%p/%p/%p/%p/%p", Y.from, Y.n_pairs,
-                 (void*)Y.mark, (void*)Y.queue, (void*)Y.moves, (void*)Y.sites, (void*)Y.packed);
+        snprintf(key + kl, sizeof key - (size_t)kl, "/cl/%d/%d/%d/%p/%p/%p/%p", Y.from, Y.n_pairs,
+                 Y.stage, (void*)Y.queue, (void*)Y.moves, (void*)Y.sites, (void*)Y.packed);
       }
     }
     if (!L.exec || L.graph_key != key) {

@@ -171,6 +171,11 @@ struct SwapDev {
 struct ClusterDev {
   int32_t K, n_pairs, from;
   int32_t n, n_pad, R;
+  int32_t n_adj;         // 2m adjacency entries
+  int32_t stage;         // the parents, the position CSR and pos fit in LDS
+                         // (the latter as 16-bit entries: n_pad, 2m < 2^16)
+  int32_t unit;          // with stage: unit weights and n_pad < 2^15, so an
+                         // entry's bit 15 can carry the sign of its weight
   uint32_t seed_lo, seed_hi;
   const int32_t* row;    // CSR over positions
   const int32_t* adj;
@@ -184,8 +189,7 @@ struct ClusterDev {
   int32_t* field;        // PLAIN: [n_pad][R]
   int8_t* best;          // PLAIN: [n_pad][R] (pending lazy snapshots)
   int32_t* snap;         // PLAIN: [R] last improving sweep
-  int32_t* mark;         // [workgroups][n_pad] scratch, zeroed by the kernel
-  int32_t* queue;        // [workgroups][n_pad] scratch
+  int32_t* queue;        // [workgroups][n_pad] union-find parents (when not staged)
   long long* moves;      // [n_pairs][K]
   long long* sites;      // [n_pairs][K]
 };

@@ -55,6 +55,9 @@ hipError_t launch_swap(const SwapDev& X, int m, int32_t* clear8, hipStream_t s);
 // Houdayer cluster moves of round m, after sweep t (one workgroup per pair
 // and temperature from X.from up).
 hipError_t launch_houdayer(const ClusterDev& X, int m, int t, hipStream_t s);
+// Dynamic LDS of the cluster-move kernel (bitmasks, plus the staged queue
+// and CSR when `stage`).
+size_t houdayer_lds(int n, int n_pad, int n_adj, bool stage);
 
 // Static LDS of the persistent kernels (bytes), for the LDS budget.
 constexpr size_t kFieldStaticLds = 512;

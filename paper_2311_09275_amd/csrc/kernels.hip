@@ -1404,128 +1404,230 @@ __global__ void k_pt_init(SwapDev X) {
 // D; the seed is the (u mod |D|)-th site of D in ascending original id, u
 // word 0 of Philox(m, k, p, 4); its connected component in the subgraph
 // induced by D flips in both replicas (which keeps E_a + E_b), and both
-// replicas' fields and energies are recomputed.  One workgroup per (p, k);
-// D is a bitmask over positions in LDS, the BFS queue and the claim marks
-// are the workgroup's global scratch.
-__global__ void __launch_bounds__(256) k_houdayer(ClusterDev X, int m, int t) {
-  extern __shared__ uint32_t dmask[];  // [n_pad / 32]
-  __shared__ int scan[256];
-  __shared__ int sh_i0, sh_tail, sh_total;
+// replicas' fields and energies are recomputed.  One workgroup per (p, k).
+// The two replicas' spins, D and the cluster marks are bitmasks over the
+// positions in LDS; the component is found by union-find (a search from
+// the seed would take one dependent step per level of the cluster, and
+// clusters of thousands of sites have hundreds).  With X.stage the parents
+// and the position CSR are staged in LDS too, else the parents live in the
+// workgroup's global scratch.
+constexpr int kClusterThreads = 1024;
+
+__global__ void __launch_bounds__(kClusterThreads) k_houdayer(ClusterDev X, int m, int t) {
+  extern __shared__ uint32_t lds[];
+  __shared__ int scan[kClusterThreads / 64];
+  __shared__ int sh_i0, sh_tail;
   __shared__ int esum[2];
+  const int n_pad = X.n_pad, n = X.n;
+  const int W = (n_pad + 31) / 32;
+  uint32_t* dmask = lds;
+  uint32_t* abits = lds + W;
+  uint32_t* bbits = lds + 2 * W;
+  uint32_t* mk = lds + 3 * W;
   const int nk = X.K - X.from;
   const int p = blockIdx.x / nk, k = X.from + (int)(blockIdx.x - p * nk);
   const int tid = threadIdx.x;
   const int a = X.slot[(2 * p) * X.K + k], b = X.slot[(2 * p + 1) * X.K + k];
-  const int n_pad = X.n_pad, n = X.n;
-  int32_t* mark = X.mark + (int64_t)blockIdx.x * n_pad;
-  int32_t* queue = X.queue + (int64_t)blockIdx.x * n_pad;
   const bool plain = X.packed == nullptr;
-  auto bit_of = [&](int r, int q) -> int {
-    return plain ? (X.spins[(int64_t)q * X.R + r] > 0) : (X.packed[(int64_t)r * n_pad + q] & 1);
+  const int n_adj = X.row[n_pad];
+  // union-find parents of the positions (LDS when staged, else the
+  // workgroup's global scratch); staged: 16-bit row offsets, neighbour
+  // positions and vertex positions in LDS
+  const bool stage = X.stage != 0;
+  int32_t* parent = stage ? reinterpret_cast<int32_t*>(lds + 4 * W) : X.queue + (int64_t)blockIdx.x * n_pad;
+  uint16_t* row16 = reinterpret_cast<uint16_t*>(lds + 4 * W + n_pad);
+  uint16_t* adj16 = row16 + n_pad + 1;
+  uint16_t* pos16 = adj16 + n_adj;
+  // unit weights on fewer than 2^15 positions: an entry also carries the
+  // sign of its weight in bit 15
+  const bool signs = stage && X.unit;
+  if (stage) {
+    copy_in(row16, X.row, n_pad + 1, [](int32_t x) { return (uint16_t)x; });
+    copy_in(pos16, X.pos, n, [](int32_t x) { return (uint16_t)x; });
+    if (signs) {
+      // two passes keep each copy a plain map of one source array
+      copy_in(adj16, X.adj, n_adj, [](int32_t x) { return (uint16_t)x; });
+      __syncthreads();
+      for (int i0 = tid; i0 < n_adj; i0 += 8 * kClusterThreads) {
+        int32_t wv[8];
+#pragma unroll
+        for (int z = 0; z < 8; ++z) wv[z] = X.wgt[min(i0 + z * kClusterThreads, n_adj - 1)];
+#pragma unroll
+        for (int z = 0; z < 8; ++z)
+          if (i0 + z * kClusterThreads < n_adj && wv[z] > 0) adj16[i0 + z * kClusterThreads] |= 0x8000u;
+      }
+    } else {
+      copy_in(adj16, X.adj, n_adj, [](int32_t x) { return (uint16_t)x; });
+    }
+  }
+  auto row_at = [&](int i) -> int { return stage ? (int)row16[i] : X.row[i]; };
+  auto adj_at = [&](int e) -> int { return stage ? (int)(adj16[e] & 0x7FFFu) : X.adj[e]; };
+  auto pos_at = [&](int v) -> int { return stage ? (int)pos16[v] : X.pos[v]; };
+
+  auto state_bit = [&](int r, int q) -> uint32_t {
+    return plain ? (X.spins[(int64_t)q * X.R + r] > 0 ? 1u : 0u) : (uint32_t)(X.packed[(int64_t)r * n_pad + q] & 1);
   };
   auto real = [&](int q) { return (q & 3) <= (X.grp[q >> 2] >> kGroupCountShift); };
   // pending lazy snapshots of the plain path: the last sweep improved, so
   // its end state is the best state; take it before the move changes it
-  if (plain && (X.snap[a] == t || X.snap[b] == t)) {
-    for (int q = tid; q < n_pad; q += 256) {
-      if (X.snap[a] == t) X.best[(int64_t)q * X.R + a] = X.spins[(int64_t)q * X.R + a];
-      if (X.snap[b] == t) X.best[(int64_t)q * X.R + b] = X.spins[(int64_t)q * X.R + b];
-    }
-    __syncthreads();
-    if (tid == 0) {
-      if (X.snap[a] == t) X.snap[a] = -2;
-      if (X.snap[b] == t) X.snap[b] = -2;
+  const bool snap_a = plain && X.snap[a] == t, snap_b = plain && X.snap[b] == t;
+  if (snap_a || snap_b) {
+    for (int q = tid; q < n_pad; q += kClusterThreads) {
+      if (snap_a) X.best[(int64_t)q * X.R + a] = X.spins[(int64_t)q * X.R + a];
+      if (snap_b) X.best[(int64_t)q * X.R + b] = X.spins[(int64_t)q * X.R + b];
     }
   }
-  for (int i = tid; i < (n_pad + 31) / 32; i += 256) dmask[i] = 0u;
-  for (int q = tid; q < n_pad; q += 256) mark[q] = 0;
+  // bitmasks: a wave reads 64 consecutive positions and ballots them into
+  // two words
+  const int lane = tid & 63;
+  for (int q0 = tid - lane; q0 < n_pad; q0 += kClusterThreads) {
+    const int q = q0 + lane;
+    const bool in = q < n_pad;
+    const uint64_t ba = __ballot(in && state_bit(a, q));
+    const uint64_t bb = __ballot(in && state_bit(b, q));
+    const uint64_t br = __ballot(in && real(q));
+    if (lane < 2 && (q0 >> 5) + lane < W) {
+      const int i = (q0 >> 5) + lane;
+      const uint32_t wa = (uint32_t)(ba >> (32 * lane)), wb = (uint32_t)(bb >> (32 * lane));
+      abits[i] = wa;
+      bbits[i] = wb;
+      dmask[i] = (wa ^ wb) & (uint32_t)(br >> (32 * lane));
+      mk[i] = 0u;
+    }
+  }
+  for (int q = tid; q < n_pad; q += kClusterThreads) parent[q] = q;
   if (tid == 0) sh_tail = 0;
   __syncthreads();
-  for (int q = tid; q < n_pad; q += 256)
-    if (real(q) && bit_of(a, q) != bit_of(b, q)) atomicOr(&dmask[q >> 5], 1u << (q & 31));
-  __syncthreads();
+  if (tid == 0) {
+    if (snap_a) X.snap[a] = -2;
+    if (snap_b) X.snap[b] = -2;
+  }
   auto in_d = [&](int q) { return (dmask[q >> 5] >> (q & 31)) & 1u; };
   // |D| and the seed: ids in contiguous chunks per lane, an exclusive scan
-  const int chunk = (n + 255) / 256;
+  const int chunk = (n + kClusterThreads - 1) / kClusterThreads;
   const int v0 = min(n, tid * chunk), v1 = min(n, v0 + chunk);
   int cnt = 0;
-  for (int v = v0; v < v1; ++v) cnt += (int)in_d(X.pos[v]);
-  scan[tid] = cnt;
-  __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int i = 0; i < 256; ++i) {
-      const int c = scan[i];
-      scan[i] = acc;
-      acc += c;
-    }
-    sh_total = acc;
-    sh_i0 = -1;
+  for (int v = v0; v < v1; ++v) cnt += (int)in_d(pos_at(v));
+  // exclusive scan of the counts: within each wave by lane shuffles, then
+  // over the waves' totals
+  int incl = cnt;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
   }
+  if (lane == 63) scan[tid >> 6] = incl;
+  if (tid == 0) sh_i0 = -1;
   __syncthreads();
-  const int total = sh_total;
+  int before = 0, total = 0;
+  for (int wv = 0; wv < kClusterThreads / 64; ++wv) {
+    const int c = scan[wv];
+    before += wv < (tid >> 6) ? c : 0;
+    total += c;
+  }
+  const int excl = before + incl - cnt;
   if (total == 0) return;  // uniform: the replicas agree everywhere
   const uint4 x = philox10((uint32_t)m, (uint32_t)k, (uint32_t)p, kTagCluster, X.seed_lo, X.seed_hi);
   const int j = (int)(x.x % (uint32_t)total);
-  if (j >= scan[tid] && j < scan[tid] + cnt) {
-    int left = j - scan[tid];
+  if (j >= excl && j < excl + cnt) {
+    int left = j - excl;
     for (int v = v0; v < v1; ++v)
-      if (in_d(X.pos[v]) && left-- == 0) {
-        sh_i0 = X.pos[v];
+      if (in_d(pos_at(v)) && left-- == 0) {
+        sh_i0 = pos_at(v);
         break;
       }
   }
   __syncthreads();
   if (sh_i0 < 0) return;  // (uniform; cannot happen: j < |D|)
-  // level-synchronous BFS over D from the seed
-  if (tid == 0) {
-    mark[sh_i0] = 1;
-    queue[0] = sh_i0;
-    sh_tail = 1;
-  }
-  __syncthreads();
-  int lo = 0, hi = 1;
-  while (lo < hi) {
-    for (int i = lo + tid; i < hi; i += 256) {
-      const int v = queue[i];
-      for (int e = X.row[v]; e < X.row[v + 1]; ++e) {
-        const int u = X.adj[e];
-        if (in_d(u) && atomicExch(&mark[u], 1) == 0) queue[atomicAdd(&sh_tail, 1)] = u;
+  // Connected components of the subgraph induced by D by concurrent
+  // union-find: every edge inside D hooks the larger of its ends' roots
+  // onto the smaller with a compare-and-swap (retrying when another lane
+  // moved the root first), and finds halve their paths.  The components,
+  // and so the seed's cluster, do not depend on the order of the hooks.
+  volatile int32_t* par = parent;
+  auto find = [&](int v) {
+    int p = par[v];
+    while (p != v) {
+      const int g = par[p];
+      if (g != p) par[v] = g;
+      v = p;
+      p = g;
+    }
+    return v;
+  };
+  for (int q = tid; q < n_pad; q += kClusterThreads) {
+    if (!in_d(q)) continue;
+    const int e1 = row_at(q + 1);
+    for (int e = row_at(q); e < e1; ++e) {
+      const int u = adj_at(e);
+      if (u <= q || !in_d(u)) continue;
+      int x = q, y = u;
+      for (;;) {
+        x = find(x);
+        y = find(y);
+        if (x == y) break;
+        if (x > y) {
+          const int z = x;
+          x = y;
+          y = z;
+        }
+        if (atomicCAS(&parent[y], y, x) == y) break;
       }
     }
-    __syncthreads();
-    lo = hi;
-    hi = sh_tail;
-    __syncthreads();
   }
-  const int size = hi;
-  // flip the cluster in both replicas
-  for (int i = tid; i < size; i += 256) {
-    const int q = queue[i];
-    if (plain) {
-      X.spins[(int64_t)q * X.R + a] = (int8_t)-X.spins[(int64_t)q * X.R + a];
-      X.spins[(int64_t)q * X.R + b] = (int8_t)-X.spins[(int64_t)q * X.R + b];
-    } else {
-      X.packed[(int64_t)a * n_pad + q] ^= 1;
-      X.packed[(int64_t)b * n_pad + q] ^= 1;
-    }
+  __syncthreads();
+  // the seed's cluster as marks, and its size
+  const int root = find(sh_i0);
+  int mine = 0;
+  const int lane2 = tid & 63;
+  for (int q0 = tid - lane2; q0 < n_pad; q0 += kClusterThreads) {
+    const int q = q0 + lane2;
+    const bool inc = q < n_pad && in_d(q) && find(q) == root;
+    const uint64_t bm = __ballot(inc);
+    if (lane2 < 2 && (q0 >> 5) + lane2 < W) mk[(q0 >> 5) + lane2] = (uint32_t)(bm >> (32 * lane2));
+    mine += inc ? 1 : 0;
+  }
+  {
+    const int s2 = wave_sum(mine);
+    if (lane2 == 0 && s2 != 0) atomicAdd(&sh_tail, s2);
+  }
+  __syncthreads();
+  const int size = sh_tail;
+  // flip the cluster in both replicas (the marks are exactly the cluster)
+  for (int i = tid; i < W; i += kClusterThreads) {
+    abits[i] ^= mk[i];
+    bbits[i] ^= mk[i];
   }
   if (tid < 2) esum[tid] = 0;
   __syncthreads();
   // fields and energies from scratch: h = -sum w s, E = -1/2 sum s h
+  auto bit_l = [&](const uint32_t* bits, int q) -> int { return (int)((bits[q >> 5] >> (q & 31)) & 1u); };
   int part[2] = {0, 0};
-  for (int q = tid; q < n_pad; q += 256) {
+  for (int q = tid; q < n_pad; q += kClusterThreads) {
     if (!real(q)) continue;
 #pragma unroll
     for (int z = 0; z < 2; ++z) {
+      const uint32_t* bits = z ? bbits : abits;
       const int r = z ? b : a;
       int h = 0;
-      for (int e = X.row[q]; e < X.row[q + 1]; ++e) h -= X.wgt[e] * (bit_of(r, X.adj[e]) ? 1 : -1);
-      const int sb = bit_of(r, q);
+      const int e1 = row_at(q + 1);
+      if (signs) {
+        // w = +1 (bit 15 set) or -1: h = -sum w s
+        for (int e = row_at(q); e < e1; ++e) {
+          const int en = adj16[e];
+          h += ((en >> 15) ^ bit_l(bits, en & 0x7FFF)) ? 1 : -1;
+        }
+      } else {
+        for (int e = row_at(q); e < e1; ++e) h -= X.wgt[e] * (bit_l(bits, adj_at(e)) ? 1 : -1);
+      }
+      const int sb = bit_l(bits, q);
       part[z] += sb ? h : -h;
-      // (bit 0 of a packed word, read by other lanes, is unchanged here)
-      if (plain) X.field[(int64_t)q * X.R + r] = h;
-      else X.packed[(int64_t)r * n_pad + q] = (h << 1) | sb;
+      if (plain) {
+        X.spins[(int64_t)q * X.R + r] = (int8_t)(sb ? 1 : -1);
+        X.field[(int64_t)q * X.R + r] = h;
+      } else {
+        X.packed[(int64_t)r * n_pad + q] = (h << 1) | sb;
+      }
     }
   }
 #pragma unroll
@@ -1729,11 +1831,24 @@ hipError_t launch_swap(const SwapDev& X, int m, int32_t* clear8, hipStream_t s) 
   return hipGetLastError();
 }
 
+size_t houdayer_lds(int n, int n_pad, int n_adj, bool stage) {
+  const size_t words = 4 * (size_t)((n_pad + 31) / 32);
+  return sizeof(uint32_t) * words +
+         (stage ? sizeof(int32_t) * (size_t)n_pad +
+                      sizeof(uint16_t) * ((size_t)n_pad + 1 + (size_t)n_adj + (size_t)n)
+                : 0);
+}
+
 hipError_t launch_houdayer(const ClusterDev& X, int m, int t, hipStream_t s) {
   const int wgs = X.n_pairs * (X.K - X.from);
   if (wgs <= 0) return hipSuccess;
-  const size_t lds = sizeof(uint32_t) * (size_t)((X.n_pad + 31) / 32);
-  hipLaunchKernelGGL(k_houdayer, dim3(wgs), dim3(256), lds, s, X, m, t);
+  const size_t lds = houdayer_lds(X.n, X.n_pad, X.n_adj, X.stage != 0);
+  if (lds > 48 * 1024) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_houdayer,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) (void)hipGetLastError();  // advisory on this runtime
+  }
+  hipLaunchKernelGGL(k_houdayer, dim3(wgs), dim3(kClusterThreads), lds, s, X, m, t);
   return hipGetLastError();
 }
 

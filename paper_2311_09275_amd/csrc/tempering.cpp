@@ -97,13 +97,17 @@ int ising_temper(ising_problem* p, const ising_tempering* x, uint64_t seed,
   const int n_pairs = cm ? n_sets / 2 : 0;
   const int wgs = n_pairs * (K - (cm ? x->cluster_from : K));
   const size_t cl_stats = (size_t)n_pairs * (size_t)K;
-  const size_t cl_scratch = (size_t)wgs * (size_t)p->g.n_pad;
+  // the BFS queue and the position CSR go to LDS when they fit
+  const int n_adj = (int)(2 * p->g.m);
+  const bool cl_stage = p->g.n_pad < 65536 && n_adj < 65536 &&
+                        houdayer_lds(p->g.n, p->g.n_pad, n_adj, true) <= 150 * 1024;
+  const size_t cl_scratch = cl_stage ? 0 : (size_t)wgs * (size_t)p->g.n_pad;
   const size_t bytes = 2 * DeviceArena::span(sizeof(int32_t) * (size_t)R) +
                        DeviceArena::span(sizeof(long long) * pairs) +
                        DeviceArena::span(sizeof(uint32_t) * T.swap.tq.size()) +
                        2 * DeviceArena::span(sizeof(int32_t) * (size_t)T.swap.S) +
                        2 * DeviceArena::span(sizeof(long long) * cl_stats) +
-                       2 * DeviceArena::span(sizeof(int32_t) * cl_scratch);
+                       DeviceArena::span(sizeof(int32_t) * cl_scratch);
   IRET(T.arena.reserve(bytes));
   SwapDev X;
   memset(&X, 0, sizeof X);
@@ -136,6 +140,9 @@ int ising_temper(ising_problem* p, const ising_tempering* x, uint64_t seed,
   Y.n = p->g.n;
   Y.n_pad = p->g.n_pad;
   Y.R = R;
+  Y.n_adj = n_adj;
+  Y.stage = cl_stage ? 1 : 0;
+  Y.unit = cl_stage && p->g.unit && p->g.n_pad < 32768 ? 1 : 0;
   Y.seed_lo = X.seed_lo;
   Y.seed_hi = X.seed_hi;
   Y.row = p->dg.row;
@@ -155,7 +162,6 @@ int ising_temper(ising_problem* p, const ising_tempering* x, uint64_t seed,
   }
   Y.moves = T.arena.take<long long>(cl_stats);
   Y.sites = T.arena.take<long long>(cl_stats);
-  Y.mark = T.arena.take<int32_t>(cl_scratch);
   Y.queue = T.arena.take<int32_t>(cl_scratch);
   T.cluster = Y;
   T.cluster_on = cm;
