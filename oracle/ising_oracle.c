@@ -135,6 +135,15 @@ int oracle_validate(const or_graph_in* g) {
     uint32_t lo = (uint32_t)(a < b ? a : b), hi = (uint32_t)(a < b ? b : a);
     keys[e] = ((uint64_t)lo << 32) | hi;
   }
+  if (g->field)
+    for (int32_t i = 0; i < g->n; ++i) {
+      const int32_t b = g->field[i];
+      if (b > 32768 || b < -32768) {
+        free(keys);
+        return -1;
+      }
+      total += 2 * (int64_t)(b < 0 ? -b : b);
+    }
   if (total >= ((int64_t)1 << 30)) {
     free(keys);
     return -1;
@@ -161,6 +170,7 @@ typedef struct {
   int32_t* row;  /* [n+1] */
   int32_t* nbr;  /* [2m] neighbour id */
   int32_t* wt;   /* [2m] MaxCut weight w of that edge */
+  int32_t* bf;   /* [n] local fields b, or NULL */
   int32_t n_colours;
   int32_t* colour;       /* [n] */
   int32_t* class_start;  /* [C+1] into members */
@@ -172,6 +182,7 @@ typedef struct {
 } or_graph;
 
 static void graph_free(or_graph* G) {
+  free(G->bf);
   free(G->row);
   free(G->nbr);
   free(G->wt);
@@ -250,9 +261,14 @@ static int graph_build(const or_graph_in* in, or_graph* G) {
     G->W += in->w[e];
   }
   free(fill);
+  if (in->field) {
+    G->bf = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    memcpy(G->bf, in->field, sizeof(int32_t) * (size_t)n);
+  }
+  /* the largest |k|: sum of |w| plus 2 |b| */
   G->kmax = 0;
   for (int32_t i = 0; i < n; ++i) {
-    int64_t s = 0;
+    int64_t s = G->bf ? 2 * (int64_t)(G->bf[i] < 0 ? -G->bf[i] : G->bf[i]) : 0;
     for (int32_t a = G->row[i]; a < G->row[i + 1]; ++a)
       s += G->wt[a] < 0 ? -G->wt[a] : G->wt[a];
     if (s > G->kmax) G->kmax = s;
@@ -317,24 +333,29 @@ int64_t oracle_cut(int32_t n, int64_t m, const int32_t* u, const int32_t* v,
   return cut;
 }
 
-/* Local field h_i = sum_j J_ij s_j = -sum_j w_ij s_j, from scratch. */
+/* Local field h_i = sum_j J_ij s_j + 2 b_i = -sum_j w_ij s_j + 2 b_i, from
+ * scratch. */
 static void fields_from_scratch(const or_graph* G, const int8_t* s,
                                 int64_t* h) {
   for (int32_t i = 0; i < G->n; ++i) {
-    int64_t acc = 0;
+    int64_t acc = G->bf ? 2 * (int64_t)G->bf[i] : 0;
     for (int32_t a = G->row[i]; a < G->row[i + 1]; ++a)
       acc -= (int64_t)G->wt[a] * s[G->nbr[a]];
     h[i] = acc;
   }
 }
 
-/* E(s) = sum_e w_e s_u s_v, from scratch (each edge seen from both ends). */
+/* E(s) = sum_e w_e s_u s_v - 2 sum_v b_v s_v, from scratch (each edge seen
+ * from both ends). */
 static int64_t energy_from_scratch(const or_graph* G, const int8_t* s) {
   int64_t twice = 0;
   for (int32_t i = 0; i < G->n; ++i)
     for (int32_t a = G->row[i]; a < G->row[i + 1]; ++a)
       twice += (int64_t)G->wt[a] * s[i] * s[G->nbr[a]];
-  return twice / 2;
+  int64_t lin = 0;
+  if (G->bf)
+    for (int32_t i = 0; i < G->n; ++i) lin += 2 * (int64_t)G->bf[i] * s[i];
+  return twice / 2 - lin;
 }
 
 static uint64_t splitmix64(uint64_t* x) {
@@ -816,6 +837,8 @@ int oracle_temper(const or_graph_in* gin, const or_temper_in* pt, or_temper_out*
     if (k > 0 && pt->betas[k] < pt->betas[k - 1]) return -1;
   }
   const int32_t g = pt->cluster_moves ? 2 : 1;
+  /* cluster moves rely on spin-reversal symmetry, which fields break */
+  if (pt->cluster_moves && gin->field) return -1;
   if (pt->cluster_moves &&
       (pt->cluster_from < 0 || pt->cluster_from > pt->n_temps || !out->cluster_moves ||
        !out->cluster_sites))

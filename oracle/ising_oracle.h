@@ -15,6 +15,13 @@
  *     cut(s) = (W - E(s)) / 2  with W = sum_e w_e.
  * Work is counted in sweeps (paper Sec. III.A); one sweep here visits every
  * vertex once, colour class by colour class.
+ *
+ * Local fields (the paper notes that some sparse Ising problems have them,
+ * Sec. II.C): with integer b_v,
+ *     E(s) = sum_e w_e s_u s_v - 2 sum_v b_v s_v,
+ *     h_v  = -sum_u w_vu s_u + 2 b_v,       k = s_v h_v as before,
+ * and the reported objective (W - E)/2 becomes cut(s) + sum_v b_v s_v, still
+ * an integer.  |b_v| <= 32768 and sum_v (sum_u |w_vu| + 2 |b_v|) < 2^30.
  */
 #ifndef ISING_ORACLE_H
 #define ISING_ORACLE_H
@@ -33,6 +40,7 @@ typedef struct {
   const int32_t* v;
   const int32_t* w;
   const int32_t* colour; /* NULL: greedy first-fit colouring in index order */
+  const int32_t* field;  /* NULL, or [n] local fields b (see below) */
 } or_graph_in;
 
 typedef struct {

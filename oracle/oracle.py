@@ -32,7 +32,8 @@ def build(force: bool = True) -> str:
 
 class _GraphIn(C.Structure):
     _fields_ = [("n", C.c_int32), ("m", C.c_int64), ("u", C.c_void_p),
-                ("v", C.c_void_p), ("w", C.c_void_p), ("colour", C.c_void_p)]
+                ("v", C.c_void_p), ("w", C.c_void_p), ("colour", C.c_void_p),
+                ("field", C.c_void_p)]
 
 
 class _RunIn(C.Structure):
@@ -142,12 +143,16 @@ def cut(inst, spins) -> int:
 
 
 def _graph(inst, colour=None):
+    """The graph of an instance; its local fields (``inst.field``, when the
+    instance has that attribute and it is not None) go along."""
     u = np.ascontiguousarray(inst.u, np.int32)
     v = np.ascontiguousarray(inst.v, np.int32)
     w = np.ascontiguousarray(inst.w, np.int32)
     col = None if colour is None else np.ascontiguousarray(colour, np.int32)
-    g = _GraphIn(inst.n, inst.m, _p(u), _p(v), _p(w), _p(col))
-    return g, (u, v, w, col)
+    f = getattr(inst, "field", None)
+    f = None if f is None else np.ascontiguousarray(f, np.int32)
+    g = _GraphIn(inst.n, inst.m, _p(u), _p(v), _p(w), _p(col), _p(f))
+    return g, (u, v, w, col, f)
 
 
 def validate(inst, colour=None) -> bool:

@@ -30,6 +30,7 @@ class Instance:
     u: np.ndarray  # int32 [m]
     v: np.ndarray  # int32 [m]
     w: np.ndarray  # int32 [m]
+    field: np.ndarray | None = None  # int32 [n] local fields b, or None
 
     @property
     def m(self) -> int:
@@ -199,3 +200,12 @@ def workload_c3() -> Instance:
 def workload_c4(count: int = 64) -> list[Instance]:
     sides = torus_batch_sides(count, seed=100)
     return [torus(L, L, seed=100 + i + 1) for i, L in enumerate(sides)]
+
+
+def with_fields(inst: Instance, seed: int, bmax: int, density: float = 1.0) -> Instance:
+    """inst with integer local fields b uniform in [-bmax, bmax] on a
+    `density` fraction of the vertices (zero elsewhere)."""
+    rng = _rng(seed + 0xF1E1D)
+    b = rng.integers(-bmax, bmax + 1, size=inst.n)
+    b[rng.random(inst.n) >= density] = 0
+    return Instance(inst.name + f"_b{bmax}", inst.n, inst.u, inst.v, inst.w, b.astype(np.int32))
