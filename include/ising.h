@@ -98,10 +98,11 @@ typedef struct {
   int32_t n, n_colours;
   int64_t m;
   int64_t total_weight;   /* W = sum_e w_e */
-  int32_t kmax;           /* max_i sum_j |w_ij| (largest |k|) */
+  int32_t kmax;           /* max_i (sum_j |w_ij| + 2 |b_i|): the largest |k| */
   int32_t max_degree;
   int32_t unit_weights;   /* 1 when every |w| == 1 (multispin path allowed) */
   int32_t n_padded;       /* vertices after padding each class to 4 */
+  int32_t fields;         /* 1 when nonzero local fields are set */
 } ising_info;
 
 /* Facts about a compiled problem (host-only). */
@@ -118,8 +119,23 @@ int ising_colouring(const ising_problem* p, int32_t* colour);
  * XOR of one fixed bit.  [4n], caller-owned.  ISING_ERR_UNSUPPORTED when
  * the problem has no degree-4 form. */
 int ising_neighbour_labels(const ising_problem* p, int32_t* lab);
-/* MaxCut value of a +-1 assignment in original order (host-only). */
+/* MaxCut value of a +-1 assignment in original order (host-only); the
+ * plain cut, without the field term. */
 int ising_eval_cut(const ising_problem* p, const int8_t* spins, int64_t* cut);
+/*
+ * Local fields (the paper notes that some sparse Ising problems have them,
+ * Sec. II.C): b[v] for every vertex, original order, copied; NULL removes
+ * them.  With fields the energy is E(s) = sum_e w_e s_u s_v - 2 sum_v b_v s_v
+ * (so h_v = -sum_u w_vu s_u + 2 b_v and k = s_v h_v as before), and every
+ * "cut" the library reports (best cuts, per-replica cuts, argmax) is the
+ * objective (W - E)/2 = cut(s) + sum_v b_v s_v.  kmax becomes
+ * max_v (sum_u |w_vu| + 2 |b_v|).  Applies to later runs.  Refused with
+ * fields: the multispin path and the degree-4 adjacency forms (their state
+ * words hold no field; other FIELD forms are chosen), and tempering's
+ * cluster moves (ISING_ERR_UNSUPPORTED).  ISING_ERR_INVALID when some
+ * |b_v| > 32768 or sum_v (sum_u |w_vu| + 2 |b_v|) >= 2^30.
+ */
+int ising_set_fields(ising_problem* p, const int32_t* b);
 
 /* -------------------------------------------------------------- schedule */
 enum { ISING_SCHED_LINEAR = 0, ISING_SCHED_GEOMETRIC = 1, ISING_SCHED_EXPLICIT = 2 };

@@ -83,7 +83,7 @@ class Tempering(C.Structure):
 class Info(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_colours", C.c_int32), ("m", C.c_int64),
                 ("total_weight", C.c_int64), ("kmax", C.c_int32), ("max_degree", C.c_int32),
-                ("unit_weights", C.c_int32), ("n_padded", C.c_int32)]
+                ("unit_weights", C.c_int32), ("n_padded", C.c_int32), ("fields", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -103,6 +103,7 @@ _sig = {
     "ising_colouring": ([P, P], C.c_int),
     "ising_neighbour_labels": ([P, P], C.c_int),
     "ising_eval_cut": ([P, P, C.POINTER(C.c_int64)], C.c_int),
+    "ising_set_fields": ([P, P], C.c_int),
     "ising_threshold_table": ([C.POINTER(Schedule), C.c_int32, P], C.c_int),
     "ising_anneal": ([P, C.POINTER(Schedule), C.c_int32, C.c_uint64, P], C.c_int),
     "ising_anneal_tuned": ([P, C.POINTER(Schedule), C.c_int32, C.c_uint64, C.POINTER(Tuning), P], C.c_int),
@@ -394,7 +395,17 @@ class Problem:
 
     @classmethod
     def from_instance(cls, inst, colour=None) -> "Problem":
-        return cls(inst.n, inst.u, inst.v, inst.w, colour)
+        """The problem of an instance, with its local fields when it has any."""
+        p = cls(inst.n, inst.u, inst.v, inst.w, colour)
+        f = getattr(inst, "field", None)
+        if f is not None:
+            p.set_fields(f)
+        return p
+
+    def set_fields(self, b) -> None:
+        """Local fields b [n] (None removes them); see ``ising_set_fields``."""
+        arr = None if b is None else np.ascontiguousarray(b, np.int32)
+        _check(_L.ising_set_fields(self.handle, _ptr(arr)), "ising_set_fields")
 
     def close(self) -> None:
         if self.handle:

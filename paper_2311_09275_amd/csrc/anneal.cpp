@@ -93,7 +93,8 @@ int upload_graph(const HostGraph& g, DevGraph& d) {
                  3 * DeviceArena::span(sizeof(int32_t) * g.grp.size()) +
                  DeviceArena::span(sizeof(int32_t) * g.cls.size()) +
                  DeviceArena::span(sizeof(int32_t) * g.n) +
-                 DeviceArena::span(sizeof(uint32_t) * g.adj4.size());
+                 DeviceArena::span(sizeof(uint32_t) * g.adj4.size()) +
+                 DeviceArena::span(sizeof(int32_t) * (size_t)g.n_pad);
   IRET(d.arena.reserve(bytes));
   d.device = d.arena.device;
   d.row = d.arena.take<int32_t>(g.n_pad + 1);
@@ -109,6 +110,8 @@ int upload_graph(const HostGraph& g, DevGraph& d) {
   d.cls = d.arena.take<int32_t>(g.cls.size());
   d.pos = d.arena.take<int32_t>(g.n);
   d.adj4 = g.adj4.empty() ? nullptr : d.arena.take<uint32_t>(g.adj4.size());
+  d.bf = d.arena.take<int32_t>((size_t)g.n_pad);
+  ICHK(hipMemcpy(d.bf, g.bpos.data(), sizeof(int32_t) * (size_t)g.n_pad, hipMemcpyHostToDevice));
   if (d.adj4)
     ICHK(hipMemcpy(d.adj4, g.adj4.data(), sizeof(uint32_t) * g.adj4.size(), hipMemcpyHostToDevice));
   ICHK(hipMemcpy(d.row, g.row.data(), sizeof(int32_t) * g.row.size(), hipMemcpyHostToDevice));
@@ -229,8 +232,9 @@ static size_t adjacency_lds(const HostGraph& g, int form) {
   return 12 + 4 * (size_t)g.m + 4 + (size_t)(1024 / 64) * 256 * 4;
 }
 static bool adjacency_fits(const HostGraph& g, int form) {
-  if (form == kFormHbmDeg4) return !g.adj4.empty();
-  if (form == kFormDeg4) return !g.adj4.empty() && g.n_pad < (1 << 15);
+  // the degree-4 forms' bond words carry no field term
+  if (form == kFormHbmDeg4) return !g.adj4.empty() && !g.fields;
+  if (form == kFormDeg4) return !g.adj4.empty() && !g.fields && g.n_pad < (1 << 15);
   return g.unit && g.n_pad < (1 << 15) && 2 * g.m < (1 << 17) && g.max_deg <= 255;
 }
 // The adjacency form that tuning value `adj` (0 decide, 1 LDS, 2 HBM
@@ -274,8 +278,8 @@ int check_config(const HostGraph& g, const Table& t, int R, const PersistentConf
     return ISING_ERR_INVALID;
   }
   if (c.adj == 4 && (c.path != ISING_PATH_FIELD || !adjacency_fits(g, kFormHbmDeg4))) {
-    set_error("the degree-4 adjacency form needs unit weights, every vertex of degree 4 "
-              "and at most 2^16 positions");
+    set_error("the degree-4 adjacency form needs unit weights, every vertex of degree 4, "
+              "at most 2^16 positions and no local fields");
     return ISING_ERR_UNSUPPORTED;
   }
   if ((c.adj == 1 || c.adj == 3) && !form_in_lds(staged_form(g, t, c))) {
@@ -287,6 +291,10 @@ int check_config(const HostGraph& g, const Table& t, int R, const PersistentConf
     return ISING_ERR_UNSUPPORTED;
   }
   if (c.path == ISING_PATH_MSC) {
+    if (g.fields) {
+      set_error("the multispin path has no local field term");
+      return ISING_ERR_UNSUPPORTED;
+    }
     if (!g.unit) {
       set_error("the multispin path needs all |w| == 1");
       return ISING_ERR_UNSUPPORTED;
@@ -519,6 +527,7 @@ JobDev make_job(const HostGraph& g, const DevGraph& d, const RunBuffers& b, int 
   J.accepts = b.accepts;
   J.trace = b.trace_buf;
   J.argmax = b.argmax;
+  J.bfield = g.fields ? d.bf : nullptr;
   return J;
 }
 
@@ -759,6 +768,8 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
 
 using namespace ising;
 
+const int32_t* fields_or_null(const ising_problem* p) { return p->g.fields ? p->dg.bf : nullptr; }
+
 // Arguments of the per-pass kernels for a run of p in b.
 PlainDev make_plain(const ising_problem* p, const RunBuffers& b, int R, uint64_t seed) {
   PlainDev P;
@@ -787,6 +798,7 @@ PlainDev make_plain(const ising_problem* p, const RunBuffers& b, int R, uint64_t
   P.snap = b.snap;
   P.accepts = b.accepts;
   P.trace = b.trace_buf;
+  P.bfield = fields_or_null(p);
   return P;
 }
 
@@ -850,6 +862,7 @@ int ising_problem_info(const ising_problem* p, ising_info* out) {
   i.max_degree = p->g.max_deg;
   i.unit_weights = p->g.unit ? 1 : 0;
   i.n_padded = p->g.n_pad;
+  i.fields = p->g.fields ? 1 : 0;
   *out = i;
   return ISING_OK;
 }
@@ -876,6 +889,46 @@ int ising_eval_cut(const ising_problem* p, const int8_t* spins, int64_t* cut) {
   for (int64_t e = 0; e < p->g.m; ++e)
     if (spins[p->g.u[(size_t)e]] != spins[p->g.v[(size_t)e]]) c += p->g.w[(size_t)e];
   *cut = c;
+  return ISING_OK;
+}
+
+int ising_set_fields(ising_problem* p, const int32_t* b) {
+  if (!p) return ISING_ERR_INVALID;
+  HostGraph& g = p->g;
+  int64_t total = g.abs_total;
+  if (b) {
+    for (int32_t v = 0; v < g.n; ++v) {
+      if (b[v] > 32768 || b[v] < -32768) {
+        set_error("local field of vertex %d outside [-32768, 32768]", v);
+        return ISING_ERR_INVALID;
+      }
+      total += 2 * (int64_t)std::abs(b[v]);
+    }
+    if (total >= ((int64_t)1 << 30)) {
+      set_error("sum over vertices of sum |w| + 2 |b| must stay below 2^30");
+      return ISING_ERR_INVALID;
+    }
+  }
+  // the device copy may still be read by a run in flight
+  if (p->run.valid && p->run.stream) (void)hipStreamSynchronize(p->run.stream);
+  g.bpos.assign((size_t)g.n_pad, 0);
+  g.fields = false;
+  g.kmax = 0;
+  for (int32_t v = 0; v < g.n; ++v) {
+    const int32_t bv = b ? b[v] : 0;
+    g.bpos[(size_t)g.pos[(size_t)v]] = bv;
+    g.fields = g.fields || bv != 0;
+    g.kmax = std::max<int32_t>(g.kmax, (int32_t)(g.wsum[(size_t)v] + 2 * (int64_t)std::abs(bv)));
+  }
+  // thresholds were built for the old kmax
+  p->sched.table = Table();
+  p->sched.kind = -1;
+  p->temper.rows = Table();
+  p->temper.betas.clear();
+  if (p->dg.device >= 0) {
+    DeviceGuard dg(p->dg.device);
+    ICHK(hipMemcpy(p->dg.bf, g.bpos.data(), sizeof(int32_t) * (size_t)g.n_pad, hipMemcpyHostToDevice));
+  }
   return ISING_OK;
 }
 

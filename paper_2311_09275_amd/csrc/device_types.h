@@ -101,6 +101,8 @@ struct JobDev {
   // parallel tempering: row of replica r is temp[r] for every sweep (the
   // rows are then one per temperature); null = row t for sweep t
   const int32_t* temp;
+  // local fields b, position order [n_pad] (h = -sum w s + 2 b), or null
+  const int32_t* bfield;
   int32_t S, t_begin, t_end, flags;
   int32_t kw;            // longest row (LDS row capacity)
   // run
@@ -131,6 +133,7 @@ struct PlainDev {
   const int32_t* tq_off;
   const int32_t* tq_len;
   const int32_t* temp;   // parallel tempering: row of replica r; null = row t
+  const int32_t* bfield; // local fields [n_pad], or null
   uint32_t seed_lo, seed_hi;
   const int8_t* init_spins;  // [R][n_pad] or null
   int8_t* spins;         // [n_pad][R]

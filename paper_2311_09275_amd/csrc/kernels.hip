@@ -160,11 +160,14 @@ __global__ void k_plain_fields(PlainDev P) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)P.n_pad * P.R) return;
   const int p = (int)(idx / P.R), r = (int)(idx - (int64_t)p * P.R);
-  int h = 0;
+  // with local fields h_p = -sum w s + 2 b_p, and the energy sum takes
+  // s (h + 2 b): E = sum w s s - 2 sum b s = -1/2 sum s (h + 2 b)
+  const int bf = P.bfield ? 2 * P.bfield[p] : 0;
+  int h = bf;
   for (int a = P.row[p]; a < P.row[p + 1]; ++a)
     h -= P.wgt[a] * (int)P.spins[(int64_t)P.adj[a] * P.R + r];
   P.field[idx] = h;
-  const int sh = (int)P.spins[idx] * h;
+  const int sh = (int)P.spins[idx] * (h + bf);
   if (sh != 0) atomicAdd(&P.eacc[r], sh);
 }
 
@@ -717,14 +720,16 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
         int a = U.gbase[g];
         for (int i = 0; i < j; ++i) a += (int)((dg >> (8 * i)) & 255u);
         const int d = (int)((dg >> (8 * j)) & 255u);
-        int h = 0;
+        // local fields: h starts at 2 b, and the energy sum takes h + 2 b
+        const int bf = J.bfield ? 2 * J.bfield[p] : 0;
+        int h = bf;
         for (int e = 0; e < d; ++e) {
           const i32x2 q = aw[a + e];
           h -= q.y * ((st[widx(q.x >> 2, q.x & 3)] & 1) ? 1 : -1);
         }
         const int b = st[widx(g, j)] & 1;
         st[widx(g, j)] = (h << 1) | b;
-        part += b ? h : -h;
+        part += b ? h + bf : -(h + bf);
       }
     }
     part = wave_sum(part);

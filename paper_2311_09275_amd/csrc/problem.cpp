@@ -212,12 +212,16 @@ int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, cons
   g.kmax = 0;
   g.max_deg = 0;
   g.unit = true;
+  g.wsum.assign((size_t)n, 0);
+  g.abs_total = 0;
   for (int32_t i = 0; i < n; ++i) {
     int64_t s = 0;
     for (int32_t a = deg[(size_t)i]; a < deg[(size_t)i + 1]; ++a) {
       s += std::abs(nw[(size_t)a]);
       if (std::abs(nw[(size_t)a]) != 1) g.unit = false;
     }
+    g.wsum[(size_t)i] = s;
+    g.abs_total += s;
     g.kmax = std::max<int32_t>(g.kmax, (int32_t)s);
     g.max_deg = std::max<int32_t>(g.max_deg, deg[(size_t)i + 1] - deg[(size_t)i]);
   }
@@ -345,6 +349,8 @@ int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, cons
       }
     }
   }
+  g.fields = false;
+  g.bpos.assign((size_t)g.n_pad, 0);
   return ISING_OK;
 }
 

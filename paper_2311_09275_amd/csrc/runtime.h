@@ -85,6 +85,12 @@ struct HostGraph {
   int64_t W = 0;
   int32_t kmax = 0, max_deg = 0;
   bool unit = true;
+  // local fields b (ising_set_fields): position order, 0 on padding; kmax
+  // is max_v (sum_u |w_vu| + 2 |b_v|)
+  bool fields = false;
+  std::vector<int32_t> bpos;           // [n_pad]
+  std::vector<int64_t> wsum;           // [n] sum_u |w_vu|
+  int64_t abs_total = 0;               // sum_v sum_u |w_vu|
   bool deg4 = false;                   // every vertex has degree 4 (tori)
   int32_t C = 0;
   int32_t n_pad = 0;
@@ -131,6 +137,7 @@ struct DevGraph {
   uint32_t *adjm = nullptr, *gdeg = nullptr;
   uint32_t* adj4 = nullptr;
   int2* aw = nullptr;
+  int32_t* bf = nullptr;  // [n_pad] local fields, position order
 };
 int upload_graph(const HostGraph& g, DevGraph& d);
 
@@ -269,6 +276,8 @@ struct ising_problem {
   } sched;
 };
 
+// Local fields of p's device graph, or null when p has none.
+const int32_t* fields_or_null(const ising_problem* p);
 // Arguments of the per-pass kernels for a run of p in b (anneal.cpp).
 ising::PlainDev make_plain(const ising_problem* p, const ising::RunBuffers& b, int R, uint64_t seed);
 // Launch configuration of tuning t (NULL or ISING_PATH_AUTO: the tuned or

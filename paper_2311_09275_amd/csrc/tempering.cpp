@@ -61,6 +61,10 @@ int ising_temper(ising_problem* p, const ising_tempering* x, uint64_t seed,
     set_error("cluster_from must lie in 0..n_temps");
     return ISING_ERR_INVALID;
   }
+  if (cm && p->g.fields) {
+    set_error("cluster moves rely on spin-reversal symmetry, which local fields break");
+    return ISING_ERR_UNSUPPORTED;
+  }
   if (cm && p->g.n_pad > (1 << 18)) {
     set_error("cluster moves keep a bitmask of the positions in LDS: at most 2^18 positions");
     return ISING_ERR_UNSUPPORTED;

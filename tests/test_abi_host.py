@@ -211,3 +211,30 @@ def test_temper_rejects_bad_ladders(betas, n_sets, S, P):
         p.temper_results()
     assert e.value.status == B.ERR_STATE
     p.close()
+
+
+def test_local_fields_host():
+    """ising_set_fields: kmax becomes max_v (sum |w| + 2 |b|), the info flag
+    follows, bad fields are refused, NULL removes them."""
+    inst = I.with_fields(I.random_weighted(50, 120, 3, 4), 2, 6)
+    p = B.Problem.from_instance(inst)
+    info = p.info()
+    wsum = np.zeros(inst.n, np.int64)
+    np.add.at(wsum, inst.u, np.abs(inst.w))
+    np.add.at(wsum, inst.v, np.abs(inst.w))
+    assert info.fields == 1
+    assert info.kmax == int((wsum + 2 * np.abs(inst.field)).max())
+    with pytest.raises(B.IsingError) as e:
+        p.set_fields(np.full(inst.n, 40000, np.int32))
+    assert e.value.status == B.ERR_INVALID
+    assert p.info().kmax == info.kmax  # a refused call changes nothing
+    p.set_fields(None)
+    assert p.info().fields == 0 and p.info().kmax == int(wsum.max())
+    p.set_fields(np.zeros(inst.n, np.int32))
+    assert p.info().fields == 0
+    p.close()
+    big = I.torus(200, 200, 1)
+    q = B.Problem.from_instance(big)
+    with pytest.raises(B.IsingError):
+        q.set_fields(np.full(big.n, 32768, np.int32))  # total above 2^30
+    q.close()

@@ -73,7 +73,10 @@ def compare(inst, S, R, seed, kind=O.LINEAR, b0=0.1, b1=3.0, betas=None, tuning=
         assert best == per.max()
         assert arg == int(np.argmax(per))
         bstate = p.best_state()
-        assert p.eval_cut(bstate) == best
+        # with local fields the reported value is cut + sum b s
+        f = getattr(inst, "field", None)
+        lin = 0 if f is None else int((f.astype(np.int64) * bstate).sum())
+        assert p.eval_cut(bstate) + lin == best
     p.close()
     return per
 
