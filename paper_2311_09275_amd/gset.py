@@ -10,16 +10,20 @@ A binary value x maps to the spin s = 2x - 1; the cut is the same for s and
 
     python -m paper_2311_09275_amd.gset solve GRAPH.txt --sweeps 4000 --replicas 256 \\
         --beta0 0.1 --beta1 4.0 --target 14030 [--hex-out best.txt]
+    python -m paper_2311_09275_amd.gset solve GRAPH.txt --temps 32 --sets 8 --swap-every 10 \\
+        --beta0 0.2 --beta1 3.0 [--cluster-from 16]   (parallel tempering, geometric ladder)
     python -m paper_2311_09275_amd.gset verify GRAPH.txt SOLUTION_HEX.txt
 
-`solve` anneals on the GPU through the C ABI and reports the best cut, the
-success probability of the target and the time to target (Eq. 1-2, one
-replica per trial); `verify` evaluates a bitstring's cut on the host.
+`solve` anneals (or, with --temps, runs parallel tempering) on the GPU
+through the C ABI and reports the best cut, the success probability of the
+target and the time to target (Eq. 1-2; one replica per trial, one set per
+trial for tempering); `verify` evaluates a bitstring's cut on the host.
 """
 from __future__ import annotations
 
 import argparse
 import io
+import json
 import os
 import sys
 import time
@@ -120,7 +124,12 @@ def _solve(args) -> int:
                             args.beta1)
     t = time.perf_counter()  # the paper's t_trial counts pre-processing (Sec. III.A)
     p = B.Problem.from_instance(inst)
-    p.anneal(sched, args.replicas, args.seed, stream=stream)
+    if args.temps:
+        ladder = np.geomspace(args.beta0, args.beta1, args.temps) if args.temps > 1 else [args.beta1]
+        p.temper(list(ladder), args.sets, args.sweeps, args.swap_every, args.seed, stream=stream,
+                 cluster_from=args.cluster_from)
+    else:
+        p.anneal(sched, args.replicas, args.seed, stream=stream)
     res = p.cut()
     wall = time.perf_counter() - t
     spins = p.best_state()
@@ -128,13 +137,15 @@ def _solve(args) -> int:
     bits = bits_from_spins(spins)
     assert cut_value(inst, bits) == res.best_cut
     out = {"graph": inst.name, "n": inst.n, "m": inst.m, "best_cut": int(res.best_cut),
-           "replicas": args.replicas, "sweeps": args.sweeps, "wall_s": wall}
+           "replicas": int(res.per_replica.size), "sweeps": args.sweeps, "wall_s": wall}
     if args.target is not None:
-        out.update(ttt.replica_ttt(res.per_replica, args.target, wall, args.sweeps))
+        trials = res.per_replica.reshape(args.sets, args.temps).max(axis=1) if args.temps \
+            else res.per_replica
+        out.update(ttt.replica_ttt(trials, args.target, wall, args.sweeps))
     if args.hex_out:
         with open(args.hex_out, "w") as f:
             f.write(hex_from_bits(bits) + "\n")
-    print(out)
+    print(json.dumps(out))
     return 0
 
 
@@ -159,6 +170,11 @@ def main(argv=None) -> int:
     s.add_argument("--seed", type=int, default=1)
     s.add_argument("--target", type=int, default=None)
     s.add_argument("--hex-out", default=None)
+    s.add_argument("--temps", type=int, default=0, help="parallel tempering: temperatures per set")
+    s.add_argument("--sets", type=int, default=8)
+    s.add_argument("--swap-every", type=int, default=10)
+    s.add_argument("--cluster-from", type=int, default=None,
+                   help="Houdayer cluster moves at temperatures >= this index")
     v = sub.add_parser("verify", help="cut of a hexadecimal solution string")
     v.add_argument("graph")
     v.add_argument("solution")

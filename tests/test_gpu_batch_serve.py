@@ -183,3 +183,22 @@ def test_serving_admission_under_memory_pressure():
         assert B.ising_cut(p.handle, R)[0] == res[0]
     for p in probs:
         p.close()
+
+
+def test_serving_with_local_fields():
+    """Served requests on problems with local fields equal one-shot anneals
+    and the oracle (the objective cut + sum b s)."""
+    insts = [I.with_fields(I.torus(20, 18, 211), 1, 3), I.torus(16, 16, 212),
+             I.with_fields(I.random_graph(600, 700, 213), 2, 2, 0.5)]
+    probs = [B.Problem.from_instance(x) for x in insts]
+    S = 200
+    sched = B.Schedule.make(B.LINEAR, S, 0.1, 3.0)
+    reqs = [(p, sched, 32, 400 + i, 10 ** 9, 50) for i, p in enumerate(probs)]
+    mixed, _ = _serve(reqs, chunk=37, slots=2)
+    for x, req, res in zip(insts, reqs, mixed):
+        p, s, R, seed, target, ce = req
+        o = O.anneal(x, S, R, seed, kind=O.LINEAR, beta0=0.1, beta1=3.0)
+        assert res[0] == int(o.best_cut.max()) and res[1] == o.argmax()
+        np.testing.assert_array_equal(res[4], o.best_state[o.argmax()])
+    for p in probs:
+        p.close()

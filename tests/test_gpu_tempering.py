@@ -196,3 +196,12 @@ def test_cluster_moves_full_size_sampled_pairs():
     temperatures: the oracle checks one pair of sets over 400 sweeps."""
     compare(I.workload_c2(), list(np.geomspace(0.2, 3.0, 32)), 8, 400, 10, 1002, None,
             sets=(2, 4), states=False, cluster_from=16)
+
+
+@pytest.mark.parametrize("path", ["plain", "field_g1_b256_hbmadj"])
+def test_interval_longer_than_run(path):
+    """P > S: no exchange round at all; every replica anneals at its
+    starting temperature."""
+    o = compare(I.torus(9, 8, 4), [0.3, 0.9, 1.8], 2, 25, 40, 54, PATHS[path])
+    assert (o.swaps == 0).all()
+    np.testing.assert_array_equal(o.final_temp, np.tile(np.arange(3), 2))
