@@ -93,6 +93,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-torus batch leg")
     ap.add_argument("--no-random", action="store_true", help="skip the sparse random graph leg")
     ap.add_argument("--no-temper", action="store_true", help="skip the parallel tempering leg")
+    ap.add_argument("--no-msc", action="store_true", help="skip the multispin leg")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests of the Poisson serving leg (0 = skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
@@ -168,6 +169,19 @@ def main():
         plain_ms = float(np.mean(walls_p)) * 1e3
         assert np.array_equal(res_p.per_replica, per_rep), "plain and persistent forms disagree"
 
+    # multispin form (32 replicas per word) on the same seeds: identical
+    # results; its time and, below, its ALU roofline fraction
+    msc_leg = None
+    if not args.no_msc:
+        msc_leg = {"workload": "the benchmark anneal on the multispin path", "configs": {}}
+        for name, tun in (("words1_threads256", B.Tuning(B.PATH_MSC, 1, 256, 0)),
+                          ("words2_threads512", B.Tuning(B.PATH_MSC, 2, 512, 0))):
+            res_m, walls_m, kern_m = run_steps(tun, 2, 1)
+            assert np.array_equal(res_m.per_replica, per_rep), "multispin and field forms disagree"
+            msc_leg["configs"][name] = {"ms_per_anneal": float(np.mean(walls_m)) * 1e3,
+                                        "kernel_ms": float(np.mean(kern_m)),
+                                        "attempts_per_s": attempts / float(np.mean(walls_m))}
+
     # ------------------------------------------------------------ time to target
     # Reference best cut of this instance: a longer anneal of 1024 replicas
     # (512-thread blocks, so that its dispatches are told apart in profiles).
@@ -209,9 +223,19 @@ def main():
         cuts_p = [B.ising_cut(h)[0] for h in handles]
         plain_b_s = time.perf_counter() - t
         assert cuts_b == cuts_p, "batched and plain forms disagree"
+        # the batch on the multispin path (one 32-replica word per unit)
+        msc_b = B.Tuning(B.PATH_MSC, 1, 256, 0)
+        B.ising_anneal_batch(handles, sched, Rb, seeds, msc_b, stream=stream)  # warm (captures)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        B.ising_anneal_batch(handles, sched, Rb, seeds, msc_b, stream=stream)
+        cuts_m = [B.ising_cut(h)[0] for h in handles]
+        msc_b_s = time.perf_counter() - t
+        assert cuts_m == cuts_p, "batched multispin and plain forms disagree"
         batch = {"workload": "64 LxL +-1 tori, L~U{32..141}, 128 replicas, 4000 sweeps geometric 0.1->4.0",
                  "attempts": bat_att, "batched_s": bat_s, "plain_s": plain_b_s,
                  "batched_attempts_per_s": bat_att / bat_s, "plain_attempts_per_s": bat_att / plain_b_s,
+                 "msc_s": msc_b_s, "msc_attempts_per_s": bat_att / msc_b_s,
                  "tuning": {"path": int(tun.path), "replicas_per_block": int(tun.replicas_per_block),
                             "block_threads": int(tun.block_threads),
                             "lds_adjacency": int(tun.lds_adjacency)}}
@@ -379,6 +403,9 @@ def main():
                        accepts_per_attempt * (2.0 + mean_degree))
     achieved = ops_per_attempt * attempts / (kern_ms / 1e3)
     rates = B.ising_valu_rates()
+    if msc_leg is not None:
+        for cfg_ in msc_leg["configs"].values():
+            cfg_["alu_frac"] = ops_per_attempt * attempts / (cfg_["kernel_ms"] / 1e3) / VALU_PEAK_PER_S
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_PER_S / 1e12,
                 "unit": "T int32 ops/s", "frac": achieved / VALU_PEAK_PER_S,
                 "traffic": measured_traffic(), "valu_issue_frac": measured_valu_issue(),
@@ -404,6 +431,7 @@ def main():
         "batch": batch,
         "random_graph": random_leg,
         "tempering": temper_leg,
+        "multispin": msc_leg,
         "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
