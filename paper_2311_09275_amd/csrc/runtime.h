@@ -249,8 +249,6 @@ struct TemperState {
   std::vector<double> betas;      // ladder the tables were built for
   ising::Table rows;              // flip thresholds, one row per temperature
   ising::Table swap;              // exchange thresholds, one row per pair
-  std::vector<uint32_t> swap_tq;  // host copies behind the async uploads
-  std::vector<int32_t> swap_off, swap_len;
   ising::SwapDev dev{};
   ising::ClusterDev cluster{};
   bool cluster_on = false;
