@@ -41,6 +41,7 @@
  */
 #ifndef ISING_H
 #define ISING_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -62,6 +63,26 @@ const char* ising_status_string(int status);
 /* Detail of the last error raised on the calling thread (thread-local
  * storage, valid until the thread's next failing call). */
 const char* ising_last_error(void);
+
+/*
+ * Device memory (optional).  By default the library takes its device memory
+ * (problem graphs, run buffers, launch structures, tempering state, server
+ * pools) with hipMalloc and returns it with hipFree.  A caller may route it
+ * through its own allocator, e.g. PyTorch's caching allocator:
+ *   alloc(bytes, device, ctx) returns device memory of `device` (the
+ *   current device at the call), at least `bytes`, 256-byte aligned, or
+ *   NULL (the library call then fails with ISING_ERR_NOMEM);
+ *   free(ptr, bytes, device, ctx) takes back exactly what alloc returned.
+ * Memory is returned through the functions it was obtained with, even
+ * after the allocator changes; before calling free the library waits for
+ * the device to finish (the allocator may reuse the memory at once).  Both
+ * NULL restores hipMalloc/hipFree; one NULL is ISING_ERR_INVALID.  Affects
+ * later allocations only.  The functions may be called from the server's
+ * scheduler thread.
+ */
+typedef void* (*ising_alloc_fn)(size_t bytes, int device, void* ctx);
+typedef void (*ising_free_fn)(void* ptr, size_t bytes, int device, void* ctx);
+int ising_set_allocator(ising_alloc_fn alloc, ising_free_fn free_fn, void* ctx);
 
 /* --------------------------------------------------------------- problem */
 typedef struct ising_problem ising_problem;

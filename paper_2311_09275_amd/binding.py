@@ -94,9 +94,12 @@ class Result(C.Structure):
 
 
 P = C.c_void_p
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
 _sig = {
     "ising_status_string": ([C.c_int], C.c_char_p),
     "ising_last_error": ([], C.c_char_p),
+    "ising_set_allocator": ([ALLOC_FN, FREE_FN, P], C.c_int),
     "ising_create": ([C.c_int32, C.c_int64, P, P, P, P, C.POINTER(C.c_void_p)], C.c_int),
     "ising_destroy": ([P], C.c_int),
     "ising_problem_info": ([P, C.POINTER(Info)], C.c_int),
@@ -137,6 +140,32 @@ for _name, (_args, _res) in _sig.items():
     _f.argtypes = _args
     _f.restype = _res
 EXPORTED = tuple(_sig)
+
+
+_allocator = None  # the ctypes callbacks in use (kept alive here)
+
+
+def set_allocator(alloc=None, free=None) -> None:
+    """Route the library's device memory through alloc(bytes, device) ->
+    int address and free(address, bytes, device); no arguments restores
+    hipMalloc/hipFree (see ising_set_allocator)."""
+    global _allocator
+    if alloc is None and free is None:
+        _check(_L.ising_set_allocator(ALLOC_FN(), FREE_FN(), None), "ising_set_allocator")
+        _allocator = None
+        return
+    a = ALLOC_FN(lambda n, dev, ctx: int(alloc(int(n), int(dev)) or 0))
+    f = FREE_FN(lambda p, n, dev, ctx: free(int(p), int(n), int(dev)))
+    _check(_L.ising_set_allocator(a, f, None), "ising_set_allocator")
+    _allocator = (a, f)
+
+
+def use_torch_allocator() -> None:
+    """Take the library's device memory from PyTorch's caching allocator."""
+    import torch
+
+    set_allocator(lambda n, dev: torch.cuda.caching_allocator_alloc(n, device=dev),
+                  lambda p, n, dev: torch.cuda.caching_allocator_delete(p))
 
 
 def _check(rc: int, where: str) -> None:

@@ -11,13 +11,69 @@
 namespace ising {
 
 // ---------------------------------------------------------------- memory
+namespace {
+std::mutex g_alloc_mu;
+ising_alloc_fn g_alloc = nullptr;
+ising_free_fn g_free = nullptr;
+void* g_alloc_ctx = nullptr;
+}  // namespace
+
+int device_alloc(size_t bytes, DeviceBlock& out) {
+  out = DeviceBlock();
+  if (hipGetDevice(&out.device) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("no HIP device");
+    return ISING_ERR_DEVICE;
+  }
+  ising_alloc_fn a;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    a = g_alloc;
+    out.free_fn = g_free;
+    out.ctx = g_alloc_ctx;
+  }
+  if (a) {
+    out.ptr = a(bytes, out.device, out.ctx);
+    if (!out.ptr || (reinterpret_cast<uintptr_t>(out.ptr) & 255u)) {
+      set_error("the caller's allocator returned %s for %zu bytes",
+                out.ptr ? "memory not aligned to 256 bytes" : "no memory", bytes);
+      if (out.ptr) out.free_fn(out.ptr, bytes, out.device, out.ctx);
+      out.ptr = nullptr;
+      return ISING_ERR_NOMEM;
+    }
+  } else {
+    out.free_fn = nullptr;
+    hipError_t e = hipMalloc(&out.ptr, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      out.ptr = nullptr;
+      set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? ISING_ERR_NOMEM : ISING_ERR_DEVICE;
+    }
+  }
+  out.bytes = bytes;
+  return ISING_OK;
+}
+
+void device_free(DeviceBlock& b) {
+  if (!b.ptr) return;
+  DeviceGuard g(b.device);
+  if (b.free_fn) {
+    // the caller's allocator may hand the memory out again at once: let
+    // every kernel that could still read it finish first
+    (void)hipDeviceSynchronize();
+    b.free_fn(b.ptr, b.bytes, b.device, b.ctx);
+  } else {
+    (void)hipFree(b.ptr);
+  }
+  b = DeviceBlock();
+}
+
 DeviceArena::~DeviceArena() { release(); }
 
 void DeviceArena::release() {
-  if (base && owned) {
-    DeviceGuard g(device);
-    (void)hipFree(base);
-  }
+  if (base && owned) device_free(block);
+  block = DeviceBlock();
   base = nullptr;
   cap = used = 0;
   owned = true;
@@ -28,18 +84,9 @@ int DeviceArena::reserve(size_t bytes) {
   if (bytes <= cap && base && owned) return ISING_OK;
   release();
   bytes = std::max<size_t>(bytes, 4096);
-  if (hipGetDevice(&device) != hipSuccess) {
-    set_error("no HIP device");
-    return ISING_ERR_DEVICE;
-  }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-    return e == hipErrorOutOfMemory ? ISING_ERR_NOMEM : ISING_ERR_DEVICE;
-  }
-  base = static_cast<char*>(p);
+  IRET(device_alloc(bytes, block));
+  device = block.device;
+  base = static_cast<char*>(block.ptr);
   cap = bytes;
   ++generation;
   return ISING_OK;
@@ -819,6 +866,18 @@ const char* ising_status_string(int status) {
 }
 
 const char* ising_last_error(void) { return last_error(); }
+
+int ising_set_allocator(ising_alloc_fn alloc, ising_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) {
+    set_error("give both an allocation and a free function, or neither");
+    return ISING_ERR_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc = alloc;
+  g_free = free_fn;
+  g_alloc_ctx = ctx;
+  return ISING_OK;
+}
 
 int ising_create(int32_t n, int64_t m, const int32_t* u, const int32_t* v, const int32_t* w,
                  const int32_t* colour, ising_problem** out) {

@@ -45,11 +45,25 @@ struct DeviceGuard {
   }
 };
 
+// Device memory of the library: hipMalloc, or the caller's allocator
+// (ising_set_allocator).  A block remembers how it was obtained, so it is
+// returned the same way even if the allocator changes meanwhile.
+struct DeviceBlock {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+  ising_free_fn free_fn = nullptr;  // null: hipFree
+  void* ctx = nullptr;
+};
+int device_alloc(size_t bytes, DeviceBlock& out);
+void device_free(DeviceBlock& b);
+
 // One device allocation carved into 256-byte aligned pieces.
 struct DeviceArena {
   char* base = nullptr;
   size_t cap = 0, used = 0;
   int device = -1;
+  DeviceBlock block;  // what reserve() obtained (owned memory only)
   bool owned = true;  // false: memory lent by a pool, not freed here
   uint64_t generation = 0;  // bumped whenever the memory behind base changes
   void adopt(char* p, size_t bytes, int dev) {

@@ -118,6 +118,7 @@ struct ising_server {
   std::map<uint64_t, std::shared_ptr<Request>> all;
   uint64_t next_ticket = 1;
   Pool pool;
+  DeviceBlock pool_block;
   char* pool_mem = nullptr;
   uint64_t budget = 0;
   int max_slots = 1, chunk = 50, backend = 0, device = -1;
@@ -314,15 +315,11 @@ int ising_server_create(uint64_t hbm_budget, int32_t max_slots, int32_t chunk_sw
       set_error("no HIP device available");
       return ISING_ERR_DEVICE;
     }
-    void* mem = nullptr;
-    hipError_t e = hipMalloc(&mem, hbm_budget);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
+    if (device_alloc(hbm_budget, s->pool_block) != ISING_OK) {
       delete s;
-      set_error("server pool of %llu bytes: %s", (unsigned long long)hbm_budget, hipGetErrorString(e));
       return ISING_ERR_NOMEM;
     }
-    s->pool_mem = static_cast<char*>(mem);
+    s->pool_mem = static_cast<char*>(s->pool_block.ptr);
     s->pool.init(s->pool_mem, hbm_budget);
   } else {
     // offsets only: a base far from any real mapping, never dereferenced
@@ -331,7 +328,7 @@ int ising_server_create(uint64_t hbm_budget, int32_t max_slots, int32_t chunk_sw
   try {
     s->th = std::thread(scheduler, s);
   } catch (...) {
-    if (s->pool_mem) (void)hipFree(s->pool_mem);
+    device_free(s->pool_block);
     delete s;
     return ISING_ERR_NOMEM;
   }
@@ -429,7 +426,7 @@ int ising_server_destroy(ising_server* s) {
   {
     DeviceGuard g(s->device);
     for (auto& kv : s->all) kv.second->buf.arena.release();
-    if (s->pool_mem) (void)hipFree(s->pool_mem);
+    device_free(s->pool_block);
   }
   delete s;
   return ISING_OK;

@@ -238,3 +238,9 @@ def test_local_fields_host():
     with pytest.raises(B.IsingError):
         q.set_fields(np.full(big.n, 32768, np.int32))  # total above 2^30
     q.close()
+
+
+def test_allocator_needs_both_functions():
+    a = B.ALLOC_FN(lambda n, dev, ctx: 0)
+    assert B._L.ising_set_allocator(a, B.FREE_FN(), None) == B.ERR_INVALID
+    assert B._L.ising_set_allocator(B.ALLOC_FN(), B.FREE_FN(), None) == B.OK
