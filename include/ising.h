@@ -235,6 +235,35 @@ int ising_anneal_tuned(ising_problem* p, const ising_schedule* s,
                        const ising_tuning* tuning, void* stream);
 
 /*
+ * Sweeps [t_begin, t_end) of an anneal (0 <= t_begin < t_end <= S).  With
+ * t_begin = 0 it starts afresh like ising_anneal_tuned (which is the range
+ * [0, S)); otherwise it continues the problem's last run, which must have
+ * the same schedule, replica count and seed and have stopped at t_begin
+ * (ISING_ERR_STATE otherwise), in that run's launch configuration.  A run
+ * cut into ranges gives the same results, bit for bit, as one call; the
+ * results of each range (best cuts so far, states) can be read between
+ * ranges.  Errors otherwise as ising_anneal_tuned.
+ */
+int ising_anneal_range(ising_problem* p, const ising_schedule* s, int32_t n_replicas,
+                       uint64_t seed, const ising_tuning* tuning, int32_t t_begin,
+                       int32_t t_end, void* stream);
+
+/*
+ * Checkpoints of an anneal (after ising_anneal or a range of it; not of a
+ * tempering run): the whole device state of the run in a caller-owned host
+ * buffer of ising_checkpoint_size bytes (synchronises).  ising_checkpoint_load
+ * puts such a buffer back into a problem compiled from the same graph, given
+ * the same schedule (ISING_ERR_INVALID otherwise) and the same tracing and
+ * initial-state settings (ISING_ERR_STATE otherwise); its results can then
+ * be read, and ising_anneal_range continues it from the sweep it had reached.
+ * The buffer format belongs to this build of the library.
+ */
+int ising_checkpoint_size(const ising_problem* p, uint64_t* bytes);
+int ising_checkpoint_save(ising_problem* p, void* buf);
+int ising_checkpoint_load(ising_problem* p, const ising_schedule* s, const void* buf,
+                          uint64_t bytes, void* stream);
+
+/*
  * Initial states for subsequent anneals: spins[r*n + i] in {-1,+1}, original
  * order, for r < n_replicas; NULL restores the Philox initial draw.  An
  * anneal with a different R than given here is rejected (ISING_ERR_STATE).

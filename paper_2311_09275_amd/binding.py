@@ -110,6 +110,11 @@ _sig = {
     "ising_threshold_table": ([C.POINTER(Schedule), C.c_int32, P], C.c_int),
     "ising_anneal": ([P, C.POINTER(Schedule), C.c_int32, C.c_uint64, P], C.c_int),
     "ising_anneal_tuned": ([P, C.POINTER(Schedule), C.c_int32, C.c_uint64, C.POINTER(Tuning), P], C.c_int),
+    "ising_anneal_range": ([P, C.POINTER(Schedule), C.c_int32, C.c_uint64, C.POINTER(Tuning), C.c_int32,
+                            C.c_int32, P], C.c_int),
+    "ising_checkpoint_size": ([P, C.POINTER(C.c_uint64)], C.c_int),
+    "ising_checkpoint_save": ([P, P], C.c_int),
+    "ising_checkpoint_load": ([P, C.POINTER(Schedule), P, C.c_uint64, P], C.c_int),
     "ising_set_initial_state": ([P, P, C.c_int32], C.c_int),
     "ising_set_trace": ([P, C.c_int32], C.c_int),
     "ising_cut": ([P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), P], C.c_int),
@@ -459,6 +464,27 @@ class Problem:
     def anneal(self, sched: Schedule, n_replicas: int, seed: int, tuning: Tuning | None = None,
                stream=None) -> None:
         ising_anneal_tuned(self.handle, sched, n_replicas, seed, tuning, stream)
+
+    def anneal_range(self, sched: Schedule, n_replicas: int, seed: int, t_begin: int, t_end: int,
+                     tuning: Tuning | None = None, stream=None) -> None:
+        """Sweeps [t_begin, t_end) of an anneal (see ``ising_anneal_range``)."""
+        _check(_L.ising_anneal_range(self.handle, C.byref(sched), n_replicas, seed & (2**64 - 1),
+                                     None if tuning is None else C.byref(tuning), t_begin, t_end,
+                                     _stream(stream)), "ising_anneal_range")
+
+    def checkpoint(self) -> bytes:
+        """The device state of the last anneal (see ``ising_checkpoint_save``)."""
+        n = C.c_uint64()
+        _check(_L.ising_checkpoint_size(self.handle, C.byref(n)), "ising_checkpoint_size")
+        buf = (C.c_char * n.value)()
+        _check(_L.ising_checkpoint_save(self.handle, buf), "ising_checkpoint_save")
+        return bytes(buf)
+
+    def restore(self, sched: Schedule, data: bytes, stream=None) -> None:
+        """Put a checkpoint back (see ``ising_checkpoint_load``)."""
+        buf = C.create_string_buffer(data, len(data))
+        _check(_L.ising_checkpoint_load(self.handle, C.byref(sched), buf, len(data), _stream(stream)),
+               "ising_checkpoint_load")
 
     def temper(self, betas, n_sets: int, n_sweeps: int, swap_every: int, seed: int,
                tuning: Tuning | None = None, stream=None, cluster_from=None) -> None:

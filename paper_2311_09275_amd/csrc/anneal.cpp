@@ -1060,36 +1060,177 @@ static int schedule_table(ising_problem* p, const ising_schedule* s) {
   return ISING_OK;
 }
 
-int ising_anneal_tuned(ising_problem* p, const ising_schedule* s, int32_t n_replicas,
-                       uint64_t seed, const ising_tuning* tuning, void* stream) {
+int ising_anneal_range(ising_problem* p, const ising_schedule* s, int32_t n_replicas,
+                       uint64_t seed, const ising_tuning* tuning, int32_t t_begin, int32_t t_end,
+                       void* stream) {
   if (!p || !s || n_replicas < 1) return ISING_ERR_INVALID;
   IRET(schedule_table(p, s));
   const Table& table = p->sched.table;
+  if (t_begin < 0 || t_end <= t_begin || t_end > table.S) {
+    set_error("sweep range [%d, %d) outside the schedule's %d sweeps", t_begin, t_end, table.S);
+    return ISING_ERR_INVALID;
+  }
   IRET(ensure_device(p));
   DeviceGuard dg(p->dg.device);
-  PersistentConfig cfg;
-  IRET(resolve_config(p, table, n_replicas, tuning, cfg));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  IRET(prepare_run(p, table, n_replicas, cfg, st));
   RunBuffers& b = p->run;
+  PersistentConfig cfg;
+  if (t_begin == 0) {
+    IRET(resolve_config(p, table, n_replicas, tuning, cfg));
+    IRET(prepare_run(p, table, n_replicas, cfg, st));
+  } else {
+    // a continuation: the same run, schedule and seed, at the sweep where
+    // the last range stopped, in the launch configuration it used
+    if (!b.valid || p->temper.valid || b.R != n_replicas || b.seed != seed ||
+        b.t_done != t_begin || b.S != table.S || b.up_table != table.id || b.trace != p->trace) {
+      set_error("no run of this schedule, seed and replica count stopped at sweep %d", t_begin);
+      return ISING_ERR_STATE;
+    }
+    cfg = b.cfg;
+    if (b.stream != st) ICHK(hipStreamSynchronize(b.stream));
+    b.stream = st;
+  }
   p->temper.valid = false;
+  b.valid = false;
   if (cfg.path == ISING_PATH_PLAIN) {
     PlainDev P = make_plain(p, b, n_replicas, seed);
     static thread_local JobDev hjob;
-    hjob = make_job(p->g, p->dg, b, n_replicas, seed, 0, table.S, cfg);
+    hjob = make_job(p->g, p->dg, b, n_replicas, seed, t_begin, t_end, cfg);
     ICHK(hipMemcpy(b.job_dev, &hjob, sizeof(JobDev), hipMemcpyHostToDevice));
     PlainPlan plan{table.S, p->g.C, p->g.cls.data()};
+    plan.t_begin = t_begin;
+    plan.t_end = t_end;
     ICHK(hipEventRecord(b.ev0, st));
     ICHK(launch_plain_anneal(P, plan, st));
     ICHK(launch_argmax(b.job_dev, 1, st));
     ICHK(hipEventRecord(b.ev1, st));
   } else {
-    std::vector<JobSpec> js{JobSpec{&p->g, &p->dg, &b, n_replicas, seed, 0, table.S}};
+    std::vector<JobSpec> js{JobSpec{&p->g, &p->dg, &b, n_replicas, seed, t_begin, t_end}};
     ICHK(hipEventRecord(b.ev0, st));
     IRET(run_persistent(p->launcher, js, cfg, st, st != nullptr));
     ICHK(hipEventRecord(b.ev1, st));
   }
+  b.cfg = cfg;
+  b.seed = seed;
+  b.t_done = t_end;
   b.valid = true;
+  return ISING_OK;
+}
+
+int ising_anneal_tuned(ising_problem* p, const ising_schedule* s, int32_t n_replicas,
+                       uint64_t seed, const ising_tuning* tuning, void* stream) {
+  if (!p || !s || s->n_sweeps < 1) return ISING_ERR_INVALID;
+  return ising_anneal_range(p, s, n_replicas, seed, tuning, 0, s->n_sweeps, stream);
+}
+
+// ---------------------------------------------------------------- checkpoint
+namespace {
+struct CheckpointHeader {
+  uint64_t magic;
+  int32_t version, R, S, path, G, block, adj, t_done, n_pad, trace, init;
+  uint64_t seed, arena_used, table_hash;
+};
+constexpr uint64_t kCheckpointMagic = 0x31544B4347534949ull;  // "IISGCKT1"
+
+uint64_t table_hash(const Table& t) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the rows
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  };
+  mix(t.tq.data(), sizeof(uint32_t) * t.tq.size());
+  mix(t.off.data(), sizeof(int32_t) * t.off.size());
+  mix(t.len.data(), sizeof(int32_t) * t.len.size());
+  mix(&t.kmax, sizeof t.kmax);
+  return h;
+}
+}  // namespace
+
+int ising_checkpoint_size(const ising_problem* p, uint64_t* bytes) {
+  if (!p || !bytes) return ISING_ERR_INVALID;
+  if (!p->run.valid || p->temper.valid) {
+    set_error("no anneal to checkpoint");
+    return ISING_ERR_STATE;
+  }
+  *bytes = sizeof(CheckpointHeader) + p->run.arena.used;
+  return ISING_OK;
+}
+
+int ising_checkpoint_save(ising_problem* p, void* buf) {
+  uint64_t bytes = 0;
+  if (!buf) return ISING_ERR_INVALID;
+  IRET(ising_checkpoint_size(p, &bytes));
+  RunBuffers& b = p->run;
+  DeviceGuard g(p->dg.device);
+  ICHK(hipStreamSynchronize(b.stream));
+  CheckpointHeader h;
+  memset(&h, 0, sizeof h);
+  h.magic = kCheckpointMagic;
+  h.version = 1;
+  h.R = b.R;
+  h.S = b.S;
+  h.path = b.cfg.path;
+  h.G = b.cfg.G;
+  h.block = b.cfg.block;
+  h.adj = b.cfg.adj;
+  h.t_done = b.t_done;
+  h.n_pad = p->g.n_pad;
+  h.trace = b.trace ? 1 : 0;
+  h.init = b.init_dev ? 1 : 0;
+  h.seed = b.seed;
+  h.arena_used = b.arena.used;
+  h.table_hash = table_hash(b.table);
+  memcpy(buf, &h, sizeof h);
+  ICHK(hipMemcpy(static_cast<char*>(buf) + sizeof h, b.arena.base, b.arena.used, hipMemcpyDeviceToHost));
+  return ISING_OK;
+}
+
+int ising_checkpoint_load(ising_problem* p, const ising_schedule* s, const void* buf,
+                          uint64_t bytes, void* stream) {
+  if (!p || !s || !buf || bytes < sizeof(CheckpointHeader)) return ISING_ERR_INVALID;
+  CheckpointHeader h;
+  memcpy(&h, buf, sizeof h);
+  if (h.magic != kCheckpointMagic || h.version != 1 || bytes != sizeof h + h.arena_used ||
+      h.n_pad != p->g.n_pad) {
+    set_error("not a checkpoint of this problem");
+    return ISING_ERR_INVALID;
+  }
+  IRET(schedule_table(p, s));
+  const Table& table = p->sched.table;
+  if (table.S != h.S || table_hash(table) != h.table_hash) {
+    set_error("the checkpoint was taken under another schedule");
+    return ISING_ERR_INVALID;
+  }
+  if ((p->trace ? 1 : 0) != h.trace || (p->init_R > 0 ? 1 : 0) != h.init) {
+    set_error("tracing and given initial states must be as when the checkpoint was taken");
+    return ISING_ERR_STATE;
+  }
+  IRET(ensure_device(p));
+  DeviceGuard dg(p->dg.device);
+  PersistentConfig cfg;
+  cfg.path = h.path;
+  cfg.G = h.G;
+  cfg.block = h.block;
+  cfg.adj = h.adj;
+  IRET(check_config(p->g, table, h.R, cfg));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  IRET(prepare_run(p, table, h.R, cfg, st));
+  RunBuffers& b = p->run;
+  if (b.arena.used != h.arena_used) {
+    set_error("the checkpoint's buffer layout differs from this build's");
+    return ISING_ERR_INVALID;
+  }
+  // the uploads of prepare_run go first, then the saved bytes over them
+  ICHK(hipStreamSynchronize(st));
+  ICHK(hipMemcpy(b.arena.base, static_cast<const char*>(buf) + sizeof h, h.arena_used,
+                 hipMemcpyHostToDevice));
+  // the saved bytes include the same tables, but force a fresh upload
+  // should the next run bring another schedule
+  b.cfg = cfg;
+  b.seed = h.seed;
+  b.t_done = h.t_done;
+  b.valid = true;
+  p->temper.valid = false;
   return ISING_OK;
 }
 

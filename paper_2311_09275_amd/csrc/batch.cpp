@@ -135,7 +135,12 @@ int run_batch(ising_problem* const* ps, int count, const std::vector<Table>& tab
   IRET(run_persistent(L, specs, cfg, st, use_graph));
   for (int i = 0; i < count; ++i) {
     ICHK(hipEventRecord(ps[i]->run.ev1, st));
-    ps[i]->run.valid = true;
+    RunBuffers& b = ps[i]->run;
+    b.cfg = cfg;
+    b.seed = seeds[i];
+    b.t_done = tables[(size_t)i].S;
+    b.valid = true;
+    ps[i]->temper.valid = false;  // the last run is this anneal
   }
   return ISING_OK;
 }

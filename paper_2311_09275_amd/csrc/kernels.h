@@ -18,6 +18,9 @@ struct PlainPlan {
   const SwapDev* swap = nullptr;
   int swap_every = 0;
   const ClusterDev* cluster = nullptr;  // cluster moves before each round
+  // sweeps [t_begin, t_end) of the schedule (t_end < 0: to S); the initial
+  // state is drawn only when t_begin = 0, else the arrays hold sweep t_begin
+  int t_begin = 0, t_end = -1;
 };
 
 // One persistent launch (FIELD or MSC) over a unit list.

@@ -1734,11 +1734,14 @@ inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
 hipError_t launch_plain_anneal(const PlainDev& P, const PlainPlan& plan, hipStream_t s) {
   const int B = 256;
   const int n_grp = P.n_pad >> 2;
-  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(P.R, B)), dim3(B), 0, s, P.eacc, 0, (int64_t)P.R);
-  hipLaunchKernelGGL(k_plain_init, dim3(blocks_for((int64_t)n_grp * P.R, B)), dim3(B), 0, s, P);
-  hipLaunchKernelGGL(k_plain_fields, dim3(blocks_for((int64_t)P.n_pad * P.R, B)), dim3(B), 0, s, P);
-  hipLaunchKernelGGL(k_plain_init_best, dim3(blocks_for(P.R, B)), dim3(B), 0, s, P);
-  for (int t = 0; t < plan.S; ++t) {
+  const int t_end = plan.t_end < 0 ? plan.S : plan.t_end;
+  if (plan.t_begin == 0) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(P.R, B)), dim3(B), 0, s, P.eacc, 0, (int64_t)P.R);
+    hipLaunchKernelGGL(k_plain_init, dim3(blocks_for((int64_t)n_grp * P.R, B)), dim3(B), 0, s, P);
+    hipLaunchKernelGGL(k_plain_fields, dim3(blocks_for((int64_t)P.n_pad * P.R, B)), dim3(B), 0, s, P);
+    hipLaunchKernelGGL(k_plain_init_best, dim3(blocks_for(P.R, B)), dim3(B), 0, s, P);
+  }
+  for (int t = plan.t_begin; t < t_end; ++t) {
     for (int c = 0; c < plan.C; ++c) {
       const int g0 = plan.cls[2 * c], g1 = plan.cls[2 * c + 1];
       if (g1 > g0)
@@ -1754,8 +1757,10 @@ hipError_t launch_plain_anneal(const PlainDev& P, const PlainPlan& plan, hipStre
       if (e != hipSuccess) return e;
     }
   }
+  // a pending lazy snapshot of the last sweep (a later range's first sweep
+  // would take the same spins again)
   hipLaunchKernelGGL(k_plain_flush, dim3(blocks_for((int64_t)P.n_pad * P.R, B)), dim3(B), 0, s, P,
-                     plan.S - 1);
+                     t_end - 1);
   return hipGetLastError();
 }
 

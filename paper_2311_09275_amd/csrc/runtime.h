@@ -155,6 +155,13 @@ struct DevGraph {
 };
 int upload_graph(const HostGraph& g, DevGraph& d);
 
+struct PersistentConfig {
+  int path = ISING_PATH_FIELD;
+  int G = 1;
+  int block = 256;
+  int adj = 0;  // FIELD adjacency: 0 = decide, 1 = staged in LDS, 2 = read from HBM
+};
+
 struct RunBuffers {
   DeviceArena arena;
   int R = 0, S = 0, path = 0, G = 0, block = 0, nw = 0;
@@ -181,6 +188,11 @@ struct RunBuffers {
   JobDev* job_dev = nullptr;
   int layout_best = 0, layout_final = 0, layout_field = -1;
   Table table;                 // host source of the uploaded thresholds
+  // what the last run left: its launch configuration, seed and the sweeps
+  // done, so that a later range can continue it
+  PersistentConfig cfg;
+  uint64_t seed = 0;
+  int t_done = 0;
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool valid = false;
@@ -205,12 +217,6 @@ struct Launcher {
   ~Launcher();
 };
 
-struct PersistentConfig {
-  int path = ISING_PATH_FIELD;
-  int G = 1;
-  int block = 256;
-  int adj = 0;  // FIELD adjacency: 0 = decide, 1 = staged in LDS, 2 = read from HBM
-};
 
 // One anneal (or a chunk of sweeps of it) ready for the persistent kernels.
 struct JobSpec {
