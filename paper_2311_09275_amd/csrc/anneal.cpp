@@ -882,6 +882,7 @@ int ising_set_allocator(ising_alloc_fn alloc, ising_free_fn free_fn, void* ctx) 
 int ising_create(int32_t n, int64_t m, const int32_t* u, const int32_t* v, const int32_t* w,
                  const int32_t* colour, ising_problem** out) {
   if (!out) return ISING_ERR_INVALID;
+  TraceRange tr("ising_create");
   ising_problem* p = nullptr;
   try {
     p = new ising_problem();
@@ -1064,6 +1065,7 @@ int ising_anneal_range(ising_problem* p, const ising_schedule* s, int32_t n_repl
                        uint64_t seed, const ising_tuning* tuning, int32_t t_begin, int32_t t_end,
                        void* stream) {
   if (!p || !s || n_replicas < 1) return ISING_ERR_INVALID;
+  TraceRange tr("ising_anneal_range");
   IRET(schedule_table(p, s));
   const Table& table = p->sched.table;
   if (t_begin < 0 || t_end <= t_begin || t_end > table.S) {

@@ -166,6 +166,7 @@ int ising_anneal_batch(ising_problem* const* ps, int32_t count, const ising_sche
                        int32_t n_replicas, const uint64_t* seeds, const ising_tuning* tuning,
                        void* stream) {
   if (!ps || count < 1 || !s || n_replicas < 1 || !seeds) return ISING_ERR_INVALID;
+  TraceRange tr("ising_anneal_batch");
   std::vector<Table> tables;
   IRET(batch_tables(ps, count, s, tables));
   IRET(ensure_all(ps, count));
@@ -237,6 +238,7 @@ int ising_last_batch_ms(double* ms) {
 int ising_autotune(ising_problem* const* ps, int32_t count, const ising_schedule* s,
                    int32_t n_replicas, int32_t prefix_sweeps, ising_tuning* best, void* stream) {
   if (!ps || count < 1 || !s || n_replicas < 1 || !best) return ISING_ERR_INVALID;
+  TraceRange tr("ising_autotune");
   std::vector<double> beta;
   IRET(eval_schedule(s, beta));
   const int S = (int)beta.size();

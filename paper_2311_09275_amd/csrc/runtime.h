@@ -1,6 +1,7 @@
 // runtime.h -- host runtime of libising (internal).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 
 #include <memory>
@@ -32,6 +33,15 @@ const char* last_error();
     int rc_ = (expr);               \
     if (rc_ != ISING_OK) return rc_; \
   } while (0)
+
+// A named roctx range for the scope: the library's calls show up in
+// rocprofv3 --marker-trace timelines.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // Switches to a device for the scope and restores the caller's device.
 struct DeviceGuard {

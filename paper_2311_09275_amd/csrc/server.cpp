@@ -171,6 +171,7 @@ int step_device(ising_server* s, std::vector<std::shared_ptr<Request>>& batch) {
     ends.push_back(end);
     specs.push_back(JobSpec{&r->p->g, &r->p->dg, &r->buf, r->R, r->seed, r->t_done, end});
   }
+  TraceRange tr("ising_server_step");
   IRET(run_persistent(s->launcher, specs, s->cfg, s->stream, true));
   ICHK(hipStreamSynchronize(s->stream));
   for (size_t i = 0; i < batch.size(); ++i) {

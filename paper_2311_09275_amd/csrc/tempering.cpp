@@ -40,6 +40,7 @@ extern "C" {
 int ising_temper(ising_problem* p, const ising_tempering* x, uint64_t seed,
                  const ising_tuning* tuning, void* stream) {
   if (!p || !x || !x->betas) return ISING_ERR_INVALID;
+  TraceRange tr("ising_temper");
   const int32_t K = x->n_temps, n_sets = x->n_sets, S = x->n_sweeps, P = x->swap_every;
   if (K < 1 || n_sets < 1 || S < 1 || P < 1 || (int64_t)K * n_sets > 0x7FFFFFFF) {
     set_error("tempering needs n_temps, n_sets, n_sweeps, swap_every >= 1");
