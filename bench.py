@@ -74,6 +74,13 @@ def measured_valu_issue():
     return _profile_figure("k_field_torus100x80_r256_valu.md", r"VALU issue fraction: [^=]*= ([0-9]+\.[0-9]+)", float)
 
 
+def measured_lds():
+    """LDS active and bank-conflict fractions of the timed kernel."""
+    act = _profile_figure("k_field_torus100x80_r256_lds.md", r"LDS active fraction: ([0-9.]+)", float)
+    conf = _profile_figure("k_field_torus100x80_r256_lds.md", r"LDS bank-conflict fraction: ([0-9.]+)", float)
+    return None if act is None else {"active_frac": act, "bank_conflict_frac": conf}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -409,6 +416,7 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_PER_S / 1e12,
                 "unit": "T int32 ops/s", "frac": achieved / VALU_PEAK_PER_S,
                 "traffic": measured_traffic(), "valu_issue_frac": measured_valu_issue(),
+                "lds": measured_lds(),
                 "ops_per_attempt": ops_per_attempt,
                 "measured_lane_ops_per_s": {k: v for k, v in rates.items()}}
 
