@@ -150,7 +150,9 @@ int ising_eval_cut(const ising_problem* p, const int8_t* spins, int64_t* cut);
  * (so h_v = -sum_u w_vu s_u + 2 b_v and k = s_v h_v as before), and every
  * "cut" the library reports (best cuts, per-replica cuts, argmax) is the
  * objective (W - E)/2 = cut(s) + sum_v b_v s_v.  kmax becomes
- * max_v (sum_u |w_vu| + 2 |b_v|).  Applies to later runs.  Refused with
+ * max_v (sum_u |w_vu| + 2 |b_v|).  Applies to later runs; it waits for
+ * the problem's own last run, but must not be called while a server holds
+ * a request of p (the server reads the same device copy).  Refused with
  * fields: the multispin path and the degree-4 adjacency forms (their state
  * words hold no field; other FIELD forms are chosen), and tempering's
  * cluster moves (ISING_ERR_UNSUPPORTED).  ISING_ERR_INVALID when some
