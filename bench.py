@@ -103,7 +103,7 @@ def parse():
     ap.add_argument("--no-msc", action="store_true", help="skip the multispin leg")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests of the Poisson serving leg (0 = skip)")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparisons")
     ap.add_argument("--no-ttt", action="store_true", help="skip the reference run for targets")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 256 MiB device copy first (byte-counter calibration)")
@@ -273,20 +273,22 @@ def main():
         path3 = B.ising_last_run_info(p3.handle)[2]
         kern3 = p3.last_anneal_ms()
         per3 = res3.per_replica.copy()
-        t = time.perf_counter()
-        p3.anneal(sched3, R3, SEED3, B.Tuning(B.PATH_PLAIN, 1, 256, 0), stream=stream)
-        res3p = p3.cut()
-        plain3_s = time.perf_counter() - t
-        assert np.array_equal(res3p.per_replica, per3), "plain and automatic forms disagree"
         ms3 = float(np.mean(walls3)) * 1e3
         att3 = inst3.n * R3 * S3
         random_leg = {"workload": "sparse random graph N=10000 M=9999 w=1, 1024 replicas, "
                                   "4000 sweeps linear 0.05->3.0",
                       "attempts_per_s": att3 / (ms3 / 1e3), "ms_per_anneal": ms3,
-                      "plain_ms": plain3_s * 1e3, "speedup_vs_plain": plain3_s * 1e3 / ms3,
                       "kernel_ms": kern3, "best_cut": int(res3.best_cut),
                       "path": {1: "plain", 2: "field", 3: "msc"}.get(path3, str(path3)),
                       "tuning": "automatic"}
+        if not args.no_plain:
+            t = time.perf_counter()
+            p3.anneal(sched3, R3, SEED3, B.Tuning(B.PATH_PLAIN, 1, 256, 0), stream=stream)
+            res3p = p3.cut()
+            plain3_s = time.perf_counter() - t
+            assert np.array_equal(res3p.per_replica, per3), "plain and automatic forms disagree"
+            random_leg["plain_ms"] = plain3_s * 1e3
+            random_leg["speedup_vs_plain"] = plain3_s * 1e3 / ms3
         if not args.no_ttt:
             ref3 = B.Problem.from_instance(inst3)
             ref3.anneal(B.Schedule.make(B.LINEAR, 5 * S3, 0.05, 3.0), R3, 7, auto, stream=stream)
@@ -298,8 +300,10 @@ def main():
                 target = ttt.target_cut(c_ref3, q)
                 tf = ttt.replica_ttt(per3, target, ms3 / 1e3, S3)
                 random_leg["ttt"][str(q)] = {
-                    "target": target, "ps": tf["ps"], "ttt_persistent_s": tf["ttt_s"],
-                    "ttt_plain_s": ttt.replica_ttt(per3, target, plain3_s, S3)["ttt_s"]}
+                    "target": target, "ps": tf["ps"], "ttt_persistent_s": tf["ttt_s"]}
+                if not args.no_plain:
+                    random_leg["ttt"][str(q)]["ttt_plain_s"] = \
+                        ttt.replica_ttt(per3, target, plain3_s, S3)["ttt_s"]
         p3.close()
 
     # ------------------------------------------------------------ tempering leg
