@@ -226,8 +226,11 @@ typedef struct {
  * call starts afresh.  `tuning` NULL = ISING_PATH_AUTO.
  * Errors: ISING_ERR_INVALID (bad schedule, R < 1, tuning out of range, a
  * threshold table over 2^26 entries); ISING_ERR_UNSUPPORTED (MSC on
- * non-unit weights, FIELD with more than 64 colour classes, or a problem
- * too large for the requested LDS path);
+ * non-unit weights, FIELD with more than 64 colour classes, the LDS paths
+ * (FIELD, MSC) on a vertex of degree above 255 or a threshold row longer
+ * than 1024 keys (a schedule whose smallest beta accepts some k > 1024 with
+ * nonzero probability), or a problem too large for the requested LDS path;
+ * ISING_PATH_AUTO then runs PLAIN);
  * ISING_ERR_NOMEM; ISING_ERR_DEVICE.
  */
 int ising_anneal(ising_problem* p, const ising_schedule* s, int32_t n_replicas,

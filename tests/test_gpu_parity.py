@@ -136,6 +136,40 @@ def test_weighted_graph(path):
             tuning=PATHS[path])
 
 
+def weight_limit_instance():
+    """Weights at the largest allowed magnitude: |w| uniform in [1, 2^15] on a
+    random graph, every seventh edge at exactly +-2^15 (k reaches 250,226)."""
+    inst = I.random_weighted(120, 300, 31, 32768)
+    w = inst.w.copy()
+    w[::7] = np.where(w[::7] > 0, 32768, -32768)
+    return I.Instance("wlimit", inst.n, inst.u, inst.v, w)
+
+
+@pytest.mark.parametrize("path", ["plain", "field_g1_b256_hbmadj", "field_g4_b256_hbmadj",
+                                  "field_g1_b512_auto"])
+def test_weights_at_the_limit_long_rows(path):
+    """From beta 0.011 the threshold rows hold about 1008 keys, near the LDS
+    paths' 1024-key limit (2018 words: the FIELD path stages one sweep's row
+    at a time)."""
+    compare(weight_limit_instance(), 40, 12, 3, kind=O.LINEAR, b0=0.011, b1=0.05,
+            tuning=PATHS[path])
+
+
+@pytest.mark.parametrize("b0", [0.0008, 1e-5])
+def test_weights_at_the_limit_rows_beyond_lds_paths(b0):
+    """At beta 0.0008 a row covers k up to ~13,900, at 1e-5 every k up to
+    250,226: the FIELD path refuses the schedule, and the automatic
+    configuration runs the plain path with oracle-equal results."""
+    inst = weight_limit_instance()
+    p = B.Problem.from_instance(inst)
+    with pytest.raises(B.IsingError) as e:
+        p.anneal(B.Schedule.make(B.LINEAR, 40, b0, 10 * b0), 12, 3, PATHS["field_g1_b256_hbmadj"])
+    assert e.value.status == B.ERR_UNSUPPORTED
+    p.close()
+    compare(inst, 40, 12, 3, kind=O.LINEAR, b0=b0, b1=10 * b0,
+            tuning=B.Tuning(B.PATH_AUTO, 0, 0, 0))
+
+
 def test_field_path_colour_limit():
     """The FIELD path keeps class bounds in two registers (at most 64
     classes): a supplied 70-colouring is refused there, and the automatic
