@@ -170,6 +170,44 @@ def test_weights_at_the_limit_rows_beyond_lds_paths(b0):
             tuning=B.Tuning(B.PATH_AUTO, 0, 0, 0))
 
 
+def hub_graph(n_leaves, seed):
+    """A hub joined to n_leaves leaves, the leaves joined in a ring, +-1
+    weights: one vertex of degree n_leaves, the rest of degree 3."""
+    leaves = np.arange(1, n_leaves + 1, dtype=np.int32)
+    u = np.concatenate([np.zeros(n_leaves, np.int32), leaves])
+    v = np.concatenate([leaves, np.roll(leaves, -1)]).astype(np.int32)
+    w = (np.random.Generator(np.random.PCG64(seed)).integers(0, 2, 2 * n_leaves) * 2 - 1)
+    return I.Instance(f"hub{n_leaves}", n_leaves + 1, u, v, w.astype(np.int32))
+
+
+_DEG_PATHS = ["plain", "field_g1_b256_hbmadj", "field_g1_b1024_ldsadj", "field_g2_b512_ldsadj",
+              "field_g1_b1024_csradj"]
+
+
+@pytest.mark.parametrize("hub,path", [(31, p) for p in _DEG_PATHS + ["msc_g1_b256"]] +
+                         [(255, p) for p in _DEG_PATHS])
+def test_degree_at_the_limits(hub, path):
+    """Degree 31 (the multispin path's limit) and 255 (the LDS paths' 8-bit
+    degree field)."""
+    compare(hub_graph(hub, 5), 60, 40, 7, kind=O.GEOMETRIC, b0=0.1, b1=3.0, tuning=PATHS[path])
+
+
+def test_degree_beyond_the_limits():
+    """Degree 32 is refused by the multispin path and 256 by the FIELD
+    path; the automatic configuration runs them with oracle-equal results."""
+    sched = B.Schedule.make(B.LINEAR, 10, 0.1, 1.0)
+    for hub, refused in ((32, ["msc_g1_b256"]), (256, ["field_g1_b256_hbmadj", "field_g1_b1024_ldsadj"])):
+        inst = hub_graph(hub, 6)
+        p = B.Problem.from_instance(inst)
+        for path in refused:
+            with pytest.raises(B.IsingError) as e:
+                p.anneal(sched, 8, 1, PATHS[path])
+            assert e.value.status == B.ERR_UNSUPPORTED, (hub, path)
+        p.close()
+        compare(inst, 60, 40, 7, kind=O.GEOMETRIC, b0=0.1, b1=3.0,
+                tuning=B.Tuning(B.PATH_AUTO, 0, 0, 0))
+
+
 def test_field_path_colour_limit():
     """The FIELD path keeps class bounds in two registers (at most 64
     classes): a supplied 70-colouring is refused there, and the automatic
