@@ -202,3 +202,83 @@ def test_serving_with_local_fields():
         np.testing.assert_array_equal(res[4], o.best_state[o.argmax()])
     for p in probs:
         p.close()
+
+
+@pytest.mark.parametrize("form", ["autotuned", "msc"])
+def test_c4_full_size_batch_sampled(form):
+    """The 64-torus batch at full size (sides uniform in 32..141, 128
+    replicas, 4000 sweeps geometric 0.1 -> 4.0) in the two launch
+    configurations the benchmark times: the autotuned one and the multispin
+    one (one 32-replica word per unit).  The oracle recomputes two replicas
+    each of the smallest, a middle and the largest problem."""
+    insts = I.workload_c4()
+    S, R = 4000, 128
+    sched = B.Schedule.make(B.GEOMETRIC, S, 0.1, 4.0)
+    probs = [B.Problem.from_instance(x) for x in insts]
+    hs = [p.handle for p in probs]
+    seeds = np.array([2000 + i for i in range(len(insts))], np.uint64)
+    tun = (B.ising_autotune(hs, sched, R, prefix_sweeps=200) if form == "autotuned"
+           else B.Tuning(B.PATH_MSC, 1, 256, 0))
+    B.ising_anneal_batch(hs, sched, R, seeds, tun)
+    order = np.argsort([x.n for x in insts], kind="stable")
+    for i in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        p = probs[i]
+        _, _, per = B.ising_cut(p.handle, R)
+        bs, acc, en = p.replica_results()
+        for r in (i % R, R - 1 - i % 7):
+            o = O.anneal(insts[i], S, R, int(seeds[i]), kind=O.GEOMETRIC, beta0=0.1, beta1=4.0,
+                         r_begin=r, r_end=r + 1)
+            assert (per[r], bs[r], acc[r], en[r]) == (o.best_cut[0], o.best_sweep[0], o.accepts[0],
+                                                      o.final_energy[0]), (insts[i].name, r)
+            gb, gf = p.replica_state(r)
+            np.testing.assert_array_equal(gb, o.best_state[0], err_msg=f"{insts[i].name} r={r}")
+            np.testing.assert_array_equal(gf, o.final_state[0], err_msg=f"{insts[i].name} r={r}")
+    for p in probs:
+        p.close()
+
+
+def test_c5_full_size_serving_sampled():
+    """Serving at full size, in the benchmark's server configuration (256 MiB
+    budget, 16 slots, chunks of 50 sweeps): two requests of each of the five
+    shapes (tori of 8,000 to 20,000 vertices, the random 10,000-vertex
+    graph), 256 replicas, up to 1000 sweeps linear 0.1 -> 3.0, submitted at
+    once.  Odd requests stop at a target (checked every 50 sweeps).  Each
+    result equals a one-shot anneal of the sweeps it ran, and the oracle
+    recomputes the served best replica and one other replica of each."""
+    from paper_2311_09275_amd import serve_load
+    insts = [mk() for _, mk in serve_load.SHAPES]
+    probs = [B.Problem.from_instance(x) for x in insts]
+    S, R = 1000, 256
+    sched = B.Schedule.make(B.LINEAR, S, 0.1, 3.0)
+    reqs = []
+    for i in range(2 * len(insts)):
+        k = i % len(insts)
+        target = 10 ** 9
+        if i % 2 == 1:
+            probs[k].anneal(B.Schedule.make(B.LINEAR, S, 0.1, 3.0), R, 900 + i,
+                            B.Tuning(B.PATH_FIELD, 1, 512, 2))
+            target = int(0.98 * B.ising_cut(probs[k].handle, R)[0])
+        reqs.append((probs[k], sched, R, 900 + i, target, 50))
+    served, stats = _serve(reqs, chunk=50, budget=256 << 20, slots=16)
+    betas_all = O.schedule(O.LINEAR, S, 0.1, 3.0)
+    for i, (req, res) in enumerate(zip(reqs, served)):
+        p, _, _, seed, target, _ = req
+        k = i % len(insts)
+        best, arg, done, reached, state = res
+        if target < 10 ** 9:
+            assert reached == 1 and best >= target and done % 50 == 0 and done <= S
+        else:
+            assert done == S
+        # one-shot anneal of the sweeps the request ran
+        p.anneal(B.Schedule.make(betas=betas_all[:done]), R, seed, B.Tuning(B.PATH_FIELD, 1, 512, 2))
+        b1, a1, per = B.ising_cut(p.handle, R)
+        assert (b1, a1) == (best, arg)
+        np.testing.assert_array_equal(p.best_state(), state)
+        for r in (arg, (arg + 101) % R):
+            o = O.anneal(insts[k], done, R, seed, betas=betas_all[:done], kind=O.EXPLICIT,
+                         r_begin=r, r_end=r + 1)
+            assert per[r] == o.best_cut[0], (insts[k].name, i, r)
+            if r == arg:
+                np.testing.assert_array_equal(state, o.best_state[0])
+    for p in probs:
+        p.close()
