@@ -239,6 +239,7 @@ def main():
         cuts_m = [B.ising_cut(h)[0] for h in handles]
         msc_b_s = time.perf_counter() - t
         assert cuts_m == cuts_p, "batched multispin and plain forms disagree"
+        per_b = [B.ising_cut(h, Rb)[2].copy() for h in handles]  # identical on every form
         batch = {"workload": "64 LxL +-1 tori, L~U{32..141}, 128 replicas, 4000 sweeps geometric 0.1->4.0",
                  "attempts": bat_att, "batched_s": bat_s, "plain_s": plain_b_s,
                  "batched_attempts_per_s": bat_att / bat_s, "plain_attempts_per_s": bat_att / plain_b_s,
@@ -246,6 +247,24 @@ def main():
                  "tuning": {"path": int(tun.path), "replicas_per_block": int(tun.replicas_per_block),
                             "block_threads": int(tun.block_threads),
                             "lds_adjacency": int(tun.lds_adjacency)}}
+        if not args.no_ttt:
+            # reference best of every problem: one batched anneal of 5x the
+            # sweeps with other seeds; a replica of the timed batch is a trial
+            # of its problem, and the batch's wall time runs R trials of every
+            # problem (t_trial = wall / R), batched and plain alike
+            B.ising_anneal_batch(handles, B.Schedule.make(B.GEOMETRIC, 5 * S, B0, B1), Rb,
+                                 seeds + np.uint64(50_000), tun, stream=stream)
+            refs = [B.ising_cut(h)[0] for h in handles]
+            batch["ttt"] = {}
+            for q in (0.995, 0.998):
+                rows = [ttt.replica_ttt(per_b[i], ttt.target_cut(refs[i], q), bat_s, S)
+                        for i in range(len(handles))]
+                hit = [r_ for r_ in rows if r_["ps"] > 0]
+                med = float(np.median([r_["ttt_s"] for r_ in hit])) if hit else float("inf")
+                batch["ttt"][str(q)] = {"problems_with_ps_above_0": len(hit),
+                                        "median_ttt_batched_s": med,
+                                        "median_ttt_plain_s": med * plain_b_s / bat_s,
+                                        "median_ps": float(np.median([r_["ps"] for r_ in rows]))}
         for p in probs:
             p.close()
 
