@@ -244,3 +244,23 @@ def test_allocator_needs_both_functions():
     a = B.ALLOC_FN(lambda n, dev, ctx: 0)
     assert B._L.ising_set_allocator(a, B.FREE_FN(), None) == B.ERR_INVALID
     assert B._L.ising_set_allocator(B.ALLOC_FN(), B.FREE_FN(), None) == B.OK
+
+
+def test_c_program_uses_the_header(tmp_path):
+    """A plain C99 program compiled against include/ising.h (-Wall -Wextra
+    -Werror -pedantic) and linked to the library runs the host-only entry
+    points: problem compile and info, colouring, cut evaluation on all 32
+    states of a small weighted graph, rejected inputs and thresholds."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    root = ROOT
+    pkg = os.path.join(root, "paper_2311_09275_amd")
+    exe = str(tmp_path / "host_abi")
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                    "-I", os.path.join(root, "include"), os.path.join(root, "tests", "c", "host_abi.c"),
+                    "-L", pkg, "-lising", f"-Wl,-rpath,{pkg}", "-o", exe], check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "ok"
