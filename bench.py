@@ -10,8 +10,8 @@ plain one-launch-per-colour-pass form is timed beside it on the same seeds
 and so is the batched form on 64 uneven tori.  The CPU oracle is timed on a
 bounded sample of the same workload on the host cores.
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
-GPU.
+Prints one JSON line.  `--gpus N` with N > 1 exits: the benchmark measures
+one GPU.
 """
 from __future__ import annotations
 
@@ -113,7 +113,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
 

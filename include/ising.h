@@ -261,7 +261,7 @@ int ising_anneal_range(ising_problem* p, const ising_schedule* s, int32_t n_repl
  * the same schedule (ISING_ERR_INVALID otherwise) and the same tracing and
  * initial-state settings (ISING_ERR_STATE otherwise); its results can then
  * be read, and ising_anneal_range continues it from the sweep it had reached.
- * The buffer format belongs to this build of the library.
+ * The buffer format is private to the library version that wrote it.
  */
 int ising_checkpoint_size(const ising_problem* p, uint64_t* bytes);
 int ising_checkpoint_save(ising_problem* p, void* buf);

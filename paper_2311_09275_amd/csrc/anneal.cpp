@@ -1219,7 +1219,7 @@ int ising_checkpoint_load(ising_problem* p, const ising_schedule* s, const void*
   IRET(prepare_run(p, table, h.R, cfg, st));
   RunBuffers& b = p->run;
   if (b.arena.used != h.arena_used) {
-    set_error("the checkpoint's buffer layout differs from this build's");
+    set_error("the checkpoint was written by a library with another buffer layout");
     return ISING_ERR_INVALID;
   }
   // the uploads of prepare_run go first, then the saved bytes over them
