@@ -324,6 +324,32 @@ static uint32_t draw(const or_graph* G, uint64_t seed, int32_t v, uint32_t t,
   return out[G->rank[v]];
 }
 
+int oracle_stream_map(const or_graph_in* gin, int32_t* run, int32_t* rank) {
+  if (!gin || !run || !rank) return -1;
+  or_graph G;
+  if (graph_build(gin, &G) != 0) {
+    graph_free(&G);
+    return -1;
+  }
+  memcpy(run, G.run, sizeof(int32_t) * (size_t)G.n);
+  memcpy(rank, G.rank, sizeof(int32_t) * (size_t)G.n);
+  graph_free(&G);
+  return 0;
+}
+
+int oracle_draws(const or_graph_in* gin, uint64_t seed, uint32_t t, uint32_t r,
+                 uint32_t tag, uint32_t* out) {
+  if (!gin || !out) return -1;
+  or_graph G;
+  if (graph_build(gin, &G) != 0) {
+    graph_free(&G);
+    return -1;
+  }
+  for (int32_t v = 0; v < G.n; ++v) out[v] = draw(&G, seed, v, t, r, tag);
+  graph_free(&G);
+  return 0;
+}
+
 int64_t oracle_cut(int32_t n, int64_t m, const int32_t* u, const int32_t* v,
                    const int32_t* w, const int8_t* s) {
   (void)n;
@@ -394,9 +420,11 @@ static void sweep_once(const or_graph* G, uint64_t seed, int32_t t, int32_t r,
       } else {
         uint32_t u = draw(G, seed, i, (uint32_t)t, (uint32_t)r, 0);
         accept = (uint64_t)u < tq[k];
-        /* bookkeeping only: one Philox block serves a whole group, so
-         * count each (run, sweep) once; a draw whose threshold is
-         * 0 or 2^32 decides nothing and is not counted */
+        /* bookkeeping only: the stream gives the four vertices of a run
+         * the four words of one Philox block, so the arithmetic the
+         * method needs is one block per (run, sweep) that draws at all;
+         * a draw whose threshold is 0 or 2^32 decides nothing and is not
+         * counted */
         if (tq[k] != 0 && tq[k] != ((uint64_t)1 << 32) && drawn_at[G->run[i]] != t) {
           drawn_at[G->run[i]] = t;
           ++*draws;

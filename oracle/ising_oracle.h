@@ -85,6 +85,19 @@ uint64_t oracle_threshold(double beta, int64_t k);
  * or -1 on invalid input. */
 int32_t oracle_colouring(int32_t n, int64_t m, const int32_t* u,
                          const int32_t* v, int32_t* colour);
+/* The random-number stream of a graph (its colouring as given, or greedy
+ * first-fit): inside each colour class, taken in ascending id, consecutive
+ * runs of four vertices (the class's last run may be shorter) are numbered
+ * 0, 1, ... in class order, then in id order within a class.  run[v] is the
+ * ordinal of v's run and rank[v] its place in the run, so v's draw for
+ * sweep t, replica r and purpose tag (0 sweep, 1 initial state) is word
+ * rank[v] of Philox4x32-10 with counter (t, run[v], r, tag) and key
+ * (seed low, seed high).  A different colouring gives a different stream.
+ * Returns 0, or -1 on invalid input. */
+int oracle_stream_map(const or_graph_in* g, int32_t* run, int32_t* rank);
+/* out[v] = that draw for every vertex v (t, r, tag fixed). */
+int oracle_draws(const or_graph_in* g, uint64_t seed, uint32_t t, uint32_t r,
+                 uint32_t tag, uint32_t* out);
 /* MaxCut value of a +-1 assignment. */
 int64_t oracle_cut(int32_t n, int64_t m, const int32_t* u, const int32_t* v,
                    const int32_t* w, const int8_t* spins);

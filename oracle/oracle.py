@@ -96,6 +96,9 @@ def lib():
         L.oracle_temper.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_cluster.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
         L.oracle_cluster.restype = C.c_int64
+        L.oracle_stream_map.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oracle_draws.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
+                                   C.c_uint32, C.c_void_p]
         L.oracle_swap_accept.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                          C.c_int64, C.c_int64, C.c_double, C.c_double]
         _lib = L
@@ -153,6 +156,27 @@ def _graph(inst, colour=None):
     f = None if f is None else np.ascontiguousarray(f, np.int32)
     g = _GraphIn(inst.n, inst.m, _p(u), _p(v), _p(w), _p(col), _p(f))
     return g, (u, v, w, col, f)
+
+
+def stream_map(inst, colour=None) -> tuple[np.ndarray, np.ndarray]:
+    """(run, rank) of every vertex: its draws are word rank[v] of the
+    Philox block with counter (t, run[v], r, tag)."""
+    g, keep = _graph(inst, colour)
+    run = np.zeros(inst.n, np.int32)
+    rank = np.zeros(inst.n, np.int32)
+    if lib().oracle_stream_map(C.byref(g), _p(run), _p(rank)) != 0:
+        raise ValueError("invalid graph")
+    return run, rank
+
+
+def draws(inst, seed, t, r, tag, colour=None) -> np.ndarray:
+    """The u32 draw of every vertex for sweep t, replica r, purpose tag."""
+    g, keep = _graph(inst, colour)
+    out = np.zeros(inst.n, np.uint32)
+    if lib().oracle_draws(C.byref(g), int(seed) & 0xFFFFFFFFFFFFFFFF, int(t), int(r), int(tag),
+                          _p(out)) != 0:
+        raise ValueError("invalid graph")
+    return out
 
 
 def validate(inst, colour=None) -> bool:
