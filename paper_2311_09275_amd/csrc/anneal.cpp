@@ -104,6 +104,7 @@ Launcher::~Launcher() {
   if (staged) (void)hipEventDestroy(staged);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
+  if (done) (void)hipEventDestroy(done);
 }
 
 int device_cu_count() {
@@ -690,7 +691,14 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   }
   const int n_dev_jobs = (int)jobs.size();
 
-  // device and pinned staging buffers
+  // The jobs, units and list cursors on the device are shared by every
+  // launch of this launcher.  A launch on another stream must not rewrite
+  // them while an earlier one still claims units, so this stream first
+  // waits for the previous launch (on the same stream the wait is already
+  // implied by stream order).
+  if (L.done_recorded) ICHK(hipStreamWaitEvent(stream, L.done, 0));
+  // device and pinned staging buffers (a reallocation frees the old
+  // device buffers after a device synchronisation)
   if (L.jobs_cap < (size_t)n_dev_jobs || L.units_cap < (size_t)n_units || !L.arena.base) {
     L.jobs_cap = std::max<size_t>(n_dev_jobs, 16);
     L.units_cap = std::max<size_t>(n_units, 1024);
@@ -808,6 +816,9 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
     ICHK(enqueue(stream));
   }
   ICHK(hipEventRecord(L.ev1, stream));
+  if (!L.done) ICHK(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
+  ICHK(hipEventRecord(L.done, stream));
+  L.done_recorded = true;
   return ISING_OK;
 }
 

@@ -224,6 +224,10 @@ struct Launcher {
   hipGraph_t graph = nullptr;
   std::string graph_key;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // recorded after every launch: the next launch, on whatever stream, waits
+  // for it before it rewrites the shared device launch structures
+  hipEvent_t done = nullptr;
+  bool done_recorded = false;
   ~Launcher();
 };
 

@@ -93,6 +93,20 @@ struct Request {
   RunBuffers buf;
   char* mem = nullptr;
   bool prepared = false;
+  // Progress as the scheduler thread computes it.  The step functions run
+  // without the server lock and write only this; the scheduler copies it
+  // into the published fields below under the lock after each step.
+  struct Progress {
+    int t_done = 0;
+    bool done = false;
+    bool reached = false;
+    int64_t best_cut = 0;
+    int best_replica = -1;
+    std::vector<int8_t> best_state;
+  } work;
+  // Published fields: written and read only under the server lock.  A
+  // client that sees done == true also sees the final values of the
+  // others (they are set in the same critical section).
   int t_done = 0;
   bool done = false;
   int status = ISING_OK;
@@ -137,23 +151,35 @@ struct ising_server {
 namespace {
 
 int next_end(const Request& r, int chunk) {
-  int end = std::min(r.S, r.t_done + chunk);
-  if (r.check_every > 0) end = std::min(end, (r.t_done / r.check_every + 1) * r.check_every);
+  const int t_done = r.work.t_done;
+  int end = std::min(r.S, t_done + chunk);
+  if (r.check_every > 0) end = std::min(end, (t_done / r.check_every + 1) * r.check_every);
   return end;
 }
 
-// After a chunk: decide whether the request is finished.
+// After a chunk: decide whether the request is finished (scheduler-private
+// progress only).
 void settle(Request& r, int end) {
-  r.t_done = end;
-  const bool at_check = r.check_every > 0 && r.t_done % r.check_every == 0;
-  if (at_check && r.best_cut >= r.target) {
-    r.reached = true;
-    r.done = true;
+  Request::Progress& w = r.work;
+  w.t_done = end;
+  const bool at_check = r.check_every > 0 && w.t_done % r.check_every == 0;
+  if (at_check && w.best_cut >= r.target) {
+    w.reached = true;
+    w.done = true;
   }
-  if (r.t_done >= r.S) {
-    r.reached = r.reached || r.best_cut >= r.target;
-    r.done = true;
+  if (w.t_done >= r.S) {
+    w.reached = w.reached || w.best_cut >= r.target;
+    w.done = true;
   }
+}
+
+// Under the server lock: make the step's progress visible to clients.
+void publish(Request& r) {
+  const Request::Progress& w = r.work;
+  r.t_done = w.t_done;
+  r.reached = w.reached;
+  r.best_cut = w.best_cut;
+  r.best_replica = w.best_replica;
 }
 
 // One chunk of sweeps for every resident request on the device.
@@ -169,7 +195,7 @@ int step_device(ising_server* s, std::vector<std::shared_ptr<Request>>& batch) {
     }
     const int end = next_end(*r, s->chunk);
     ends.push_back(end);
-    specs.push_back(JobSpec{&r->p->g, &r->p->dg, &r->buf, r->R, r->seed, r->t_done, end});
+    specs.push_back(JobSpec{&r->p->g, &r->p->dg, &r->buf, r->R, r->seed, r->work.t_done, end});
   }
   TraceRange tr("ising_server_step");
   IRET(run_persistent(s->launcher, specs, s->cfg, s->stream, true));
@@ -178,18 +204,18 @@ int step_device(ising_server* s, std::vector<std::shared_ptr<Request>>& batch) {
     Request& r = *batch[i];
     unsigned long long key = 0;
     ICHK(hipMemcpy(&key, r.buf.argmax, sizeof key, hipMemcpyDeviceToHost));
-    r.best_cut = (int64_t)(int32_t)((uint32_t)(key >> 32) ^ 0x80000000u);
-    r.best_replica = (int32_t)(0xFFFFFFFFu - (uint32_t)key);
+    r.work.best_cut = (int64_t)(int32_t)((uint32_t)(key >> 32) ^ 0x80000000u);
+    r.work.best_replica = (int32_t)(0xFFFFFFFFu - (uint32_t)key);
     settle(r, ends[i]);
-    if (r.done) {
+    if (r.work.done) {
       const HostGraph& g = r.p->g;
-      ICHK(launch_gather(r.buf.best, r.buf.layout_best, r.R, g.n_pad, r.best_replica, r.p->dg.pos,
-                         g.n, r.buf.gather, s->stream));
+      ICHK(launch_gather(r.buf.best, r.buf.layout_best, r.R, g.n_pad, r.work.best_replica,
+                         r.p->dg.pos, g.n, r.buf.gather, s->stream));
       std::vector<int32_t> tmp((size_t)g.n);
       ICHK(hipMemcpyAsync(tmp.data(), r.buf.gather, sizeof(int32_t) * g.n, hipMemcpyDeviceToHost,
                           s->stream));
       ICHK(hipStreamSynchronize(s->stream));
-      r.best_state.assign(tmp.begin(), tmp.end());
+      r.work.best_state.assign(tmp.begin(), tmp.end());
     }
   }
   return ISING_OK;
@@ -200,10 +226,10 @@ int step_device(ising_server* s, std::vector<std::shared_ptr<Request>>& batch) {
 int step_null(ising_server* s, std::vector<std::shared_ptr<Request>>& batch) {
   for (auto& r : batch) {
     const int end = next_end(*r, s->chunk);
-    r->best_cut = end;
-    r->best_replica = 0;
+    r->work.best_cut = end;
+    r->work.best_replica = 0;
     settle(*r, end);
-    if (r->done) r->best_state.assign((size_t)r->p->g.n, 1);
+    if (r->work.done) r->work.best_state.assign((size_t)r->p->g.n, 1);
   }
   return ISING_OK;
 }
@@ -234,12 +260,15 @@ void scheduler(ising_server* s) {
     ++s->steps;
     std::vector<std::shared_ptr<Request>> keep;
     for (auto& r : s->resident) {
+      publish(*r);
       if (rc != ISING_OK) {
         r->status = rc;
-        r->done = true;
+        r->work.done = true;
       }
-      if (r->done) {
+      if (r->work.done) {
+        r->best_state.swap(r->work.best_state);
         r->t_finish = s->now();
+        r->done = true;
         r->buf.arena.release();
         s->pool.release(r->mem);
         r->mem = nullptr;

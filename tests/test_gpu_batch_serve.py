@@ -282,3 +282,35 @@ def test_c5_full_size_serving_sampled():
                 np.testing.assert_array_equal(state, o.best_state[0])
     for p in probs:
         p.close()
+
+
+def test_back_to_back_batches_on_two_streams():
+    """Two batches of disjoint problems enqueued back to back on two streams
+    (no host wait between them) share the batch launch structures; each
+    must still equal separate anneals."""
+    import torch
+    sA, sB = torch.cuda.Stream(), torch.cuda.Stream()
+    sched = B.Schedule.make(B.GEOMETRIC, 400, 0.1, 4.0)
+    R = 32
+    insts_a = [I.torus(40, 40, 121), I.torus(17, 23, 122), I.random_graph(800, 799, 123)]
+    insts_b = [I.torus(12, 12, 124), I.torus(30, 31, 125)]
+    seeds_a = np.array([7200 + i for i in range(len(insts_a))], np.uint64)
+    seeds_b = np.array([7300 + i for i in range(len(insts_b))], np.uint64)
+    pa = [B.Problem.from_instance(x) for x in insts_a]
+    pb = [B.Problem.from_instance(x) for x in insts_b]
+    tun = B.Tuning(B.PATH_FIELD, 1, 512, 0)
+    for _ in range(2):
+        B.ising_anneal_batch([p.handle for p in pa], sched, R, seeds_a, tun, stream=sA)
+        B.ising_anneal_batch([p.handle for p in pb], sched, R, seeds_b, tun, stream=sB)
+    torch.cuda.synchronize()
+    for insts, probs, seeds in ((insts_a, pa, seeds_a), (insts_b, pb, seeds_b)):
+        for i, (inst, p) in enumerate(zip(insts, probs)):
+            per, bs, acc, en, state = _single(inst, sched, R, int(seeds[i]),
+                                              B.Tuning(B.PATH_PLAIN, 1, 256, 0))
+            np.testing.assert_array_equal(B.ising_cut(p.handle, R)[2], per, err_msg=inst.name)
+            bs_b, acc_b, en_b = p.replica_results()
+            np.testing.assert_array_equal(acc_b, acc, err_msg=inst.name)
+            np.testing.assert_array_equal(en_b, en, err_msg=inst.name)
+            np.testing.assert_array_equal(p.best_state(), state, err_msg=inst.name)
+    for p in pa + pb:
+        p.close()

@@ -106,3 +106,45 @@ def test_destroy_with_pending_requests_cancels_them():
     for i in range(4):
         B.ising_server_submit(srv, p.handle, s, 8, i, 10 ** 9, 0)
     B.ising_server_destroy(srv)  # must return promptly
+
+
+def test_results_are_published_whole_while_polled():
+    """Two threads poll wait(ticket, 0) and best_state on every request while
+    the scheduler runs them one sweep per step: a request seen as done
+    always carries its final sweep count, a finish time not before its
+    admission, and its whole best state."""
+    import threading
+    p = _problem(10)
+    S = 300
+    s = B.Schedule.make(B.LINEAR, S, 0.1, 3.0)
+    srv = B.ising_server_create(1 << 30, 4, 1, backend=1)
+    tickets = [B.ising_server_submit(srv, p.handle, s, 16, i, 10 ** 9, 0) for i in range(24)]
+    problems = []
+
+    def poll():
+        seen = set()
+        while len(seen) < len(tickets) and not problems:
+            for t in tickets:
+                if t in seen:
+                    continue
+                try:
+                    r = B.ising_server_wait(srv, t, 0.0)
+                except B.IsingError as e:
+                    if e.status != B.ERR_TIMEOUT:
+                        problems.append(("wait", t, e.status))
+                    continue
+                if not (r.status == 0 and r.sweeps_done == S and 0 <= r.t_admit <= r.t_done):
+                    problems.append(("result", t, r.status, r.sweeps_done, r.t_admit, r.t_done))
+                st = B.ising_server_best_state(srv, t, p.n)
+                if st.shape != (p.n,) or not (st == 1).all():
+                    problems.append(("state", t))
+                seen.add(t)
+
+    threads = [threading.Thread(target=poll) for _ in range(2)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(60)
+    assert not any(th.is_alive() for th in threads)
+    assert problems == []
+    B.ising_server_destroy(srv)
