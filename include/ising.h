@@ -316,6 +316,51 @@ int ising_last_anneal_ms(ising_problem* p, double* ms);
 int ising_last_run_info(const ising_problem* p, int32_t* n_replicas, int32_t* n_sweeps,
                         int32_t* path);
 
+/* ------------------------------------------------- allocation-free anneal */
+/*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the anneal
+ * of ising_anneal_tuned on the FIELD path, with no hipMalloc, hipFree or
+ * other allocating call.  Its results go to caller-owned device buffers,
+ * and every other device buffer of the run (threshold rows, launch
+ * structures, best-state snapshots) is carved from one fixed array of
+ * ISING_NOALLOC_SCRATCH_BYTES bytes per device, held by the library's code
+ * object until the process ends.  Requirements and limits:
+ *  - the problem's graph is already on the current device (its first
+ *    ising_anneal, ising_anneal_batch or ising_temper uploads it;
+ *    ISING_ERR_STATE otherwise);
+ *  - tuning NULL/AUTO or an explicit FIELD tuning; a configuration that is
+ *    not FIELD, initial states or an enabled energy trace give
+ *    ISING_ERR_UNSUPPORTED;
+ *  - R * n_padded bytes of snapshots plus the rows (about
+ *    S * (2 kmax + 10) * 4 bytes) and R * 8 bytes of launch structures must
+ *    fit the array, else ISING_ERR_UNSUPPORTED with the sizes in
+ *    ising_last_error.
+ * Results (device pointers, caller-owned, each written once the enqueued
+ * work completes), identical to those of ising_anneal_tuned:
+ *   best_cut [R], best_sweep [R] (-1 = initial state), final_energy [R]
+ *   (int32); accepts [R] (uint64); argmax [1] = (best cut + 2^31) << 32 |
+ *   (2^32 - 1 - best replica); best_states [R][n] int8 +-1, original order.
+ * Work is enqueued on `stream` and the call returns.  Every call on one
+ * device uses that device's single array: calls whose work overlaps on one
+ * GPU (other streams, other threads) race and must be serialised by the
+ * caller.  The array keeps the last call's contents; this call rewrites
+ * every part it reads.  Other errors as ising_anneal_tuned.
+ */
+#define ISING_NOALLOC_SCRATCH_BYTES (16u << 20)
+typedef struct {
+  int32_t* best_cut;
+  int32_t* best_sweep;
+  int32_t* final_energy;
+  uint64_t* accepts;
+  uint64_t* argmax;
+  int8_t* best_states;
+} ising_device_results;
+int ising_anneal_noalloc(ising_problem* p, const ising_schedule* s,
+                         int32_t n_replicas, uint64_t seed,
+                         const ising_tuning* tuning,
+                         const ising_device_results* out, void* stream);
+
 /* ------------------------------------------------------ parallel tempering */
 /*
  * Parallel tempering (replica exchange), which the paper names among the

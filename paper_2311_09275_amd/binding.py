@@ -80,6 +80,12 @@ class Tempering(C.Structure):
         return t
 
 
+class DeviceResults(C.Structure):
+    """Device pointers for ising_anneal_noalloc's results."""
+    _fields_ = [("best_cut", C.c_void_p), ("best_sweep", C.c_void_p), ("final_energy", C.c_void_p),
+                ("accepts", C.c_void_p), ("argmax", C.c_void_p), ("best_states", C.c_void_p)]
+
+
 class Info(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_colours", C.c_int32), ("m", C.c_int64),
                 ("total_weight", C.c_int64), ("kmax", C.c_int32), ("max_degree", C.c_int32),
@@ -125,6 +131,8 @@ _sig = {
     "ising_energy_trace": ([P, P], C.c_int),
     "ising_last_anneal_ms": ([P, C.POINTER(C.c_double)], C.c_int),
     "ising_last_run_info": ([P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "ising_anneal_noalloc": ([P, C.POINTER(Schedule), C.c_int32, C.c_uint64, C.POINTER(Tuning),
+                              C.POINTER(DeviceResults), P], C.c_int),
     "ising_temper": ([P, C.POINTER(Tempering), C.c_uint64, C.POINTER(Tuning), P], C.c_int),
     "ising_temper_results": ([P, P, P, P, P], C.c_int),
     "ising_anneal_batch": ([P, C.c_int32, C.POINTER(Schedule), C.c_int32, P, C.POINTER(Tuning), P], C.c_int),
@@ -313,6 +321,17 @@ def ising_last_anneal_ms(h) -> float:
 
 
 # ------------------------------------------------------------------ tempering
+def ising_anneal_noalloc(h, sched: Schedule, n_replicas: int, seed: int, tuning: Tuning | None,
+                         best_cut, best_sweep, final_energy, accepts, argmax, best_states,
+                         stream=None) -> None:
+    """The allocation-free anneal; the six result arguments are device
+    addresses (ints), e.g. torch tensors' data_ptr()."""
+    out = DeviceResults(best_cut, best_sweep, final_energy, accepts, argmax, best_states)
+    _check(_L.ising_anneal_noalloc(h, C.byref(sched), int(n_replicas), int(seed),
+                                   None if tuning is None else C.byref(tuning), C.byref(out),
+                                   _stream(stream)), "ising_anneal_noalloc")
+
+
 def ising_temper(h, pt: Tempering, seed: int, tuning: Tuning | None = None, stream=None) -> None:
     _check(_L.ising_temper(h, C.byref(pt), seed & (2**64 - 1),
                            None if tuning is None else C.byref(tuning), _stream(stream)),

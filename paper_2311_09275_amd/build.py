@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libising.so")
 SOURCES = ["kernels.hip", "problem.cpp", "anneal.cpp", "tempering.cpp", "batch.cpp", "server.cpp",
-           "calibrate.hip"]
+           "calibrate.hip", "noalloc.hip"]
 ARCH = os.environ.get("ISING_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

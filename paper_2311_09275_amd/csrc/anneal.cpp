@@ -223,11 +223,11 @@ static size_t persistent_lds(const HostGraph& g, const Table& t, const Persisten
 // row is fetched without first reading its offset.  The kernel indexes a
 // row by the key x = 2 k - c (c = 1 for spin -1, else 0), so entries
 // 2 k - 1 and 2 k both hold the threshold of k.
-static size_t padded_rows(const Table& t) {
+size_t padded_rows(const Table& t) {
   return (size_t)t.S * (size_t)field_row_words(t);
 }
 
-static void build_padded_rows(const Table& t, std::vector<uint32_t>& out) {
+void build_padded_rows(const Table& t, std::vector<uint32_t>& out) {
   const int kw = std::max(t.kw, 1), rw = field_row_words(t);
   out.assign(padded_rows(t), 0u);
   for (int s = 0; s < t.S; ++s) {
@@ -247,7 +247,7 @@ static void build_padded_rows(const Table& t, std::vector<uint32_t>& out) {
 
 // Rows of the degree-4 forms (JobDev::tqb), indexed by the bond count plus
 // one, c = popc(word) in 1..5, for k = 2 c - 6.
-static void build_bond_rows(const Table& t, std::vector<uint32_t>& out) {
+void build_bond_rows(const Table& t, std::vector<uint32_t>& out) {
   out.assign((size_t)t.S * kBondRowWords, 0u);
   for (int s = 0; s < t.S; ++s) {
     uint32_t* row = out.data() + (size_t)s * kBondRowWords;
@@ -582,24 +582,11 @@ JobDev make_job(const HostGraph& g, const DevGraph& d, const RunBuffers& b, int 
 // ---------------------------------------------------------------- persistent
 int temper_max_group(const Table& t) { return row_chunk(t); }
 
-int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const PersistentConfig& cfg,
-                   hipStream_t stream, bool use_graph, const TemperPlan* pt) {
+int plan_persistent(const std::vector<JobSpec>& specs, const PersistentConfig& cfg,
+                    PersistentPlan& P) {
   const int n_jobs = (int)specs.size();
-  if (pt && (n_jobs != 1 || cfg.path != ISING_PATH_FIELD || cfg.G > row_chunk(specs[0].b->table))) {
-    set_error("tempering runs one FIELD job with at most %d replicas per block",
-              n_jobs == 1 ? row_chunk(specs[0].b->table) : 0);
-    return ISING_ERR_UNSUPPORTED;
-  }
-  // segments of the sweeps: one launch each (tempering: up to every
-  // exchange round), else the jobs' own ranges in one launch
-  std::vector<int2> segs;
-  if (pt) {
-    for (int t0 = 0; t0 < pt->S; t0 += pt->P) segs.push_back(make_int2(t0, std::min(pt->S, t0 + pt->P)));
-  } else {
-    segs.push_back(make_int2(-1, -1));
-  }
-  const int n_segs = (int)segs.size();
-  std::vector<JobDev> jobs((size_t)n_jobs);
+  std::vector<JobDev>& jobs = P.jobs;
+  jobs.assign((size_t)n_jobs, JobDev());
   struct U {
     double cost;
     int job, block;
@@ -644,14 +631,15 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
     load[best] += u.cost;
     lists[(size_t)best].push_back(make_int2(u.job, u.block));
   }
-  std::vector<int2> units;
-  int32_t list_off[9];
-  list_off[0] = 0;
+  std::vector<int2>& units = P.units;
+  units.clear();
+  P.list_off[0] = 0;
   for (int i = 0; i < 8; ++i) {
     units.insert(units.end(), lists[(size_t)i].begin(), lists[(size_t)i].end());
-    list_off[i + 1] = (int32_t)units.size();
+    P.list_off[i + 1] = (int32_t)units.size();
   }
   const int n_units = (int)units.size();
+  P.grid = 0;
   if (n_units == 0) return ISING_OK;
 
   const int cus = std::max(device_cu_count(), 1);
@@ -679,6 +667,46 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   }
   if (staged) lds = lds_staged;
   for (int j = 0; j < n_jobs; ++j) jobs[(size_t)j].adj_form = forms[(size_t)j];
+  // raising the dynamic LDS limit is advisory on this runtime
+  if (set_persistent_lds_limit(cfg.path, cfg.block, lds) != hipSuccess) (void)hipGetLastError();
+  const int occ = persistent_occupancy(cfg.path, cfg.block, form, lds);
+  if (occ <= 0) {
+    set_error("persistent kernel cannot be resident with %zu bytes of LDS", lds);
+    return ISING_ERR_UNSUPPORTED;
+  }
+  P.lds = lds;
+  P.form = form;
+  P.planes = planes;
+  P.grid = std::min(n_units, cus * occ);
+  return ISING_OK;
+}
+
+int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const PersistentConfig& cfg,
+                   hipStream_t stream, bool use_graph, const TemperPlan* pt) {
+  const int n_jobs = (int)specs.size();
+  if (pt && (n_jobs != 1 || cfg.path != ISING_PATH_FIELD || cfg.G > row_chunk(specs[0].b->table))) {
+    set_error("tempering runs one FIELD job with at most %d replicas per block",
+              n_jobs == 1 ? row_chunk(specs[0].b->table) : 0);
+    return ISING_ERR_UNSUPPORTED;
+  }
+  // segments of the sweeps: one launch each (tempering: up to every
+  // exchange round), else the jobs' own ranges in one launch
+  std::vector<int2> segs;
+  if (pt) {
+    for (int t0 = 0; t0 < pt->S; t0 += pt->P) segs.push_back(make_int2(t0, std::min(pt->S, t0 + pt->P)));
+  } else {
+    segs.push_back(make_int2(-1, -1));
+  }
+  const int n_segs = (int)segs.size();
+  PersistentPlan plan;
+  IRET(plan_persistent(specs, cfg, plan));
+  std::vector<JobDev>& jobs = plan.jobs;
+  const std::vector<int2>& units = plan.units;
+  const int32_t* list_off = plan.list_off;
+  const int n_units = (int)units.size();
+  if (n_units == 0) return ISING_OK;
+  const size_t lds = plan.lds;
+  const int form = plan.form, planes = plan.planes;
   if (pt) {
     // one copy of the job per segment
     JobDev base = jobs[0];
@@ -710,7 +738,7 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
     L.list_off_d = L.arena.take<int32_t>(16);
     L.ctr_d = L.arena.take<int32_t>(16);
   }
-  const size_t stage_bytes = sizeof(JobDev) * n_dev_jobs + sizeof(int2) * n_units + sizeof(list_off);
+  const size_t stage_bytes = sizeof(JobDev) * n_dev_jobs + sizeof(int2) * n_units + sizeof(plan.list_off);
   if (!L.staged) ICHK(hipEventCreateWithFlags(&L.staged, hipEventDisableTiming));
   (void)hipEventSynchronize(L.staged);  // the previous upload has left the buffer
   if (L.staging_cap < stage_bytes) {
@@ -723,26 +751,19 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   const size_t jb = sizeof(JobDev) * n_dev_jobs;
   memcpy(sp, jobs.data(), jb);
   memcpy(sp + jb, units.data(), sizeof(int2) * n_units);
-  memcpy(sp + jb + sizeof(int2) * n_units, list_off, sizeof(list_off));
+  memcpy(sp + jb + sizeof(int2) * n_units, list_off, sizeof(plan.list_off));
   ICHK(hipMemcpyAsync(L.jobs_d, sp, jb, hipMemcpyHostToDevice, stream));
   ICHK(hipMemcpyAsync(L.units_d, sp + jb, sizeof(int2) * n_units, hipMemcpyHostToDevice, stream));
-  ICHK(hipMemcpyAsync(L.list_off_d, sp + jb + sizeof(int2) * n_units, sizeof(list_off),
+  ICHK(hipMemcpyAsync(L.list_off_d, sp + jb + sizeof(int2) * n_units, sizeof(plan.list_off),
                       hipMemcpyHostToDevice, stream));
   ICHK(hipEventRecord(L.staged, stream));
 
-  // raising the dynamic LDS limit is advisory on this runtime
-  if (set_persistent_lds_limit(cfg.path, cfg.block, lds) != hipSuccess) (void)hipGetLastError();
-  const int occ = persistent_occupancy(cfg.path, cfg.block, form, lds);
-  if (occ <= 0) {
-    set_error("persistent kernel cannot be resident with %zu bytes of LDS", lds);
-    return ISING_ERR_UNSUPPORTED;
-  }
   LaunchPersistent lp;
   lp.jobs = L.jobs_d;
   lp.units = L.units_d;
   lp.list_off = L.list_off_d;
   lp.ctr = L.ctr_d;
-  lp.grid = std::min(n_units, cus * occ);
+  lp.grid = plan.grid;
   lp.lds_bytes = lds;
   lp.planes = planes;
   lp.adj = form;
@@ -1048,9 +1069,9 @@ int ising_set_trace(ising_problem* p, int32_t enable) {
 }
 
 
-// Thresholds of schedule s for p, rebuilt only when s differs from the last
-// schedule p annealed with (the table costs S * kmax exponentials).
-static int schedule_table(ising_problem* p, const ising_schedule* s) {
+// The table costs S * kmax exponentials, so it is kept while the schedule
+// repeats.
+extern "C++" int schedule_table(ising_problem* p, const ising_schedule* s) {
   auto& c = p->sched;
   const bool expl = s->kind == ISING_SCHED_EXPLICIT;
   if (c.table.id != 0 && c.kind == s->kind && c.n_sweeps == s->n_sweeps && s->n_sweeps > 0) {

@@ -51,6 +51,10 @@ hipError_t launch_argmax(const JobDev* jobs, int n_jobs, hipStream_t s);
 hipError_t launch_gather(const void* buf, int layout, int R, int n_pad, int r, const int32_t* pos,
                          int n, int32_t* out, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t s);
+// Every replica's int8 state: src [R][n_pad] in position order to out
+// [R][n] in original order (pos = original id -> position).
+hipError_t launch_gather_states(const int8_t* src, int R, int n_pad, const int32_t* pos, int n,
+                                int8_t* out, hipStream_t s);
 // Parallel tempering: initial ladders, and exchange round m (which also
 // zeroes clear8[0..7] when given).
 hipError_t launch_pt_init(const SwapDev& X, hipStream_t s);

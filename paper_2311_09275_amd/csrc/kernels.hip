@@ -959,7 +959,8 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
         const uint32_t bits = (w4.x & 1) | ((w4.y & 1) << 1) | ((w4.z & 1) << 2) | ((w4.w & 1) << 3);
         *reinterpret_cast<GLOBAL_AS uint32_t*>(best + 4 * g) = spins_to_bytes(bits);
       }
-      *reinterpret_cast<int4*>(J.save + (int64_t)r * n_pad + 4 * g) = w4;
+      // a run that keeps no state for later reads (J.save null) skips it
+      if (J.save) *reinterpret_cast<int4*>(J.save + (int64_t)r * n_pad + 4 * g) = w4;
     }
   }
   // lane 0 takes part in every group iteration of its wave, so its count
@@ -1375,6 +1376,16 @@ __global__ void k_gather(const void* buf, int layout, int R, int n_pad, int r,
       break;
   }
   out[v] = val;
+}
+
+// Every replica's int8 state [R][n_pad] (position order) into [R][n]
+// (original order): one lane per (replica, vertex).
+__global__ void k_gather_states(const int8_t* src, int R, int n_pad, const int32_t* pos, int n,
+                                int8_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)R * n) return;
+  const int r = (int)(i / n), v = (int)(i - (int64_t)r * n);
+  out[i] = src[(int64_t)r * n_pad + pos[v]];
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t value, int64_t count) {
@@ -1824,6 +1835,15 @@ hipError_t launch_gather(const void* buf, int layout, int R, int n_pad, int r, c
                          int n, int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, 256)), dim3(256), 0, s, buf, layout, R, n_pad, r,
                      pos, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_states(const int8_t* src, int R, int n_pad, const int32_t* pos, int n,
+                                int8_t* out, hipStream_t s) {
+  const int64_t cnt = (int64_t)R * n;
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_states, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, src, R, n_pad, pos,
+                     n, out);
   return hipGetLastError();
 }
 

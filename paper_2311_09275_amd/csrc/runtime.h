@@ -250,6 +250,24 @@ struct TemperPlan {
   const ClusterDev* cluster;  // cluster moves before each round, or null
 };
 
+// What one persistent launch needs on the device: the jobs, the units in
+// eight per-XCD lists (longest first), and the launch shape.
+struct PersistentPlan {
+  std::vector<JobDev> jobs;
+  std::vector<int2> units;
+  int32_t list_off[9] = {0};
+  size_t lds = 0;   // dynamic LDS per workgroup
+  int form = 0;     // adjacency form (LaunchPersistent::adj)
+  int planes = 1;   // MSC bit planes
+  int grid = 0;     // workgroups (0 when there are no units)
+};
+int plan_persistent(const std::vector<JobSpec>& specs, const PersistentConfig& cfg,
+                    PersistentPlan& plan);
+// FIELD threshold rows of a table: key rows (JobDev::tqp, padded_rows(t)
+// words) and degree-4 rows (JobDev::tqb, kBondRowWords per sweep).
+size_t padded_rows(const Table& t);
+void build_padded_rows(const Table& t, std::vector<uint32_t>& out);
+void build_bond_rows(const Table& t, std::vector<uint32_t>& out);
 int run_persistent(Launcher& L, const std::vector<JobSpec>& jobs, const PersistentConfig& cfg,
                    hipStream_t stream, bool use_graph, const TemperPlan* pt = nullptr);
 // Largest replicas_per_block whose rows a FIELD tempering launch can stage
@@ -299,6 +317,14 @@ struct ising_problem {
   std::vector<int8_t> init;  // [init_R][n] original order
   int32_t init_R = 0;
   bool trace = false;
+  // ising_anneal_noalloc: the run's view of the scratch array, and host
+  // copies of what it uploads there (kept, so that repeated calls of one
+  // shape reuse their capacity)
+  struct {
+    ising::RunBuffers run;
+    std::vector<uint32_t> rows_p, rows_b;
+    ising::PersistentPlan plan;
+  } noalloc;
   // the thresholds of the last schedule annealed, reused while it repeats
   struct {
     int32_t kind = -1, n_sweeps = 0;
@@ -312,6 +338,9 @@ struct ising_problem {
 const int32_t* fields_or_null(const ising_problem* p);
 // Arguments of the per-pass kernels for a run of p in b (anneal.cpp).
 ising::PlainDev make_plain(const ising_problem* p, const ising::RunBuffers& b, int R, uint64_t seed);
+// Thresholds of schedule s for p (p->sched.table), rebuilt only when s
+// differs from the last schedule p annealed with.
+int schedule_table(ising_problem* p, const ising_schedule* s);
 // Launch configuration of tuning t (NULL or ISING_PATH_AUTO: the tuned or
 // heuristic choice), checked against the problem.
 int resolve_config(ising_problem* p, const ising::Table& table, int R, const ising_tuning* t,
