@@ -200,8 +200,14 @@ enum {
  * Launch choices.  All of them compute identical results.
  *   path                 ISING_PATH_*
  *   replicas_per_block   FIELD: replicas per workgroup (1, 2, 4, 8, 16);
- *                        MSC: 32-replica words per workgroup (1, 2, 4)
- *   block_threads        256, 512 or 1024 (MSC: 256 or 512); 0 = default
+ *                        MSC: 1, 2 or 4 = 32-replica words per workgroup
+ *                        (general form, degree <= 31); 8, 16 or 32 =
+ *                        replicas per workgroup in the degree-4 form (unit
+ *                        weights, every vertex of degree 4, at most 2^15
+ *                        padded vertices: the tori), whose state keeps each
+ *                        vertex's spins of those replicas as one bit field
+ *   block_threads        256, 512 or 1024 (general MSC form: 256 or 512);
+ *                        0 = default
  *   lds_adjacency        FIELD: 0 = decide, 1 = stage a 16-bit adjacency in
  *                        LDS (unit weights, fewer than 2^15 vertices; a
  *                        fixed 48-byte-per-group form with bond-word state

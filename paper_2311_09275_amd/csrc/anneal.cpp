@@ -142,6 +142,7 @@ int upload_graph(const HostGraph& g, DevGraph& d) {
                  DeviceArena::span(sizeof(int32_t) * g.cls.size()) +
                  DeviceArena::span(sizeof(int32_t) * g.n) +
                  DeviceArena::span(sizeof(uint32_t) * g.adj4.size()) +
+                 DeviceArena::span(sizeof(uint32_t) * g.adj4m.size()) +
                  DeviceArena::span(sizeof(int32_t) * (size_t)g.n_pad);
   IRET(d.arena.reserve(bytes));
   d.device = d.arena.device;
@@ -158,10 +159,13 @@ int upload_graph(const HostGraph& g, DevGraph& d) {
   d.cls = d.arena.take<int32_t>(g.cls.size());
   d.pos = d.arena.take<int32_t>(g.n);
   d.adj4 = g.adj4.empty() ? nullptr : d.arena.take<uint32_t>(g.adj4.size());
+  d.adj4m = g.adj4m.empty() ? nullptr : d.arena.take<uint32_t>(g.adj4m.size());
   d.bf = d.arena.take<int32_t>((size_t)g.n_pad);
   ICHK(hipMemcpy(d.bf, g.bpos.data(), sizeof(int32_t) * (size_t)g.n_pad, hipMemcpyHostToDevice));
   if (d.adj4)
     ICHK(hipMemcpy(d.adj4, g.adj4.data(), sizeof(uint32_t) * g.adj4.size(), hipMemcpyHostToDevice));
+  if (d.adj4m)
+    ICHK(hipMemcpy(d.adj4m, g.adj4m.data(), sizeof(uint32_t) * g.adj4m.size(), hipMemcpyHostToDevice));
   ICHK(hipMemcpy(d.row, g.row.data(), sizeof(int32_t) * g.row.size(), hipMemcpyHostToDevice));
   if (e2) {
     ICHK(hipMemcpy(d.adj, g.adj.data(), sizeof(int32_t) * e2, hipMemcpyHostToDevice));
@@ -213,7 +217,14 @@ static int row_chunk(const Table& t) {
 // bounds and the group descriptors (group word, adjacency base, packed
 // degrees).  The multispin kernel needs less (two rows, no class bounds).
 
+// The multispin degree-4 form (c.G = 8, 16 or 32 replicas per unit): each
+// state element next to its complement, and a chunk of degree-4 rows.
+static bool msc4_config(const PersistentConfig& c) { return c.path == ISING_PATH_MSC && c.G >= 8; }
+
 static size_t persistent_lds(const HostGraph& g, const Table& t, const PersistentConfig& c) {
+  if (msc4_config(c))
+    return (((size_t)field_state_words(g.n_pad) * (size_t)(c.G / 4) + 15) & ~(size_t)15) +
+           sizeof(uint32_t) * (size_t)row_chunk(t) * kBondRowWords;
   const size_t rows = (size_t)row_chunk(t) * (size_t)row_words_max(t);
   return sizeof(int32_t) * ((size_t)c.G * field_state_words(g.n_pad) + rows + 2 * (size_t)g.C) +
          3 * sizeof(int32_t) * (size_t)(g.n_pad / 4);
@@ -316,10 +327,17 @@ int check_config(const HostGraph& g, const Table& t, int R, const PersistentConf
     set_error("block_threads must be 256, 512 or 1024");
     return ISING_ERR_INVALID;
   }
-  const int gmax = c.path == ISING_PATH_FIELD ? kMaxReplicasPerBlock : kMaxWordsPerBlock;
-  if (!pow2_upto(c.G, gmax) || c.block / c.G < 64) {
-    set_error("replicas_per_block %d invalid for %d threads", c.G, c.block);
-    return ISING_ERR_INVALID;
+  if (msc4_config(c)) {
+    if (c.G != 8 && c.G != 16 && c.G != 32) {
+      set_error("the multispin degree-4 form takes 8, 16 or 32 replicas per block");
+      return ISING_ERR_INVALID;
+    }
+  } else {
+    const int gmax = c.path == ISING_PATH_FIELD ? kMaxReplicasPerBlock : kMaxWordsPerBlock;
+    if (!pow2_upto(c.G, gmax) || c.block / c.G < 64) {
+      set_error("replicas_per_block %d invalid for %d threads", c.G, c.block);
+      return ISING_ERR_INVALID;
+    }
   }
   if (c.adj < 0 || c.adj > 4) {
     set_error("adjacency mode %d invalid", c.adj);
@@ -351,8 +369,29 @@ int check_config(const HostGraph& g, const Table& t, int R, const PersistentConf
       set_error("the multispin path supports degree <= 31");
       return ISING_ERR_UNSUPPORTED;
     }
-    if (c.block == 1024) {
-      set_error("the multispin path runs 256 or 512 threads");
+    if (msc4_config(c)) {
+      if (g.adj4m.empty()) {
+        set_error("the multispin degree-4 form needs every vertex of degree 4 and at most "
+                  "2^15 padded positions");
+        return ISING_ERR_UNSUPPORTED;
+      }
+      if (g.C > kMaxFieldColours) {
+        set_error("the multispin degree-4 form supports at most %d colour classes", kMaxFieldColours);
+        return ISING_ERR_UNSUPPORTED;
+      }
+      // groups a lane meets per sweep bound the kernel's counter planes
+      const int per_iter = (32 / c.G) * c.block;
+      int its = 0;
+      for (int k = 0; k < g.C; ++k)
+        its += (g.cls[(size_t)(2 * k + 1)] - g.cls[(size_t)(2 * k)] + per_iter - 1) / per_iter;
+      if (its > kMsc4MaxLaneIters) {
+        set_error("the multispin degree-4 form with %d replicas and %d threads per block takes at "
+                  "most %d groups per lane and sweep (this problem needs %d)",
+                  c.G, c.block, kMsc4MaxLaneIters, its);
+        return ISING_ERR_UNSUPPORTED;
+      }
+    } else if (c.block == 1024) {
+      set_error("the general multispin form runs 256 or 512 threads");
       return ISING_ERR_INVALID;
     }
   }
@@ -418,9 +457,10 @@ size_t run_bytes(const HostGraph& g, const Table& table, int R, const Persistent
          DeviceArena::span(sizeof(int32_t) * (size_t)g.n) +
          DeviceArena::span(sizeof(uint32_t) * table.tq.size()) +
          2 * DeviceArena::span(sizeof(int32_t) * S) + (init_given ? DeviceArena::span(RR * np) : 0) +
-         (cfg.path == ISING_PATH_FIELD ? DeviceArena::span(sizeof(uint32_t) * padded_rows(table)) +
-                                            DeviceArena::span(sizeof(uint32_t) * kBondRowWords * S)
-                                      : 0) +
+         (cfg.path == ISING_PATH_FIELD ? DeviceArena::span(sizeof(uint32_t) * padded_rows(table)) : 0) +
+         (cfg.path == ISING_PATH_FIELD || msc
+              ? DeviceArena::span(sizeof(uint32_t) * kBondRowWords * S)
+              : 0) +
          DeviceArena::span(sizeof(JobDev));
 }
 
@@ -466,7 +506,8 @@ int prepare_buffers(RunBuffers& b, const HostGraph& g, const Table& table, int R
   b.tq_off = b.arena.take<int32_t>((size_t)S);
   b.tq_len = b.arena.take<int32_t>((size_t)S);
   b.tqp = cfg.path == ISING_PATH_FIELD ? b.arena.take<uint32_t>(padded_rows(table)) : nullptr;
-  b.tqb = cfg.path == ISING_PATH_FIELD ? b.arena.take<uint32_t>((size_t)kBondRowWords * S) : nullptr;
+  b.tqb = cfg.path == ISING_PATH_FIELD || msc ? b.arena.take<uint32_t>((size_t)kBondRowWords * S)
+                                              : nullptr;
   b.init_dev = init_given ? b.arena.take<int8_t>(RR * np) : nullptr;
   b.job_dev = b.arena.take<JobDev>(1);
   if (plain) {
@@ -487,7 +528,7 @@ int prepare_buffers(RunBuffers& b, const HostGraph& g, const Table& table, int R
   b.stream = stream;
   // The tables are uploaded unless this same table already sits at these
   // addresses of this same arena (a pool's memory is always rewritten).
-  const void* at = b.tqp ? (const void*)b.tqp : (const void*)b.tq;
+  const void* at = b.tqp ? (const void*)b.tqp : b.tqb ? (const void*)b.tqb : (const void*)b.tq;
   const bool resident = !pool && table.id != 0 && b.up_table == table.id &&
                         b.up_generation == b.arena.generation && b.up_at == at;
   if (!resident) {
@@ -503,6 +544,8 @@ int prepare_buffers(RunBuffers& b, const HostGraph& g, const Table& table, int R
       build_padded_rows(b.table, b.tqp_host);
       ICHK(hipMemcpyAsync(b.tqp, b.tqp_host.data(), sizeof(uint32_t) * b.tqp_host.size(),
                           hipMemcpyHostToDevice, stream));
+    }
+    if (b.tqb) {
       build_bond_rows(b.table, b.tqb_host);
       ICHK(hipMemcpyAsync(b.tqb, b.tqb_host.data(), sizeof(uint32_t) * b.tqb_host.size(),
                           hipMemcpyHostToDevice, stream));
@@ -542,6 +585,7 @@ JobDev make_job(const HostGraph& g, const DevGraph& d, const RunBuffers& b, int 
   J.wgt = d.wgt;
   J.adjm = d.adjm;
   J.adj4 = reinterpret_cast<const uint4*>(d.adj4);
+  J.adj4m = reinterpret_cast<const uint4*>(d.adj4m);
   J.aw = d.aw;
   J.grp = d.grp;
   J.gbase = d.gbase;
@@ -611,7 +655,7 @@ int plan_persistent(const std::vector<JobSpec>& specs, const PersistentConfig& c
     forms[(size_t)j] = f;
     lds_staged = std::max(lds_staged, own + (form_in_lds(f) ? adjacency_lds(*s.g, f) : 0));
     planes = std::max(planes, msc_planes(s.g->max_deg));
-    const int per = cfg.path == ISING_PATH_MSC ? 32 * cfg.G : cfg.G;
+    const int per = msc4_config(cfg) ? cfg.G : cfg.path == ISING_PATH_MSC ? 32 * cfg.G : cfg.G;
     const int nb = (s.R + per - 1) / per;
     const double cost = (double)s.g->n_pad * (s.t_end - s.t_begin) * per + 1.0;
     for (int k = 0; k < nb; ++k) all.push_back(U{cost, j, k});
@@ -643,6 +687,22 @@ int plan_persistent(const std::vector<JobSpec>& specs, const PersistentConfig& c
   if (n_units == 0) return ISING_OK;
 
   const int cus = std::max(device_cu_count(), 1);
+  if (cfg.path == ISING_PATH_MSC) {
+    // the multispin kernels read their adjacency from HBM; the form slot
+    // carries the width (0 = the general form)
+    const int width = msc4_config(cfg) ? cfg.G : 0;
+    if (set_persistent_lds_limit(cfg.path, cfg.block, lds) != hipSuccess) (void)hipGetLastError();
+    const int occ = persistent_occupancy(cfg.path, cfg.block, width, lds);
+    if (occ <= 0) {
+      set_error("persistent kernel cannot be resident with %zu bytes of LDS", lds);
+      return ISING_ERR_UNSUPPORTED;
+    }
+    P.lds = lds;
+    P.form = width;
+    P.planes = planes;
+    P.grid = std::min(n_units, cus * occ);
+    return ISING_OK;
+  }
   int form = forms.empty() ? kFormHbm : forms[0];
   bool staged = false;
   for (int f : forms) {
@@ -766,7 +826,8 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
   lp.grid = plan.grid;
   lp.lds_bytes = lds;
   lp.planes = planes;
-  lp.adj = form;
+  lp.adj = cfg.path == ISING_PATH_MSC ? 0 : form;
+  lp.width = cfg.path == ISING_PATH_MSC ? form : 0;
 
   // An exchange round also clears the list cursors for the next segment.
   auto enqueue = [&](hipStream_t s) -> hipError_t {

@@ -265,6 +265,9 @@ int ising_autotune(ising_problem* const* ps, int32_t count, const ising_schedule
       for (int G : {1, 2, 4, 8, 16}) cands.push_back(PersistentConfig{ISING_PATH_FIELD, G, block, adj});
   for (int block : {256, 512})
     for (int G : {1, 2, 4}) cands.push_back(PersistentConfig{ISING_PATH_MSC, G, block, 0});
+  // the multispin degree-4 form, 8, 16 or 32 replicas per unit
+  for (int block : {256, 512, 1024})
+    for (int G : {8, 16, 32}) cands.push_back(PersistentConfig{ISING_PATH_MSC, G, block, 0});
 
   Launcher L;
   double best_ms = 1e300;

@@ -29,6 +29,17 @@ constexpr int32_t kAcceptAll = -1;
 // e XOR 1 is v), word 8 the group's first vertex, word 9 bit 4j+e set when entry e of
 // slot j has w > 0; words 10 and 11 are zero.
 constexpr int kDeg4BlockWords = 12;
+// Multispin degree-4 form: 8 words (32 bytes) per group, the 16-bit
+// element indices of slot j's four neighbours at 16-bit index 4j..4j+3,
+// each naming the neighbour's element (even) or its complement (odd) so
+// that the read element XOR the vertex's own is the bond's unsatisfied
+// mask.  The state keeps element 2 i + 1 = NOT element 2 i.
+constexpr int kDeg4MscBlockWords = 8;
+// Multispin degree-4 form: at most this many groups of a lane's per sweep
+// (sum over classes of ceil(class groups / (32 / W * threads))), so that the
+// kernel's bit-sliced flip counters (8 planes) and sums of u (10 planes)
+// cannot overflow: 4 x 63 < 2^8, 16 x 63 < 2^10.
+constexpr int kMsc4MaxLaneIters = 63;
 
 // FIELD path, degree-4 forms: a vertex's LDS word holds bond bits instead
 // of a field.  Bit 0 is the spin bit b, bit 1 its complement, and bit
@@ -59,7 +70,7 @@ constexpr int32_t kPadWord = 0x7FFFFFFF;
 
 constexpr int kMaxReplicasPerBlock = 16;   // FIELD path
 constexpr int kMaxFieldColours = 64;       // FIELD path: colour classes
-constexpr int kMaxWordsPerBlock = 4;       // MSC path
+constexpr int kMaxWordsPerBlock = 4;       // MSC path, general form (words of 32 replicas)
 constexpr int kMaxThresholdRow = 1024;     // LDS paths stage <= this many
 constexpr int kMaxLdsDegree = 255;         // LDS paths pack degrees in 8 bits
 
@@ -79,6 +90,7 @@ struct JobDev {
   const uint32_t* adjm;  // [2m] (position << 1) | (w > 0), unit weights only
   const int2* aw;        // [2m] {neighbour position, w}
   const uint4* adj4;     // degree-4 graphs: [n_pad/4][3] group blocks (kDeg4Block*)
+  const uint4* adj4m;    // degree-4 graphs, multispin form: [n_pad/4][2] (kDeg4MscBlockWords)
   const int32_t* grp;    // [n_pad/4] group words
   const int32_t* gbase;  // [n_pad/4] first adjacency entry of the group
   const uint32_t* gdeg;  // [n_pad/4] degrees of the group's four slots, 8 bits each
@@ -108,7 +120,8 @@ struct JobDev {
   // run
   uint32_t seed_lo, seed_hi;
   int32_t R;             // replicas
-  int32_t G;             // FIELD: replicas per block; MSC: words per block
+  int32_t G;             // FIELD: replicas per block; MSC: words per block (general
+                         // form) or replicas per block (degree-4 form: 8, 16, 32)
   int32_t adj_form;      // FIELD: this job's staged adjacency form (mixed launches)
   const int8_t* init_spins;  // [R][n_pad] +-1, positions order
   // state and outputs

@@ -36,13 +36,15 @@ struct LaunchPersistent {
                            // 2 = staged degree-4 form (every vertex of degree 4),
                            // 3 = each job's own form (JobDev::adj_form),
                            // 4 = degree-4 blocks read from HBM
+  int width = 0;           // MSC: 0 = general form (units of 32-replica words);
+                           // 8, 16, 32 = degree-4 form with units of that many replicas
 };
 
 hipError_t launch_plain_anneal(const PlainDev& P, const PlainPlan& plan, hipStream_t s);
 hipError_t launch_field(const LaunchPersistent& L, int block, hipStream_t s);
 hipError_t launch_msc(const LaunchPersistent& L, int block, hipStream_t s);
 // Resident workgroups per CU of a persistent kernel (path 2 = FIELD, 3 = MSC;
-// adj = the FIELD adjacency form, as in LaunchPersistent).
+// adj = the FIELD adjacency form, as in LaunchPersistent, or the MSC width).
 int persistent_occupancy(int path, int block, int adj, size_t lds_bytes);
 hipError_t set_persistent_lds_limit(int path, int block, size_t lds_bytes);
 // Per job: argmax over replicas of best_cut, packed into *argmax as

@@ -1333,6 +1333,547 @@ k_msc(const JobDev* __restrict__ jobs, const int2* __restrict__ units,
   }
 }
 
+// ================================================================ msc4
+// Multispin form of the degree-4 graphs (unit weights, every vertex of
+// degree 4: the tori).  A unit is W replicas (W = 8, 16 or 32) of one
+// problem.  The state of position p is a W-bit element (bit b = spin of
+// replica r0 + b, set = +1), kept in LDS next to its complement in the
+// tiled layout of the FIELD kernel's degree-4 forms; an adjacency entry
+// names the neighbour's element or its complement, whichever carries the
+// edge's sign, so the element read XOR the vertex's own is the bond's
+// unsatisfied mask (w s_v s_u = +1).  A lane takes P = 32 / W groups at
+// once, their elements side by side in one register (group h in bits
+// h W .. h W + W - 1), so each bitwise operation serves 32 (group, replica)
+// pairs whatever W is.
+//
+// Per slot the four unsatisfied masks are counted bit-sliced into u (three
+// planes), and k = 4 - 2u.  Moves with u >= 2 (k <= 0) are accepted; u = 1
+// (k = 2) and u = 0 (k = 4) compare the replica's draw with the sweep's
+// thresholds.  The compares do not depend on the state: each (group,
+// replica) draw is compared with both thresholds into one bit of two masks
+// per slot, and the flip mask is F = u1 | u2 | (u0 ? A2 : A4) over the real
+// slots.  Accounting: a lane counts, bit-sliced, the flips N of a sweep and
+// the sum of u over them; a flip changes the energy by 2 k = 8 - 4 u, so the
+// sweep's change is 8 N - 4 sum(u F).  At the end of the sweep the counters
+// are summed over the wave, still bit-sliced, and each replica's totals are
+// read out by one lane.
+
+template <int W>
+struct Msc4Types;
+template <>
+struct Msc4Types<8> {
+  typedef uint8_t E;
+  typedef uint16_t Pair;
+};
+template <>
+struct Msc4Types<16> {
+  typedef uint16_t E;
+  typedef uint32_t Pair;
+};
+template <>
+struct Msc4Types<32> {
+  typedef uint32_t E;
+  typedef unsigned long long Pair;
+};
+
+// Planes of a lane's counters: a (group, replica) bit of a lane meets at
+// most kMsc4MaxLaneIters groups per sweep (checked on the host), each with
+// at most 4 flips and a sum of u of 16.
+constexpr int kMsc4NPlanes = 8;   // flips in one sweep
+constexpr int kMsc4UPlanes = 10;  // sum of u over them (also the initial sum of u)
+
+struct Msc4Shared {
+  int32_t unit;
+  int32_t dE[3][32];  // [t % 3]: energy change of sweep t, per replica of the unit
+  int32_t dN[3][32];  // [t % 3]: flips of sweep t
+  int32_t usum[32];   // fresh start: sum over positions of u
+};
+
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+}
+
+// A[j] = 2 A[j] + (x_j <= T) for the four words of a block.  The four
+// compares go to separate SGPR pairs before the four adds-with-carry read
+// them, so that no compare waits on the previous add (one carry register
+// would chain all of them).
+__device__ __forceinline__ void shift_in4(uint32_t (&A)[4], const uint4& x, uint32_t T) {
+  uint64_t m0, m1, m2, m3;
+  asm("v_cmp_ge_u32_e64 %0, %4, %5\n\t"
+      "v_cmp_ge_u32_e64 %1, %4, %6\n\t"
+      "v_cmp_ge_u32_e64 %2, %4, %7\n\t"
+      "v_cmp_ge_u32_e64 %3, %4, %8"
+      : "=&s"(m0), "=&s"(m1), "=&s"(m2), "=&s"(m3)
+      : "s"(T), "v"(x.x), "v"(x.y), "v"(x.z), "v"(x.w));
+  asm("v_addc_co_u32_e64 %0, %4, %0, %0, %4\n\t"
+      "v_addc_co_u32_e64 %1, %5, %1, %1, %5\n\t"
+      "v_addc_co_u32_e64 %2, %6, %2, %2, %6\n\t"
+      "v_addc_co_u32_e64 %3, %7, %3, %3, %7"
+      : "+v"(A[0]), "+v"(A[1]), "+v"(A[2]), "+v"(A[3]), "+s"(m0), "+s"(m1), "+s"(m2), "+s"(m3));
+}
+
+// n = a + b + c + d of four masks, bit-sliced into three planes.
+__device__ __forceinline__ void count4(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t& n0,
+                                       uint32_t& n1, uint32_t& n2) {
+  const uint32_t s = xor3(a, b, c), k = maj3(a, b, c);
+  n0 = s ^ d;
+  const uint32_t k2 = s & d;
+  n1 = k ^ k2;
+  n2 = k & k2;
+}
+
+// X += Y, bit-sliced (NY <= NX planes; a carry out of plane NX - 1 is
+// dropped, which the plane bounds exclude).
+template <int NX, int NY>
+__device__ __forceinline__ void slice_add_n(uint32_t (&X)[NX], const uint32_t (&Y)[NY]) {
+  uint32_t c = X[0] & Y[0];
+  X[0] ^= Y[0];
+#pragma unroll
+  for (int p = 1; p < NX; ++p) {
+    const uint32_t x = X[p];
+    if (p < NY) {
+      X[p] = xor3(x, Y[p], c);
+      c = maj3(x, Y[p], c);
+    } else {
+      X[p] = x ^ c;
+      c = x & c;
+    }
+  }
+}
+
+// Z holds a lane's counter in its first NP planes (zeros above); it becomes
+// the sum over the wave (NP + 6 planes), in every lane.  All lanes take part.
+template <int NP, int NZ>
+__device__ __forceinline__ void slice_wave_sum(uint32_t (&Z)[NZ]) {
+  static_assert(NZ >= NP + 6, "the wave sum needs six more planes");
+#pragma unroll
+  for (int lvl = 0; lvl < 6; ++lvl) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int p = 0; p < NP + lvl + 1; ++p) {
+      const uint32_t y = (uint32_t)__shfl_xor((int)Z[p], 1 << lvl, 64);
+      const uint32_t x = Z[p];
+      Z[p] = xor3(x, y, c);
+      c = maj3(x, y, c);
+    }
+  }
+}
+
+// Value at bit `bit` of a bit-sliced number.
+template <int NZ>
+__device__ __forceinline__ int slice_value(const uint32_t (&Z)[NZ], int bit) {
+  int v = 0;
+#pragma unroll
+  for (int p = 0; p < NZ; ++p) v |= (int)((Z[p] >> bit) & 1u) << p;
+  return v;
+}
+
+// LDS byte address base + MUL * (half HI of a packed pair of 16-bit
+// entries), one multiply-add.
+template <int HI, int MUL>
+__device__ __forceinline__ uint32_t lds_entry_addr(uint32_t two, uint32_t base) {
+  uint32_t a;
+  if (HI)
+    asm("v_mad_u32_u16 %0, %1, %3, %2 op_sel:[1,0,0,0]" : "=v"(a) : "v"(two), "v"(base), "n"(MUL));
+  else
+    asm("v_mad_u32_u16 %0, %1, %3, %2" : "=v"(a) : "v"(two), "v"(base), "n"(MUL));
+  return a;
+}
+
+template <class T>
+__device__ __forceinline__ T lds_load(uint32_t byte_addr) {
+  return *(const __attribute__((address_space(3))) T*)(uintptr_t)byte_addr;
+}
+template <class T>
+__device__ __forceinline__ void lds_store(uint32_t byte_addr, T v) {
+  *(__attribute__((address_space(3))) T*)(uintptr_t)byte_addr = v;
+}
+
+// An element and its complement, as stored.
+template <int W>
+__device__ __forceinline__ typename Msc4Types<W>::Pair msc4_pair(uint32_t e) {
+  typedef typename Msc4Types<W>::Pair Pair;
+  if constexpr (W == 32) {
+    return (Pair)e | ((Pair)(~e) << 32);
+  } else {
+    constexpr uint32_t M = (1u << W) - 1u;
+    return (Pair)((e & M) | ((~e & M) << W));
+  }
+}
+
+// Byte offset of replica block r0's element of position p in the [R/32][n_pad]
+// word arrays (save, best): the element's word is (r0 / 32, p), its byte
+// (r0 mod 32) / 8.
+__device__ __forceinline__ int64_t msc4_word_byte(int r0, int n_pad, int p) {
+  return ((int64_t)(r0 >> 5) * n_pad + p) * 4 + ((r0 & 31) >> 3);
+}
+
+template <int BLOCK, int W>
+__device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4Shared& sh) {
+  typedef typename Msc4Types<W>::E E;
+  typedef typename Msc4Types<W>::Pair Pair;
+  constexpr int P = 32 / W;
+  constexpr uint32_t WM = W == 32 ? 0xFFFFFFFFu : (1u << (W & 31)) - 1u;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int r0 = block * W;
+  const int live = min(W, J.R - r0);
+  const int n_pad = J.n_pad, n_grp = n_pad >> 2;
+  const int SW = field_state_words(n_pad);
+  const int C = J.n_colours;
+  const uint32_t k0 = J.seed_lo, k1 = J.seed_hi;
+  const bool fresh = J.t_begin == 0;
+  const uint32_t st_base = (uint32_t)(uintptr_t)(lds_i32*)smem;
+  uint32_t* rows = smem + ((SW * (int)sizeof(Pair) + 15) & ~15) / 4;
+  const GLOBAL_AS u32x4* __restrict__ am = gconst(reinterpret_cast<const u32x4*>(J.adj4m));
+  GLOBAL_AS uint8_t* saveb = gmut(reinterpret_cast<uint8_t*>(J.save));
+  GLOBAL_AS uint8_t* bestb = gmut(static_cast<uint8_t*>(J.best));
+  auto own_addr = [&](int g, int j) { return st_base + (uint32_t)sizeof(Pair) * (uint32_t)tile_word(g, j); };
+
+  for (int i = tid; i < 3 * 32; i += BLOCK) {
+    (&sh.dE[0][0])[i] = 0;
+    (&sh.dN[0][0])[i] = 0;
+  }
+  if (tid < 32) sh.usum[tid] = 0;
+
+  // ---- state in: initial draw (tag 1) or given spins, or the saved elements
+  for (int g = tid; g < n_grp; g += BLOCK) {
+    const int cnt = (J.grp[g] >> kGroupCountShift) + 1;
+    uint32_t w4[4] = {0u, 0u, 0u, 0u};
+    if (!fresh) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w4[j] = *(const GLOBAL_AS E*)(saveb + msc4_word_byte(r0, n_pad, 4 * g + j));
+    } else if (J.flags & kJobInitGiven) {
+      for (int b = 0; b < live; ++b)
+        for (int j = 0; j < cnt; ++j)
+          w4[j] |= (J.init_spins[(int64_t)(r0 + b) * n_pad + 4 * g + j] > 0 ? 1u : 0u) << b;
+    } else {
+      for (int b = 0; b < W; ++b) {
+        const uint4 x = group_block((uint32_t)g, 0, (uint32_t)(r0 + b), kTagInit, k0, k1);
+        w4[0] |= (x.x >> 31) << b;
+        w4[1] |= (x.y >> 31) << b;
+        w4[2] |= (x.z >> 31) << b;
+        w4[3] |= (x.w >> 31) << b;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) lds_store<Pair>(own_addr(g, j), msc4_pair<W>(w4[j]));
+  }
+  const int CH = J.row_chunk;
+  stage_row_chunk(J.tqb, J.t_begin, min(CH, J.t_end - J.t_begin), rows, kBondRowWords);
+  __syncthreads();
+
+  // Packed state of the lane's groups g_h = gb + h (h < P): own elements
+  // S[j], unsatisfied masks D[j][e], real slots V[j].  cnt_of(g) is the
+  // group's slot count, 0 past the end of its range; such a group reads
+  // group gb's data (every access stays valid) and V masks it off.  All
+  // adjacency loads are issued before any element is read.
+  uint32_t S[4], V[4], D[4][4];
+  auto gather = [&](int gb, auto cnt_of) {
+    u32x4 a[P][2];
+    int gs[P];
+#pragma unroll
+    for (int h = 0; h < P; ++h) {
+      const int cnt = cnt_of(gb + h);
+      gs[h] = cnt > 0 ? gb + h : gb;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) V[j] = (h == 0 ? 0u : V[j]) | ((j < cnt ? WM : 0u) << (h * W));
+      a[h][0] = am[2 * gs[h]];
+      a[h][1] = am[2 * gs[h] + 1];
+    }
+#pragma unroll
+    for (int h = 0; h < P; ++h) {
+      // one group's reads at a time, so that few loaded elements are live
+      __builtin_amdgcn_sched_barrier(0);
+      const uint32_t ent[8] = {a[h][0].x, a[h][0].y, a[h][0].z, a[h][0].w,
+                               a[h][1].x, a[h][1].y, a[h][1].z, a[h][1].w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t s = lds_load<E>(own_addr(gs[h], j));
+        const uint32_t n0 = lds_load<E>(lds_entry_addr<0, sizeof(E)>(ent[2 * j], st_base));
+        const uint32_t n1 = lds_load<E>(lds_entry_addr<1, sizeof(E)>(ent[2 * j], st_base));
+        const uint32_t n2 = lds_load<E>(lds_entry_addr<0, sizeof(E)>(ent[2 * j + 1], st_base));
+        const uint32_t n3 = lds_load<E>(lds_entry_addr<1, sizeof(E)>(ent[2 * j + 1], st_base));
+        if (h == 0) {
+          S[j] = s;
+          D[j][0] = n0;
+          D[j][1] = n1;
+          D[j][2] = n2;
+          D[j][3] = n3;
+        } else {
+          S[j] |= s << (h * W);
+          D[j][0] |= n0 << (h * W);
+          D[j][1] |= n1 << (h * W);
+          D[j][2] |= n2 << (h * W);
+          D[j][3] |= n3 << (h * W);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) D[j][e] ^= S[j];
+  };
+
+  // ---- initial energy: E = sum_p u_p - M (each unsatisfied bond counted at
+  // both ends is 2 U, and E = 2 U - M)
+  int E_r = 0, best_cut_r = 0, best_sweep_r = 0;
+  unsigned long long acc_r = 0;
+  uint32_t snapW = 0;
+  if (fresh) {
+    uint32_t AU[kMsc4UPlanes + 6];  // the top six planes take the wave sum's carries
+#pragma unroll
+    for (int p = 0; p < kMsc4UPlanes + 6; ++p) AU[p] = 0u;
+    for (int gb = P * tid; gb < n_grp; gb += P * BLOCK) {
+      gather(gb, [&](int g) { return g < n_grp ? (J.grp[g] >> kGroupCountShift) + 1 : 0; });
+      uint32_t u[4][3];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        count4(D[j][0], D[j][1], D[j][2], D[j][3], u[j][0], u[j][1], u[j][2]);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) u[j][q] &= V[j];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) slice_add_n(AU, u[j]);
+    }
+    slice_wave_sum<kMsc4UPlanes>(AU);
+    if (lane < 32) {
+      const int v = slice_value(AU, lane);
+      if (v) atomicAdd(&sh.usum[lane & (W - 1)], v);
+    }
+    __syncthreads();
+    if (lane < W) {
+      E_r = sh.usum[lane] - J.M;
+      best_cut_r = (J.W - E_r) / 2;
+      best_sweep_r = -1;
+    }
+    snapW = WM;  // the initial state is written during sweep 0
+  } else if (lane < live) {
+    E_r = J.energy[r0 + lane];
+    best_cut_r = J.best_cut[r0 + lane];
+    best_sweep_r = J.best_sweep[r0 + lane];
+    acc_r = J.accepts[r0 + lane];
+  }
+
+  int tc = 0;
+  for (int t = J.t_begin; t < J.t_end; ++t) {
+    if (tc == CH) {
+      stage_row_chunk(J.tqb, t, min(CH, J.t_end - t), rows, kBondRowWords);
+      tc = 0;
+      __syncthreads();
+    }
+    const uint32_t* row = rows + tc * kBondRowWords;
+    ++tc;
+    const uint32_t T2 = __builtin_amdgcn_readfirstlane(row[4]);
+    const uint32_t T4 = __builtin_amdgcn_readfirstlane(row[5]);
+    const int bound = __builtin_amdgcn_readfirstlane((int)row[7]);
+    const bool need2 = bound >= 4, need4 = bound >= 5;
+    const uint32_t snap32 = snapW * (W == 8 ? 0x01010101u : W == 16 ? 0x00010001u : 1u);
+    uint32_t AN[kMsc4NPlanes], AU[kMsc4UPlanes];
+#pragma unroll
+    for (int p = 0; p < kMsc4NPlanes; ++p) AN[p] = 0u;
+#pragma unroll
+    for (int p = 0; p < kMsc4UPlanes; ++p) AU[p] = 0u;
+    bool worked = false;
+    for (int c = 0; c < C; ++c) {
+      const int g0 = J.cls[2 * c], g1 = J.cls[2 * c + 1];
+      const int cnt_last = g1 > g0 ? (J.grp[g1 - 1] >> kGroupCountShift) + 1 : 0;
+      for (int gb = g0 + P * tid; gb < g1; gb += P * BLOCK) {
+        worked = true;
+        // draws of the lane's groups, compared with both thresholds; they do
+        // not depend on the state, so they come first, four independent
+        // blocks at a time (bits are shifted in from the highest: group
+        // P-1, replica W-1 first)
+        uint32_t A2[4] = {0u, 0u, 0u, 0u}, A4[4] = {0u, 0u, 0u, 0u};
+        if (need4) {
+#pragma unroll
+          for (int h = P - 1; h >= 0; --h) {
+            const uint32_t g = (uint32_t)(gb + h);
+            for (int b = W - 1; b >= 0; b -= 4) {
+              uint4 x[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) x[i] = group_block(g, t, (uint32_t)(r0 + b - i), kTagSweep, k0, k1);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                shift_in4(A2, x[i], T2);
+                shift_in4(A4, x[i], T4);
+              }
+              // four blocks in flight, not more (registers)
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          }
+        } else if (need2) {
+#pragma unroll
+          for (int h = P - 1; h >= 0; --h) {
+            const uint32_t g = (uint32_t)(gb + h);
+            for (int b = W - 1; b >= 0; b -= 4) {
+              uint4 x[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) x[i] = group_block(g, t, (uint32_t)(r0 + b - i), kTagSweep, k0, k1);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) shift_in4(A2, x[i], T2);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          }
+        }
+        gather(gb, [&](int g) { return g >= g1 ? 0 : g == g1 - 1 ? cnt_last : 4; });
+        // lazy best-state snapshot: these groups' end-of-last-sweep spins
+        if (snap32) {
+          // (rare after the first sweeps: a rolled loop, so that it adds
+          // no registers to the unrolled visit)
+#pragma unroll 1
+          for (int h = 0; h < P; ++h) {
+            const int g = gb + h;
+            if (g < g1) {
+              GLOBAL_AS E* bp = (GLOBAL_AS E*)(bestb + msc4_word_byte(r0, n_pad, 4 * g));
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                if ((V[j] >> (h * W)) & 1u) {
+                  // element j of the group is 4 bytes further per slot
+                  GLOBAL_AS E* q = (GLOBAL_AS E*)((GLOBAL_AS uint8_t*)bp + 4 * j);
+                  const uint32_t old = *q, sv = (S[j] >> (h * W)) & WM;
+                  *q = (E)((old & ~snapW) | (sv & snapW));
+                }
+              }
+            }
+          }
+        }
+        // flips, counts and the new state
+        uint32_t F[4], uF[4][3];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          uint32_t u0, u1, u2;
+          count4(D[j][0], D[j][1], D[j][2], D[j][3], u0, u1, u2);
+          const uint32_t sel = (u0 & A2[j]) | (~u0 & A4[j]);
+          F[j] = (u1 | u2 | sel) & V[j];
+          uF[j][0] = u0 & F[j];
+          uF[j][1] = u1 & F[j];
+          uF[j][2] = u2 & F[j];
+        }
+        uint32_t nf[3];
+        count4(F[0], F[1], F[2], F[3], nf[0], nf[1], nf[2]);
+        // sum of u over the flips: (uF0 + uF1) + (uF2 + uF3), 5 planes
+        uint32_t s01[4], s23[4], su[5];
+        {
+          uint32_t cy = uF[0][0] & uF[1][0];
+          s01[0] = uF[0][0] ^ uF[1][0];
+          s01[1] = xor3(uF[0][1], uF[1][1], cy);
+          cy = maj3(uF[0][1], uF[1][1], cy);
+          s01[2] = xor3(uF[0][2], uF[1][2], cy);
+          s01[3] = maj3(uF[0][2], uF[1][2], cy);
+          cy = uF[2][0] & uF[3][0];
+          s23[0] = uF[2][0] ^ uF[3][0];
+          s23[1] = xor3(uF[2][1], uF[3][1], cy);
+          cy = maj3(uF[2][1], uF[3][1], cy);
+          s23[2] = xor3(uF[2][2], uF[3][2], cy);
+          s23[3] = maj3(uF[2][2], uF[3][2], cy);
+          cy = s01[0] & s23[0];
+          su[0] = s01[0] ^ s23[0];
+#pragma unroll
+          for (int q = 1; q < 4; ++q) {
+            su[q] = xor3(s01[q], s23[q], cy);
+            cy = maj3(s01[q], s23[q], cy);
+          }
+          su[4] = cy;
+        }
+        slice_add_n(AN, nf);
+        slice_add_n(AU, su);
+#pragma unroll
+        for (int h = 0; h < P; ++h) {
+          __builtin_amdgcn_sched_barrier(0);
+          const int g = gb + h;
+          if (g < g1) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const uint32_t e = (S[j] ^ F[j]) >> (h * W);
+              lds_store<Pair>(own_addr(g, j), msc4_pair<W>(e));
+            }
+          }
+        }
+      }
+      if (c == C - 1) {
+        // the sweep's totals, summed over the wave bit-sliced; lane q < 32
+        // reads bit q, which belongs to replica q mod W
+        if (__builtin_amdgcn_ballot_w64(worked) != 0) {
+          uint32_t ZN[kMsc4NPlanes + 6], ZU[kMsc4UPlanes + 6];
+#pragma unroll
+          for (int p = 0; p < kMsc4NPlanes + 6; ++p) ZN[p] = p < kMsc4NPlanes ? AN[p] : 0u;
+#pragma unroll
+          for (int p = 0; p < kMsc4UPlanes + 6; ++p) ZU[p] = p < kMsc4UPlanes ? AU[p] : 0u;
+          slice_wave_sum<kMsc4NPlanes>(ZN);
+          slice_wave_sum<kMsc4UPlanes>(ZU);
+          if (lane < 32) {
+            const int n = slice_value(ZN, lane), us = slice_value(ZU, lane);
+            if (n != 0) {
+              atomicAdd(&sh.dN[t % 3][lane & (W - 1)], n);
+              atomicAdd(&sh.dE[t % 3][lane & (W - 1)], 8 * n - 4 * us);
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // end of sweep t: every wave keeps the unit's per-replica scalars in its
+    // lanes 0 .. W-1
+    bool imp = false;
+    if (lane < W) {
+      E_r += sh.dE[t % 3][lane];
+      acc_r += (unsigned long long)sh.dN[t % 3][lane];
+      const int cut = (J.W - E_r) / 2;
+      imp = lane < live && cut > best_cut_r;
+      if (imp) {
+        best_cut_r = cut;
+        best_sweep_r = t;
+      }
+    }
+    snapW = (uint32_t)__builtin_amdgcn_ballot_w64(imp) & WM;
+    if (tid < W) {
+      sh.dE[(t + 2) % 3][tid] = 0;
+      sh.dN[(t + 2) % 3][tid] = 0;
+    }
+    if ((J.flags & kJobTrace) && tid < live) J.trace[(int64_t)t * J.R + r0 + tid] = E_r;
+  }
+
+  // ---- state out, and the snapshot of the last sweep when it improved
+  for (int g = tid; g < n_grp; g += BLOCK) {
+    const int cnt = (J.grp[g] >> kGroupCountShift) + 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t e = lds_load<E>(own_addr(g, j));
+      const int64_t o = msc4_word_byte(r0, n_pad, 4 * g + j);
+      if (snapW && j < cnt) {
+        GLOBAL_AS E* bp = (GLOBAL_AS E*)(bestb + o);
+        *bp = (E)(((uint32_t)*bp & ~snapW) | (e & snapW));
+      }
+      if (J.save) *(GLOBAL_AS E*)(saveb + o) = (E)e;
+    }
+  }
+  if (tid < live) {
+    J.accepts[r0 + tid] = acc_r;
+    J.energy[r0 + tid] = E_r;
+    J.best_cut[r0 + tid] = best_cut_r;
+    J.best_sweep[r0 + tid] = best_sweep_r;
+  }
+}
+
+template <int BLOCK, int W>
+__global__ void __launch_bounds__(BLOCK)
+k_msc4(const JobDev* __restrict__ jobs, const int2* __restrict__ units,
+       const int32_t* __restrict__ list_off, int32_t* __restrict__ ctr) {
+  extern __shared__ __align__(16) uint32_t smem_m4[];
+  __shared__ Msc4Shared sh;
+  int tried = 0;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) sh.unit = next_unit(list_off, ctr, tried);
+    __syncthreads();
+    const int u = sh.unit;
+    if (u < 0) break;
+    const int2 un = units[u];
+    const JobDev J = jobs[un.x];  // by value: fields stay in registers
+    msc4_unit<BLOCK, W>(J, un.y, smem_m4, sh);
+  }
+}
+
 // ================================================================ utils
 // Argmax over replicas of each job: key = (best_cut + 2^31 mod 2^32) << 32
 // | ~r, so the largest key is the largest cut with the lowest replica index
@@ -1725,9 +2266,36 @@ const void* field_kernel(int adj) {
 
 template <int BLOCK>
 hipError_t launch_msc_t(const LaunchPersistent& L, hipStream_t s) {
-  hipLaunchKernelGGL(k_msc<BLOCK>, dim3(L.grid), dim3(BLOCK), L.lds_bytes, s, L.jobs,
-                     L.units, L.list_off, L.ctr, L.planes);
+  switch (L.width) {
+    case 0:
+      hipLaunchKernelGGL(k_msc<BLOCK>, dim3(L.grid), dim3(BLOCK), L.lds_bytes, s, L.jobs,
+                         L.units, L.list_off, L.ctr, L.planes);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_msc4<BLOCK, 8>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s, L.jobs,
+                         L.units, L.list_off, L.ctr);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_msc4<BLOCK, 16>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s, L.jobs,
+                         L.units, L.list_off, L.ctr);
+      break;
+    case 32:
+      hipLaunchKernelGGL((k_msc4<BLOCK, 32>), dim3(L.grid), dim3(BLOCK), L.lds_bytes, s, L.jobs,
+                         L.units, L.list_off, L.ctr);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+
+// The multispin kernel of a width (0 = the general form).
+template <int BLOCK>
+const void* msc_kernel(int width) {
+  return width == 8    ? (const void*)k_msc4<BLOCK, 8>
+         : width == 16 ? (const void*)k_msc4<BLOCK, 16>
+         : width == 32 ? (const void*)k_msc4<BLOCK, 32>
+                       : (const void*)k_msc<BLOCK>;
 }
 
 template <typename K>
@@ -1788,7 +2356,11 @@ hipError_t launch_msc(const LaunchPersistent& L, int block, hipStream_t s) {
   switch (block) {
     case 256: return launch_msc_t<256>(L, s);
     case 512: return launch_msc_t<512>(L, s);
-    default: return hipErrorInvalidValue;  // the multispin path runs 256 or 512 threads
+    case 1024:
+      // the general form runs 256 or 512 threads
+      if (L.width == 0) return hipErrorInvalidValue;
+      return launch_msc_t<1024>(L, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -1800,9 +2372,11 @@ int persistent_occupancy(int path, int block, int adj, size_t lds_bytes) {
       case 1024: return occupancy_of(field_kernel<1024>(adj), 1024, lds_bytes);
     }
   } else {
+    // adj: the multispin width (0 = the general form)
     switch (block) {
-      case 256: return occupancy_of(k_msc<256>, 256, lds_bytes);
-      case 512: return occupancy_of(k_msc<512>, 512, lds_bytes);
+      case 256: return occupancy_of(msc_kernel<256>(adj), 256, lds_bytes);
+      case 512: return occupancy_of(msc_kernel<512>(adj), 512, lds_bytes);
+      case 1024: return adj ? occupancy_of(msc_kernel<1024>(adj), 1024, lds_bytes) : 0;
     }
   }
   return 0;
@@ -1820,8 +2394,15 @@ hipError_t set_persistent_lds_limit(int path, int block, size_t lds_bytes) {
     f = block == 256 ? field_kernel<256>(kAdjHbm)
                      : block == 512 ? field_kernel<512>(kAdjHbm) : field_kernel<1024>(kAdjHbm);
   } else {
-    if (block != 256 && block != 512) return hipErrorInvalidValue;
-    f = block == 256 ? (const void*)k_msc<256> : (const void*)k_msc<512>;
+    if (block != 256 && block != 512 && block != 1024) return hipErrorInvalidValue;
+    for (int w : {0, 8, 16, 32}) {
+      if (block == 1024 && w == 0) continue;  // the general form has no 1024-thread kernel
+      const void* k = block == 256 ? msc_kernel<256>(w)
+                                   : block == 512 ? msc_kernel<512>(w) : msc_kernel<1024>(w);
+      hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
   return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }

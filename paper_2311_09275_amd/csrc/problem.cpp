@@ -348,6 +348,31 @@ int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, cons
         }
       }
     }
+    // The multispin degree-4 form keeps every state element next to its
+    // complement (element 2 i + 1 = NOT element 2 i), so that an entry can
+    // name the copy that already carries its edge's sign: entry (j, e) is
+    // 2 tile_word(neighbour) + (w > 0), and the element read there XOR the
+    // vertex's own element is the bond's "unsatisfied" mask (w s_v s_u = +1).
+    if (2 * field_state_words(g.n_pad) <= (1 << 16)) {
+      g.adj4m.assign((size_t)kDeg4MscBlockWords * ng, 0u);
+      for (size_t q = 0; q < ng; ++q) {
+        uint32_t* blk = g.adj4m.data() + (size_t)kDeg4MscBlockWords * q;
+        for (int j = 0; j < 4; ++j) {
+          const int32_t i = g.orig[4 * q + (size_t)j];
+          if (i < 0) continue;  // padding slot: its flips are masked off
+          for (int e = 0; e < 4; ++e) {
+            const int32_t nbr = lab[4 * (size_t)i + e];
+            const uint32_t pos = (uint32_t)g.pos[(size_t)nbr];
+            int32_t we = 0;
+            for (int32_t a = deg[(size_t)i]; a < deg[(size_t)i + 1]; ++a)
+              if (nb[(size_t)a] == nbr) we = nw[(size_t)a];
+            const uint32_t ent = 2u * (uint32_t)tile_word((int)(pos >> 2), (int)(pos & 3u)) +
+                                 (we > 0 ? 1u : 0u);
+            blk[2 * j + e / 2] |= ent << (16 * (e & 1));
+          }
+        }
+      }
+    }
   }
   g.fields = false;
   g.bpos.assign((size_t)g.n_pad, 0);

@@ -134,6 +134,9 @@ struct HostGraph {
   // indices of the tiled state layout (tile_word)
   std::vector<uint32_t> adj4;
   std::vector<int32_t> lab4;  // [4n] neighbours in label order, with adj4
+  // the multispin degree-4 form's blocks (kDeg4MscBlockWords), with adj4
+  // when twice the tiled state has at most 2^16 elements
+  std::vector<uint32_t> adj4m;
 };
 
 int compile_graph(int32_t n, int64_t m, const int32_t* u, const int32_t* v, const int32_t* w,
@@ -160,6 +163,7 @@ struct DevGraph {
           *pos = nullptr, *gbase = nullptr;
   uint32_t *adjm = nullptr, *gdeg = nullptr;
   uint32_t* adj4 = nullptr;
+  uint32_t* adj4m = nullptr;
   int2* aw = nullptr;
   int32_t* bf = nullptr;  // [n_pad] local fields, position order
 };

@@ -27,7 +27,19 @@ PATHS = {
     "field_g1_b512_auto": B.Tuning(B.PATH_FIELD, 1, 512, 0),
     "msc_g1_b256": B.Tuning(B.PATH_MSC, 1, 256, 0),
     "msc_g2_b512": B.Tuning(B.PATH_MSC, 2, 512, 0),
+    # the multispin degree-4 form: 8, 16 or 32 replicas per unit
+    "msc4_w8_b256": B.Tuning(B.PATH_MSC, 8, 256, 0),
+    "msc4_w16_b512": B.Tuning(B.PATH_MSC, 16, 512, 0),
+    "msc4_w32_b1024": B.Tuning(B.PATH_MSC, 32, 1024, 0),
+    "msc4_w8_b1024": B.Tuning(B.PATH_MSC, 8, 1024, 0),
 }
+DEG4_ONLY = {"field_g1_b512_hbmdeg4", "msc4_w8_b256", "msc4_w16_b512", "msc4_w32_b1024",
+             "msc4_w8_b1024"}
+
+
+def _needs_deg4(tuning):
+    return tuning is not None and (tuning.lds_adjacency == 4 or
+                                   (tuning.path == B.PATH_MSC and tuning.replicas_per_block >= 8))
 
 
 def _sched(kind, S, b0, b1, betas=None):
@@ -40,10 +52,10 @@ def compare(inst, S, R, seed, kind=O.LINEAR, b0=0.1, b1=3.0, betas=None, tuning=
             init=None, replicas=None, trace=True, colour=None):
     """Run the GPU path and check it against the oracle on `replicas`."""
     n = inst.n
-    if tuning is not None and tuning.lds_adjacency == 4:
+    if _needs_deg4(tuning):
         deg = np.bincount(np.concatenate([inst.u, inst.v]), minlength=n)
         if n == 0 or not (deg == 4).all() or not (np.abs(inst.w) == 1).all():
-            pytest.skip("the degree-4 form needs a 4-regular unit-weight graph")
+            pytest.skip("the degree-4 forms need a 4-regular unit-weight graph")
     sched, okw = _sched(kind, S, b0, b1, betas)
     p = B.Problem.from_instance(inst, colour)
     if init is not None:
@@ -95,7 +107,7 @@ def test_odd_torus_ragged_classes(path):
     compare(I.torus(7, 9, 5), 150, 40, 77, kind=O.GEOMETRIC, b0=0.2, b1=4.0, tuning=PATHS[path])
 
 
-NOT_DEG4 = [p for p in PATHS if p != "field_g1_b512_hbmdeg4"]
+NOT_DEG4 = [p for p in PATHS if p not in DEG4_ONLY]
 
 
 @pytest.mark.parametrize("path", NOT_DEG4)
@@ -331,3 +343,14 @@ def test_schedule_and_table_reuse_across_anneals():
         np.testing.assert_array_equal(got, B.ising_cut(q.handle, R)[2])
         q.close()
     p.close()
+
+
+@pytest.mark.parametrize("path", sorted(DEG4_ONLY - {"field_g1_b512_hbmdeg4"}))
+def test_msc4_small_shapes(path):
+    """The multispin degree-4 form on the smallest torus (3 classes of
+    3 vertices, one sweep, one replica), on replica counts that leave the
+    last unit partly empty, and on a torus whose groups span two tiles."""
+    compare(I.torus(3, 3, 1), 1, 1, 3, tuning=PATHS[path])
+    compare(I.torus(3, 5, 2), 20, 5, 4, tuning=PATHS[path])
+    compare(I.torus(4, 4, 3), 30, 33, 5, kind=O.GEOMETRIC, b0=0.1, b1=4.0, tuning=PATHS[path])
+    compare(I.torus(34, 30, 4), 40, 9, 6, kind=O.GEOMETRIC, b0=0.1, b1=4.0, tuning=PATHS[path])
