@@ -396,11 +396,22 @@ static uint64_t splitmix64(uint64_t* x) {
  * no two vertices are adjacent and every draw is keyed by its own vertex, so
  * the order cannot change the result).  tq[k] for k = 1..kmax holds the
  * sweep's thresholds.  Updates s, h, E and the counters. */
+/* Measurement tallies of a sweep (all optional; they never change the
+ * sweep): attempts whose acceptance a draw decides, and distinct
+ * neighbours whose field a colour pass changed (touched_at[j] holds the
+ * last pass that changed h_j). */
+typedef struct {
+  int64_t* tests;
+  int64_t* touched;
+  int64_t* touched_at;
+} sweep_tally;
+
 static void sweep_once(const or_graph* G, uint64_t seed, int32_t t, int32_t r,
                        const uint64_t* tq, int8_t* s, int64_t* h, int64_t* E,
                        int64_t* accepts, int64_t* draws, int32_t* drawn_at,
-                       int32_t* order, uint64_t* shuf) {
+                       int32_t* order, uint64_t* shuf, const sweep_tally* tally) {
   for (int32_t c = 0; c < G->n_colours; ++c) {
+    const int64_t pass = (int64_t)t * G->n_colours + c;
     const int32_t lo = G->class_start[c], hi = G->class_start[c + 1];
     for (int32_t idx = lo; idx < hi; ++idx) order[idx - lo] = G->members[idx];
     if (shuf) {
@@ -429,13 +440,19 @@ static void sweep_once(const or_graph* G, uint64_t seed, int32_t t, int32_t r,
           drawn_at[G->run[i]] = t;
           ++*draws;
         }
+        if (tally && tally->tests && tq[k] != 0 && tq[k] != ((uint64_t)1 << 32)) ++*tally->tests;
       }
       if (accept) {
         s[i] = (int8_t)-s[i];
         *E += 2 * k;
         ++*accepts;
-        for (int32_t a = G->row[i]; a < G->row[i + 1]; ++a)
+        for (int32_t a = G->row[i]; a < G->row[i + 1]; ++a) {
           h[G->nbr[a]] -= 2 * (int64_t)G->wt[a] * s[i];
+          if (tally && tally->touched && tally->touched_at[G->nbr[a]] != pass) {
+            tally->touched_at[G->nbr[a]] = pass;
+            ++*tally->touched;
+          }
+        }
       }
     }
   }
@@ -472,8 +489,21 @@ static void run_replica(worker_arg* A, int32_t r, int8_t* s, int64_t* h,
   int64_t E = energy_from_scratch(G, s);
   int64_t best_cut = (G->W - E) / 2;
   int32_t best_sweep = -1;
-  int64_t accepts = 0, draws = 0, improvements = 0;
+  int64_t accepts = 0, draws = 0, improvements = 0, tests = 0, touched = 0;
   for (int32_t i = 0; i < n; ++i) drawn_at[i] = -1;
+  sweep_tally tally = {NULL, NULL, NULL};
+  int64_t* touched_at = NULL;
+  if (out->tests || out->touched) {
+    tally.tests = out->tests ? &tests : NULL;
+    if (out->touched) {
+      touched_at = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+      if (touched_at) {
+        for (int32_t i = 0; i < n; ++i) touched_at[i] = -1;
+        tally.touched = &touched;
+        tally.touched_at = touched_at;
+      }
+    }
+  }
   if (out->best_state) memcpy(out->best_state + slot * n, s, (size_t)n);
   uint64_t shuf = run->shuffle_seed ^ ((uint64_t)r * 0x632BE59BD9B4E019ull);
 
@@ -481,7 +511,7 @@ static void run_replica(worker_arg* A, int32_t r, int8_t* s, int64_t* h,
     const double beta = A->betas[t];
     for (int64_t k = 1; k <= kmax; ++k) tq[k] = oracle_threshold(beta, k);
     sweep_once(G, run->seed, t, r, tq, s, h, &E, &accepts, &draws, drawn_at, order,
-               run->shuffle_seed ? &shuf : NULL);
+               run->shuffle_seed ? &shuf : NULL, (out->tests || out->touched) ? &tally : NULL);
     /* End of sweep: the best is taken over end-of-sweep states only, strict
      * improvement, so the earliest sweep reaching a value keeps it. */
     int64_t cut = (G->W - E) / 2;
@@ -505,6 +535,9 @@ static void run_replica(worker_arg* A, int32_t r, int8_t* s, int64_t* h,
   out->final_energy[slot] = E;
   if (out->draws) out->draws[slot] = draws;
   if (out->improvements) out->improvements[slot] = improvements;
+  if (out->tests) out->tests[slot] = tests;
+  if (out->touched) out->touched[slot] = touched;
+  free(touched_at);
   if (out->final_state) memcpy(out->final_state + slot * n, s, (size_t)n);
   if (out->final_field)
     for (int32_t i = 0; i < n; ++i) out->final_field[slot * n + i] = (int32_t)h[i];
@@ -751,7 +784,8 @@ static void temper_group(temper_arg* A, int32_t set0, int32_t ns, const temper_s
       int8_t* sj = s + (int64_t)j * n;
       for (int32_t i = 0; i < n; ++i) W->drawn_at[i] = -1;
       sweep_once(G, pt->seed, t, (int32_t)(r0 + j), W->tq + (int64_t)temp[j] * (kmax + 1), sj,
-                 h + (int64_t)j * n, &E[j], &accepts[j], &draws, W->drawn_at, W->order, NULL);
+                 h + (int64_t)j * n, &E[j], &accepts[j], &draws, W->drawn_at, W->order, NULL,
+                 NULL);
       const int64_t cut = (G->W - E[j]) / 2;
       if (cut > best_cut[j]) {
         best_cut[j] = cut;

@@ -70,6 +70,11 @@ typedef struct { /* per-replica arrays are indexed by r - r_begin */
   int64_t* draws;        /* [nr] or NULL: distinct Philox blocks the sweeps
                             needed, i.e. (t, run, r) with a draw */
   int64_t* improvements; /* [nr] or NULL: sweeps that raised the best cut */
+  /* measurement tallies (test infrastructure; NULL = not counted): */
+  int64_t* tests;        /* [nr] attempts whose acceptance a draw decided
+                            (k > 0 and 0 < Tq < 2^32) */
+  int64_t* touched;      /* [nr] distinct neighbours whose field a colour
+                            pass changed, summed over passes */
 } or_run_out;
 
 /* Philox4x32-10 block function (Salmon et al., SC'11). */

@@ -69,7 +69,8 @@ class _RunOut(C.Structure):
                 ("best_state", C.c_void_p), ("final_state", C.c_void_p),
                 ("final_field", C.c_void_p), ("energy_trace", C.c_void_p),
                 ("check_failures", C.c_int64), ("draws", C.c_void_p),
-                ("improvements", C.c_void_p)]
+                ("improvements", C.c_void_p), ("tests", C.c_void_p),
+                ("touched", C.c_void_p)]
 
 
 _lib = None
@@ -198,6 +199,8 @@ class Result:
     r_begin: int
     draws: np.ndarray         # int64 [nr] Philox blocks needed by the sweeps
     improvements: np.ndarray  # int64 [nr] sweeps that raised the best cut
+    tests: np.ndarray | None = None    # int64 [nr] attempts a draw decided
+    touched: np.ndarray | None = None  # int64 [nr] distinct fields changed per pass, summed
 
     def argmax(self) -> int:
         """Replica with the largest best cut, lowest index on ties."""
@@ -208,7 +211,10 @@ def anneal(inst, n_sweeps, n_replicas, seed, kind=LINEAR, beta0=0.1,
            beta1=3.0, betas=None, colour=None, init_spins=None,
            r_begin=0, r_end=None, n_threads=1, check=False,
            shuffle_seed=0, want_states=True, want_trace=False,
-           want_field=False) -> Result:
+           want_field=False, want_tally=False) -> Result:
+    """The anneal of replicas [r_begin, r_end).  want_tally adds the
+    measurement tallies (attempts decided by a draw, distinct fields
+    changed per colour pass); they do not change the run."""
     r_end = n_replicas if r_end is None else r_end
     nr = r_end - r_begin
     n = inst.n
@@ -228,15 +234,17 @@ def anneal(inst, n_sweeps, n_replicas, seed, kind=LINEAR, beta0=0.1,
     trace = np.zeros((nr, n_sweeps), np.int64) if want_trace else None
     draws = np.zeros(nr, np.int64)
     impr = np.zeros(nr, np.int64)
+    tests = np.zeros(nr, np.int64) if want_tally else None
+    touched = np.zeros(nr, np.int64) if want_tally else None
     out = _RunOut(_p(best_cut), _p(best_sweep), _p(accepts), _p(energy),
                   _p(best_state), _p(final_state), _p(final_field), _p(trace), 0,
-                  _p(draws), _p(impr))
+                  _p(draws), _p(impr), _p(tests), _p(touched))
     rc = lib().oracle_anneal(C.byref(g), C.byref(run), C.byref(out))
     if rc != 0:
         raise ValueError("oracle rejected the input")
     return Result(best_cut, best_sweep, accepts, energy, best_state,
                   final_state, final_field, trace, int(out.check_failures),
-                  r_begin, draws, impr)
+                  r_begin, draws, impr, tests, touched)
 
 
 @dataclass
