@@ -529,6 +529,14 @@ int ising_server_destroy(ising_server* srv);
  * ISING_ERR_DEVICE.
  */
 int ising_valu_rates(double* rates);
+/*
+ * Measurement helper for the roofline, not part of the method: LDS read
+ * bandwidth of the current device in bytes per second, from conflict-free
+ * 16-byte reads (ds_read_b128) of every lane, four 256-thread workgroups
+ * per CU.  Synchronous; takes a small temporary device buffer.  Errors:
+ * ISING_ERR_INVALID (bytes_per_s NULL), ISING_ERR_DEVICE.
+ */
+int ising_lds_rate(double* bytes_per_s);
 
 #ifdef __cplusplus
 }

@@ -147,6 +147,7 @@ _sig = {
     "ising_server_stats": ([P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)], C.c_int),
     "ising_server_destroy": ([P], C.c_int),
     "ising_valu_rates": ([P], C.c_int),
+    "ising_lds_rate": ([C.POINTER(C.c_double)], C.c_int),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_L, _name)
@@ -378,6 +379,13 @@ def ising_valu_rates() -> dict:
     _check(_L.ising_valu_rates(_ptr(out)), "ising_valu_rates")
     return dict(zip(VALU_RATE_NAMES, (float(x) for x in out)))
 
+
+
+def ising_lds_rate() -> float:
+    """LDS read bandwidth of the current device, bytes/s (ising_lds_rate)."""
+    out = C.c_double()
+    _check(_L.ising_lds_rate(C.byref(out)), "ising_lds_rate")
+    return out.value
 
 def ising_autotune(handles, sched: Schedule, n_replicas, prefix_sweeps=0, stream=None) -> Tuning:
     hs = (C.c_void_p * len(handles))(*handles)

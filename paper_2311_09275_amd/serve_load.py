@@ -36,10 +36,16 @@ def run(rate: float = 50.0, n_requests: int = 1000, seed: int = 7, budget: int =
     insts = [mk() for _, mk in SHAPES]
     probs = [B.Problem.from_instance(x) for x in insts]
     sched = B.Schedule.make(B.LINEAR, sweeps, 0.1, 3.0)
-    # reference best of each instance: 1024 replicas, 5x the request's sweeps
-    # (512-thread blocks, so these dispatches are told apart in profiles)
+    # reference best of each instance: the stored calibration, else a
+    # longer anneal (1024 replicas, 5x the request's sweeps)
+    from . import reference_cuts as RC
+    stored = RC.load()
     refs = []
-    for p in probs:
+    for (name, _), p in zip(SHAPES, probs):
+        key = "serve_" + name.replace(" ", "").replace("/", "_")
+        if key in stored:
+            refs.append(stored[key])
+            continue
         p.anneal(B.Schedule.make(B.LINEAR, 5 * sweeps, 0.1, 3.0), 1024, 99,
                  B.Tuning(B.PATH_FIELD, 1, 512, 2), stream=stream)
         refs.append(p.cut().best_cut)
@@ -66,6 +72,7 @@ def run(rate: float = 50.0, n_requests: int = 1000, seed: int = 7, budget: int =
 
     lat = np.array([r.t_done - r.t_submit for _, r in results])
     wait = np.array([r.t_admit - r.t_submit for _, r in results])
+    footprint = [B.ising_server_footprint(p.handle, sched, replicas) for p in probs]
     attempts = sum(insts[k].n * replicas * r.sweeps_done for k, r in results)
     reached = np.mean([r.reached_target for _, r in results])
     for p in probs:
@@ -77,24 +84,33 @@ def run(rate: float = 50.0, n_requests: int = 1000, seed: int = 7, budget: int =
         "requests": n_requests, "wall_s": wall,
         "requests_per_s": n_requests / wall, "attempts_per_s": attempts / wall,
         "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
-        "latency_mean_s": float(lat.mean()), "admission_wait_p99_s": float(np.percentile(wait, 99)),
+        "latency_mean_s": float(lat.mean()), "admission_wait_p50_s": float(np.percentile(wait, 50)),
+        "admission_wait_p99_s": float(np.percentile(wait, 99)),
+        "admitted_after_waiting_fraction": float(np.mean(wait > 1e-3)),
+        "footprint_bytes": {"min": int(min(footprint)), "max": int(max(footprint))},
         "target_reached_fraction": float(reached), "mean_sweeps": float(np.mean([r.sweeps_done for _, r in results])),
         "hbm_budget_bytes": budget, "slots": slots, "chunk_sweeps": chunk,
         "server_steps": steps, "peak_resident": peak,
         "offered_attempts_per_s": rate * float(np.mean([x.n for x in insts])) * replicas * sweeps,
+        "references": refs,
     }
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--rates", default=None, help="comma-separated rates: one JSON line each")
     ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--budget-mb", type=int, default=256)
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--chunk", type=int, default=50)
     args = ap.parse_args()
-    print(json.dumps(run(args.rate, args.requests, budget=args.budget_mb << 20, slots=args.slots,
-                         chunk=args.chunk)))
+    import torch
+    stream = torch.cuda.Stream()
+    rates = [args.rate] if args.rates is None else [float(x) for x in args.rates.split(",")]
+    for rate in rates:
+        print(json.dumps(run(rate, args.requests, budget=args.budget_mb << 20, slots=args.slots,
+                             chunk=args.chunk, stream=stream)), flush=True)
 
 
 if __name__ == "__main__":

@@ -90,3 +90,17 @@ def test_cut_matches_oracle_and_library(oracle_lib):
 def test_rejects(text):
     with pytest.raises(ValueError):
         gset.read_gset(io.StringIO(text))
+
+
+def test_stored_reference_cuts_cover_every_benchmark_instance():
+    """Every instance the benchmark measures has a stored reference cut, and
+    each lies above half the total weight (a uniformly random cut's
+    expectation) and at most the sum of the positive weights (no cut does
+    better than cutting every positive edge and no negative one)."""
+    from paper_2311_09275_amd import reference_cuts as RC
+    cuts = RC.load()
+    insts = RC.named_instances()
+    assert set(cuts) == set(insts)
+    for name, inst in insts.items():
+        w = inst.w.astype(np.int64)
+        assert w.sum() / 2 < cuts[name] <= w[w > 0].sum(), (name, cuts[name])
