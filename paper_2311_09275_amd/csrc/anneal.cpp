@@ -664,16 +664,39 @@ int plan_persistent(const std::vector<JobSpec>& specs, const PersistentConfig& c
     set_error("batch does not fit the LDS budget");
     return ISING_ERR_UNSUPPORTED;
   }
-  // longest processing time first, over eight lists (one per XCD)
+  // Longest processing time first, over eight lists (one per XCD).  With
+  // many jobs, all units of a job go to one list, so that its graph and
+  // tables are read through one XCD's L2 only (the lists are balanced by
+  // job); with few jobs the units spread over all lists.
   std::stable_sort(all.begin(), all.end(), [](const U& a, const U& b) { return a.cost > b.cost; });
   std::vector<std::vector<int2>> lists(8);
   double load[8] = {0};
-  for (const U& u : all) {
+  auto least = [&]() {
     int best = 0;
     for (int i = 1; i < 8; ++i)
       if (load[i] < load[best]) best = i;
-    load[best] += u.cost;
-    lists[(size_t)best].push_back(make_int2(u.job, u.block));
+    return best;
+  };
+  if (n_jobs >= 16) {
+    std::vector<double> job_cost((size_t)n_jobs, 0.0);
+    for (const U& u : all) job_cost[(size_t)u.job] += u.cost;
+    std::vector<int> order((size_t)n_jobs);
+    for (int j = 0; j < n_jobs; ++j) order[(size_t)j] = j;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return job_cost[(size_t)a] > job_cost[(size_t)b]; });
+    std::vector<int> list_of((size_t)n_jobs, 0);
+    for (int j : order) {
+      const int best = least();
+      load[best] += job_cost[(size_t)j];
+      list_of[(size_t)j] = best;
+    }
+    for (const U& u : all) lists[(size_t)list_of[(size_t)u.job]].push_back(make_int2(u.job, u.block));
+  } else {
+    for (const U& u : all) {
+      const int best = least();
+      load[best] += u.cost;
+      lists[(size_t)best].push_back(make_int2(u.job, u.block));
+    }
   }
   std::vector<int2>& units = P.units;
   units.clear();

@@ -1515,6 +1515,9 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
   constexpr int P = 32 / W;
   constexpr uint32_t WM = W == 32 ? 0xFFFFFFFFu : (1u << (W & 31)) - 1u;
   const int tid = threadIdx.x, lane = tid & 63;
+  // a step of wave w covers groups [64 P w, 64 P (w + 1)) of its range:
+  // lane l takes groups 64 P w + l + 64 h, h < P
+  const int lane_base = (tid >> 6) * 64 * P + lane;
   const int r0 = block * W;
   const int live = min(W, J.R - r0);
   const int n_pad = J.n_pad, n_grp = n_pad >> 2;
@@ -1562,19 +1565,21 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
   stage_row_chunk(J.tqb, J.t_begin, min(CH, J.t_end - J.t_begin), rows, kBondRowWords);
   __syncthreads();
 
-  // Packed state of the lane's groups g_h = gb + h (h < P): own elements
-  // S[j], unsatisfied masks D[j][e], real slots V[j].  cnt_of(g) is the
-  // group's slot count, 0 past the end of its range; such a group reads
-  // group gb's data (every access stays valid) and V masks it off.  All
-  // adjacency loads are issued before any element is read.
+  // Packed state of the lane's groups g_h = gb + 64 h (h < P): own
+  // elements S[j], unsatisfied masks D[j][e], real slots V[j].  A wave's
+  // lanes take 64 consecutive groups per h, so they touch consecutive
+  // elements of one tile.  cnt_of(g) is the group's slot count, 0 past the
+  // end of its range; such a group reads group gb's data (every access
+  // stays valid) and V masks it off.  All adjacency loads are issued before
+  // any element is read.
   uint32_t S[4], V[4], D[4][4];
   auto gather = [&](int gb, auto cnt_of) {
     u32x4 a[P][2];
     int gs[P];
 #pragma unroll
     for (int h = 0; h < P; ++h) {
-      const int cnt = cnt_of(gb + h);
-      gs[h] = cnt > 0 ? gb + h : gb;
+      const int cnt = cnt_of(gb + 64 * h);
+      gs[h] = cnt > 0 ? gb + 64 * h : gb;
 #pragma unroll
       for (int j = 0; j < 4; ++j) V[j] = (h == 0 ? 0u : V[j]) | ((j < cnt ? WM : 0u) << (h * W));
       a[h][0] = am[2 * gs[h]];
@@ -1623,7 +1628,7 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
     uint32_t AU[kMsc4UPlanes + 6];  // the top six planes take the wave sum's carries
 #pragma unroll
     for (int p = 0; p < kMsc4UPlanes + 6; ++p) AU[p] = 0u;
-    for (int gb = P * tid; gb < n_grp; gb += P * BLOCK) {
+    for (int gb = lane_base; gb < n_grp; gb += P * BLOCK) {
       gather(gb, [&](int g) { return g < n_grp ? (J.grp[g] >> kGroupCountShift) + 1 : 0; });
       uint32_t u[4][3];
 #pragma unroll
@@ -1677,7 +1682,7 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
     for (int c = 0; c < C; ++c) {
       const int g0 = J.cls[2 * c], g1 = J.cls[2 * c + 1];
       const int cnt_last = g1 > g0 ? (J.grp[g1 - 1] >> kGroupCountShift) + 1 : 0;
-      for (int gb = g0 + P * tid; gb < g1; gb += P * BLOCK) {
+      for (int gb = g0 + lane_base; gb < g1; gb += P * BLOCK) {
         worked = true;
         // draws of the lane's groups, compared with both thresholds; they do
         // not depend on the state, so they come first, four independent
@@ -1687,7 +1692,7 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
         if (need4) {
 #pragma unroll
           for (int h = P - 1; h >= 0; --h) {
-            const uint32_t g = (uint32_t)(gb + h);
+            const uint32_t g = (uint32_t)(gb + 64 * h);
             for (int b = W - 1; b >= 0; b -= 4) {
               uint4 x[4];
 #pragma unroll
@@ -1704,7 +1709,7 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
         } else if (need2) {
 #pragma unroll
           for (int h = P - 1; h >= 0; --h) {
-            const uint32_t g = (uint32_t)(gb + h);
+            const uint32_t g = (uint32_t)(gb + 64 * h);
             for (int b = W - 1; b >= 0; b -= 4) {
               uint4 x[4];
 #pragma unroll
@@ -1722,7 +1727,7 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
           // no registers to the unrolled visit)
 #pragma unroll 1
           for (int h = 0; h < P; ++h) {
-            const int g = gb + h;
+            const int g = gb + 64 * h;
             if (g < g1) {
               GLOBAL_AS E* bp = (GLOBAL_AS E*)(bestb + msc4_word_byte(r0, n_pad, 4 * g));
 #pragma unroll
@@ -1780,7 +1785,7 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
 #pragma unroll
         for (int h = 0; h < P; ++h) {
           __builtin_amdgcn_sched_barrier(0);
-          const int g = gb + h;
+          const int g = gb + 64 * h;
           if (g < g1) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
