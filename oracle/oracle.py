@@ -15,7 +15,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ising_oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# ISING_ORACLE_LIB names another build of ising_oracle.c (the sanitizer run)
+LIB = os.environ.get("ISING_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 LINEAR, GEOMETRIC, EXPLICIT = 0, 1, 2
 

@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libising.so")
+# ISING_LIB names another build of the same sources (the host-sanitizer run)
+LIB_PATH = os.environ.get("ISING_LIB") or os.path.join(HERE, "libising.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
