@@ -66,6 +66,40 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
   return make_uint4(c0, c1, c2, c3);
 }
 
+// NB blocks of counters (c0, c1, c2[b], c3) under one key, computed round
+// by round across the blocks: NB independent dependency chains in flight.
+template <int NB>
+__device__ __forceinline__ void philox10_n(uint32_t c0, uint32_t c1, const uint32_t (&c2)[NB],
+                                           uint32_t c3, uint32_t k0, uint32_t k1,
+                                           uint4 (&out)[NB]) {
+  uint32_t a0[NB], a1[NB], a2[NB], a3[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    a0[b] = c0;
+    a1[b] = c1;
+    a2[b] = c2[b];
+    a3[b] = c3;
+  }
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const uint64_t p0 = (uint64_t)kPhiloxM0 * a0[b];
+      const uint64_t p1 = (uint64_t)kPhiloxM1 * a2[b];
+      const uint32_t n0 = i < 3 ? (uint32_t)(p1 >> 32) ^ a1[b] ^ k0 : xor3((uint32_t)(p1 >> 32), a1[b], k0);
+      const uint32_t n2 = i < 3 ? (uint32_t)(p0 >> 32) ^ a3[b] ^ k1 : xor3((uint32_t)(p0 >> 32), a3[b], k1);
+      a1[b] = (uint32_t)p1;
+      a3[b] = (uint32_t)p0;
+      a0[b] = n0;
+      a2[b] = n2;
+    }
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) out[b] = make_uint4(a0[b], a1[b], a2[b], a3[b]);
+}
+
 // The block of a four-vertex group: counter (sweep, group ordinal,
 // replica, tag), key (seed low, seed high); the group's j-th vertex uses
 // word j.  The ordinal counts runs of four same-colour vertices in class
@@ -1515,9 +1549,14 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
   constexpr int P = 32 / W;
   constexpr uint32_t WM = W == 32 ? 0xFFFFFFFFu : (1u << (W & 31)) - 1u;
   const int tid = threadIdx.x, lane = tid & 63;
-  // a step of wave w covers groups [64 P w, 64 P (w + 1)) of its range:
-  // lane l takes groups 64 P w + l + 64 h, h < P
-  const int lane_base = (tid >> 6) * 64 * P + lane;
+  // a step covers P BLOCK groups of its range in slices of 64: slice
+  // h NW + w goes to wave w as its h-th, so lane l of wave w takes groups
+  // 64 (h NW + w) + l, h < P.  In a step that ends the range the waves'
+  // slices differ by at most one, and slices wholly past the end are
+  // skipped by the whole wave.
+  constexpr int NW = BLOCK / 64;
+  constexpr int HS = 64 * NW;  // group distance between a lane's slices
+  const int lane_base = (tid >> 6) * 64 + lane;
   const int r0 = block * W;
   const int live = min(W, J.R - r0);
   const int n_pad = J.n_pad, n_grp = n_pad >> 2;
@@ -1565,28 +1604,33 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
   stage_row_chunk(J.tqb, J.t_begin, min(CH, J.t_end - J.t_begin), rows, kBondRowWords);
   __syncthreads();
 
-  // Packed state of the lane's groups g_h = gb + 64 h (h < P): own
+  // Packed state of the lane's groups g_h = gb + HS h (h < P): own
   // elements S[j], unsatisfied masks D[j][e], real slots V[j].  A wave's
   // lanes take 64 consecutive groups per h, so they touch consecutive
   // elements of one tile.  cnt_of(g) is the group's slot count, 0 past the
   // end of its range; such a group reads group gb's data (every access
-  // stays valid) and V masks it off.  All adjacency loads are issued before
+  // stays valid) and V masks it off.  hn (wave-uniform, >= 1 for a lane
+  // with work) counts the wave's slices that reach into the range; the
+  // bits of the others stay zero.  All adjacency loads are issued before
   // any element is read.
   uint32_t S[4], V[4], D[4][4];
-  auto gather = [&](int gb, auto cnt_of) {
+  auto gather = [&](int gb, int hn, auto cnt_of) {
     u32x4 a[P][2];
     int gs[P];
 #pragma unroll
     for (int h = 0; h < P; ++h) {
-      const int cnt = cnt_of(gb + 64 * h);
-      gs[h] = cnt > 0 ? gb + 64 * h : gb;
+      if (h == 0 || h < hn) {
+        const int cnt = cnt_of(gb + HS * h);
+        gs[h] = cnt > 0 ? gb + HS * h : gb;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) V[j] = (h == 0 ? 0u : V[j]) | ((j < cnt ? WM : 0u) << (h * W));
-      a[h][0] = am[2 * gs[h]];
-      a[h][1] = am[2 * gs[h] + 1];
+        for (int j = 0; j < 4; ++j) V[j] = (h == 0 ? 0u : V[j]) | ((j < cnt ? WM : 0u) << (h * W));
+        a[h][0] = am[2 * gs[h]];
+        a[h][1] = am[2 * gs[h] + 1];
+      }
     }
 #pragma unroll
     for (int h = 0; h < P; ++h) {
+      if (h > 0 && h >= hn) break;
       // one group's reads at a time, so that few loaded elements are live
       __builtin_amdgcn_sched_barrier(0);
       const uint32_t ent[8] = {a[h][0].x, a[h][0].y, a[h][0].z, a[h][0].w,
@@ -1619,6 +1663,13 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
       for (int e = 0; e < 4; ++e) D[j][e] ^= S[j];
   };
 
+  // slices of the wave at step base gb (lane 0's group) that start before
+  // the end g1 of the range, at most P
+  auto slices_in = [&](int gb_lane0, int g1) {
+    const int left = g1 - gb_lane0;
+    return left <= 0 ? 0 : min(P, (left + HS - 1) / HS);
+  };
+
   // ---- initial energy: E = sum_p u_p - M (each unsatisfied bond counted at
   // both ends is 2 U, and E = 2 U - M)
   int E_r = 0, best_cut_r = 0, best_sweep_r = 0;
@@ -1629,7 +1680,8 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
 #pragma unroll
     for (int p = 0; p < kMsc4UPlanes + 6; ++p) AU[p] = 0u;
     for (int gb = lane_base; gb < n_grp; gb += P * BLOCK) {
-      gather(gb, [&](int g) { return g < n_grp ? (J.grp[g] >> kGroupCountShift) + 1 : 0; });
+      const int hn = slices_in(__builtin_amdgcn_readfirstlane(gb - lane), n_grp);
+      gather(gb, hn, [&](int g) { return g < n_grp ? (J.grp[g] >> kGroupCountShift) + 1 : 0; });
       uint32_t u[4][3];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -1684,6 +1736,7 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
       const int cnt_last = g1 > g0 ? (J.grp[g1 - 1] >> kGroupCountShift) + 1 : 0;
       for (int gb = g0 + lane_base; gb < g1; gb += P * BLOCK) {
         worked = true;
+        const int hn = slices_in(__builtin_amdgcn_readfirstlane(gb - lane), g1);
         // draws of the lane's groups, compared with both thresholds; they do
         // not depend on the state, so they come first, four independent
         // blocks at a time (bits are shifted in from the highest: group
@@ -1692,11 +1745,13 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
         if (need4) {
 #pragma unroll
           for (int h = P - 1; h >= 0; --h) {
-            const uint32_t g = (uint32_t)(gb + 64 * h);
+            if (h >= hn) continue;
+            const uint32_t g = (uint32_t)(gb + HS * h);
             for (int b = W - 1; b >= 0; b -= 4) {
               uint4 x[4];
-#pragma unroll
-              for (int i = 0; i < 4; ++i) x[i] = group_block(g, t, (uint32_t)(r0 + b - i), kTagSweep, k0, k1);
+              const uint32_t rs[4] = {(uint32_t)(r0 + b), (uint32_t)(r0 + b - 1), (uint32_t)(r0 + b - 2),
+                                      (uint32_t)(r0 + b - 3)};
+              philox10_n<4>(t, g, rs, kTagSweep, k0, k1, x);
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
                 shift_in4(A2, x[i], T2);
@@ -1709,25 +1764,27 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
         } else if (need2) {
 #pragma unroll
           for (int h = P - 1; h >= 0; --h) {
-            const uint32_t g = (uint32_t)(gb + 64 * h);
+            if (h >= hn) continue;
+            const uint32_t g = (uint32_t)(gb + HS * h);
             for (int b = W - 1; b >= 0; b -= 4) {
               uint4 x[4];
-#pragma unroll
-              for (int i = 0; i < 4; ++i) x[i] = group_block(g, t, (uint32_t)(r0 + b - i), kTagSweep, k0, k1);
+              const uint32_t rs[4] = {(uint32_t)(r0 + b), (uint32_t)(r0 + b - 1), (uint32_t)(r0 + b - 2),
+                                      (uint32_t)(r0 + b - 3)};
+              philox10_n<4>(t, g, rs, kTagSweep, k0, k1, x);
 #pragma unroll
               for (int i = 0; i < 4; ++i) shift_in4(A2, x[i], T2);
               __builtin_amdgcn_sched_barrier(0);
             }
           }
         }
-        gather(gb, [&](int g) { return g >= g1 ? 0 : g == g1 - 1 ? cnt_last : 4; });
+        gather(gb, hn, [&](int g) { return g >= g1 ? 0 : g == g1 - 1 ? cnt_last : 4; });
         // lazy best-state snapshot: these groups' end-of-last-sweep spins
         if (snap32) {
           // (rare after the first sweeps: a rolled loop, so that it adds
           // no registers to the unrolled visit)
 #pragma unroll 1
           for (int h = 0; h < P; ++h) {
-            const int g = gb + 64 * h;
+            const int g = gb + HS * h;
             if (g < g1) {
               GLOBAL_AS E* bp = (GLOBAL_AS E*)(bestb + msc4_word_byte(r0, n_pad, 4 * g));
 #pragma unroll
@@ -1785,7 +1842,7 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
 #pragma unroll
         for (int h = 0; h < P; ++h) {
           __builtin_amdgcn_sched_barrier(0);
-          const int g = gb + 64 * h;
+          const int g = gb + HS * h;
           if (g < g1) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
