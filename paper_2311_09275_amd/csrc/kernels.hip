@@ -66,15 +66,38 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
   return make_uint4(c0, c1, c2, c3);
 }
 
-// NB blocks of counters (c0, c1, c2[b], c3) under one key, computed round
-// by round across the blocks: NB independent dependency chains in flight.
-template <int NB>
-__device__ __forceinline__ void philox10_n(uint32_t c0, uint32_t c1, const uint32_t (&c2)[NB],
-                                           uint32_t c3, uint32_t k0, uint32_t k1,
-                                           uint4 (&out)[NB]) {
-  uint32_t a0[NB], a1[NB], a2[NB], a3[NB];
+// Eight 32x32->64 products p[2b] = m0 a[2b], p[2b+1] = m1 a[2b+1], issued
+// back to back: one statement, so that the eight independent chains of four
+// Philox blocks stay interleaved (the instruction scheduler would otherwise
+// order the blocks one after another, leaving a single wave waiting on
+// each product).  The carry-out SGPR pair of the instruction is unused.
+__device__ __forceinline__ void mul8_u64(uint64_t (&p)[8], const uint32_t (&a)[8], uint32_t m0,
+                                         uint32_t m1) {
+  uint64_t carry;
+  asm("v_mad_u64_u32 %0, %8, %9, %17, 0\n\t"
+      "v_mad_u64_u32 %1, %8, %10, %18, 0\n\t"
+      "v_mad_u64_u32 %2, %8, %11, %17, 0\n\t"
+      "v_mad_u64_u32 %3, %8, %12, %18, 0\n\t"
+      "v_mad_u64_u32 %4, %8, %13, %17, 0\n\t"
+      "v_mad_u64_u32 %5, %8, %14, %18, 0\n\t"
+      "v_mad_u64_u32 %6, %8, %15, %17, 0\n\t"
+      "v_mad_u64_u32 %7, %8, %16, %18, 0"
+      : "=&v"(p[0]), "=&v"(p[1]), "=&v"(p[2]), "=&v"(p[3]), "=&v"(p[4]), "=&v"(p[5]),
+        "=&v"(p[6]), "=&v"(p[7]), "=&s"(carry)
+      : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7]),
+        "s"(kPhiloxM0), "s"(kPhiloxM1));
+}
+
+// Four blocks of counters (c0, c1, c2[b], c3) under one key, computed round
+// by round across the blocks.  The first three rounds are left to the
+// compiler, which folds the products of words that are the same for the
+// whole wave; from the fourth round on every word differs per lane.
+__device__ __forceinline__ void philox10_x4(uint32_t c0, uint32_t c1, const uint32_t (&c2)[4],
+                                            uint32_t c3, uint32_t k0, uint32_t k1,
+                                            uint4 (&out)[4]) {
+  uint32_t a0[4], a1[4], a2[4], a3[4];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
+  for (int b = 0; b < 4; ++b) {
     a0[b] = c0;
     a1[b] = c1;
     a2[b] = c2[b];
@@ -82,10 +105,20 @@ __device__ __forceinline__ void philox10_n(uint32_t c0, uint32_t c1, const uint3
   }
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
+    uint64_t p[8];
+    if (i < 3) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const uint64_t p0 = (uint64_t)kPhiloxM0 * a0[b];
-      const uint64_t p1 = (uint64_t)kPhiloxM1 * a2[b];
+      for (int b = 0; b < 4; ++b) {
+        p[2 * b] = (uint64_t)kPhiloxM0 * a0[b];
+        p[2 * b + 1] = (uint64_t)kPhiloxM1 * a2[b];
+      }
+    } else {
+      const uint32_t in[8] = {a0[0], a2[0], a0[1], a2[1], a0[2], a2[2], a0[3], a2[3]};
+      mul8_u64(p, in, kPhiloxM0, kPhiloxM1);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const uint64_t p0 = p[2 * b], p1 = p[2 * b + 1];
       const uint32_t n0 = i < 3 ? (uint32_t)(p1 >> 32) ^ a1[b] ^ k0 : xor3((uint32_t)(p1 >> 32), a1[b], k0);
       const uint32_t n2 = i < 3 ? (uint32_t)(p0 >> 32) ^ a3[b] ^ k1 : xor3((uint32_t)(p0 >> 32), a3[b], k1);
       a1[b] = (uint32_t)p1;
@@ -97,7 +130,7 @@ __device__ __forceinline__ void philox10_n(uint32_t c0, uint32_t c1, const uint3
     k1 += kPhiloxW1;
   }
 #pragma unroll
-  for (int b = 0; b < NB; ++b) out[b] = make_uint4(a0[b], a1[b], a2[b], a3[b]);
+  for (int b = 0; b < 4; ++b) out[b] = make_uint4(a0[b], a1[b], a2[b], a3[b]);
 }
 
 // The block of a four-vertex group: counter (sweep, group ordinal,
@@ -1751,7 +1784,7 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
               uint4 x[4];
               const uint32_t rs[4] = {(uint32_t)(r0 + b), (uint32_t)(r0 + b - 1), (uint32_t)(r0 + b - 2),
                                       (uint32_t)(r0 + b - 3)};
-              philox10_n<4>(t, g, rs, kTagSweep, k0, k1, x);
+              philox10_x4(t, g, rs, kTagSweep, k0, k1, x);
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
                 shift_in4(A2, x[i], T2);
@@ -1770,7 +1803,7 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
               uint4 x[4];
               const uint32_t rs[4] = {(uint32_t)(r0 + b), (uint32_t)(r0 + b - 1), (uint32_t)(r0 + b - 2),
                                       (uint32_t)(r0 + b - 3)};
-              philox10_n<4>(t, g, rs, kTagSweep, k0, k1, x);
+              philox10_x4(t, g, rs, kTagSweep, k0, k1, x);
 #pragma unroll
               for (int i = 0; i < 4; ++i) shift_in4(A2, x[i], T2);
               __builtin_amdgcn_sched_barrier(0);
