@@ -243,14 +243,20 @@ int ising_autotune(ising_problem* const* ps, int32_t count, const ising_schedule
   IRET(eval_schedule(s, beta));
   const int S = (int)beta.size();
   const int prefix = prefix_sweeps > 0 ? std::min(prefix_sweeps, S) : std::min(S, 200);
-  // The trial anneal takes sweeps spread evenly over the real schedule, so
-  // that it meets each temperature for the same share of its sweeps: the
-  // paths' costs depend on how many moves are accepted.
-  std::vector<double> pre((size_t)prefix);
-  for (int i = 0; i < prefix; ++i) pre[(size_t)i] = beta[(size_t)((int64_t)i * S / prefix)];
-  ising_schedule ps_sched{ISING_SCHED_EXPLICIT, prefix, 0, 0, pre.data()};
+  // The trial anneals take sweeps spread evenly over the real schedule, so
+  // that they meet each temperature for the same share of their sweeps: the
+  // paths' costs depend on how many moves are accepted.  Every candidate is
+  // timed on `prefix` sweeps; the three fastest are timed again on five
+  // times as many, since the cost of a launch is not quite proportional to
+  // its sweeps (the longest units set the end of a persistent launch).
+  auto trial_tables = [&](int n, std::vector<Table>& tables) {
+    std::vector<double> pre((size_t)n);
+    for (int i = 0; i < n; ++i) pre[(size_t)i] = beta[(size_t)((int64_t)i * S / n)];
+    ising_schedule ps_sched{ISING_SCHED_EXPLICIT, n, 0, 0, pre.data()};
+    return batch_tables(ps, count, &ps_sched, tables);
+  };
   std::vector<Table> tables;
-  IRET(batch_tables(ps, count, &ps_sched, tables));
+  IRET(trial_tables(prefix, tables));
   IRET(ensure_all(ps, count));
   DeviceGuard dg(ps[0]->dg.device);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -270,25 +276,45 @@ int ising_autotune(ising_problem* const* ps, int32_t count, const ising_schedule
     for (int G : {8, 16, 32}) cands.push_back(PersistentConfig{ISING_PATH_MSC, G, block, 0});
 
   Launcher L;
-  double best_ms = 1e300;
-  PersistentConfig winner{ISING_PATH_PLAIN, 1, 256};
-  for (const PersistentConfig& c : cands) {
-    if (check_all(ps, count, tables, n_replicas, c) != ISING_OK) continue;
-    double ms = 1e300;
+  auto time_config = [&](const std::vector<Table>& tb, const PersistentConfig& c, double& ms) {
+    ms = 1e300;
+    if (check_all(ps, count, tb, n_replicas, c) != ISING_OK) return ISING_OK;
     for (int rep = 0; rep < 2; ++rep) {  // the first run warms caches and code
-      int rc = run_batch(ps, count, tables, n_replicas, seeds.data(), c, st, L, false);
+      int rc = run_batch(ps, count, tb, n_replicas, seeds.data(), c, st, L, false);
       if (rc != ISING_OK) {
         ms = 1e300;
-        break;
+        return ISING_OK;
       }
       ICHK(hipEventSynchronize(L.ev1));
       float f = 0;
       ICHK(hipEventElapsedTime(&f, L.ev0, L.ev1));
       ms = std::min(ms, (double)f);
     }
-    if (ms < best_ms) {
-      best_ms = ms;
-      winner = c;
+    return ISING_OK;
+  };
+  std::vector<std::pair<double, size_t>> timed;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    double ms;
+    IRET(time_config(tables, cands[i], ms));
+    if (ms < 1e300) timed.push_back({ms, i});
+  }
+  PersistentConfig winner{ISING_PATH_PLAIN, 1, 256};
+  if (!timed.empty()) {
+    std::sort(timed.begin(), timed.end());
+    winner = cands[timed[0].second];
+    const int longer = std::min(S, 5 * prefix);
+    if (timed.size() > 1 && longer > prefix) {
+      std::vector<Table> tables2;
+      IRET(trial_tables(longer, tables2));
+      double best_ms = 1e300;
+      for (size_t k = 0; k < std::min<size_t>(3, timed.size()); ++k) {
+        double ms;
+        IRET(time_config(tables2, cands[timed[k].second], ms));
+        if (ms < best_ms) {
+          best_ms = ms;
+          winner = cands[timed[k].second];
+        }
+      }
     }
   }
   for (int i = 0; i < count; ++i) ps[i]->run.valid = false;  // prefix results are not results
