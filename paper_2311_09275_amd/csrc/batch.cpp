@@ -81,12 +81,16 @@ void save_tune_file() {
   fclose(f);
 }
 
+// Each problem's threshold table of the schedule: the one it keeps while the
+// schedule repeats (so that a repeated batch neither recomputes nor uploads
+// it again).
 int batch_tables(ising_problem* const* ps, int count, const ising_schedule* s,
-                 std::vector<Table>& tables) {
-  std::vector<double> beta;
-  IRET(eval_schedule(s, beta));
+                 std::vector<const Table*>& tables) {
   tables.resize((size_t)count);
-  for (int i = 0; i < count; ++i) IRET(build_table(beta, ps[i]->g.kmax, tables[(size_t)i]));
+  for (int i = 0; i < count; ++i) {
+    IRET(schedule_table(ps[i], s));
+    tables[(size_t)i] = &ps[i]->sched.table;
+  }
   return ISING_OK;
 }
 
@@ -113,24 +117,24 @@ int ensure_all(ising_problem* const* ps, int count) {
   return ISING_OK;
 }
 
-int check_all(ising_problem* const* ps, int count, const std::vector<Table>& tables, int R,
+int check_all(ising_problem* const* ps, int count, const std::vector<const Table*>& tables, int R,
               const PersistentConfig& c) {
-  for (int i = 0; i < count; ++i) IRET(check_config(ps[i]->g, tables[(size_t)i], R, c));
+  for (int i = 0; i < count; ++i) IRET(check_config(ps[i]->g, *tables[(size_t)i], R, c));
   return ISING_OK;
 }
 
 // Run a batch of problems with one persistent launch.
-int run_batch(ising_problem* const* ps, int count, const std::vector<Table>& tables, int R,
+int run_batch(ising_problem* const* ps, int count, const std::vector<const Table*>& tables, int R,
               const uint64_t* seeds, const PersistentConfig& cfg, hipStream_t st, Launcher& L,
               bool use_graph) {
   if (cfg.path == ISING_PATH_PLAIN) {
     set_error("the plain path has no batched form");
     return ISING_ERR_INVALID;
   }
-  for (int i = 0; i < count; ++i) IRET(prepare_run(ps[i], tables[(size_t)i], R, cfg, st));
+  for (int i = 0; i < count; ++i) IRET(prepare_run(ps[i], *tables[(size_t)i], R, cfg, st));
   std::vector<JobSpec> specs;
   for (int i = 0; i < count; ++i)
-    specs.push_back(JobSpec{&ps[i]->g, &ps[i]->dg, &ps[i]->run, R, seeds[i], 0, tables[(size_t)i].S});
+    specs.push_back(JobSpec{&ps[i]->g, &ps[i]->dg, &ps[i]->run, R, seeds[i], 0, tables[(size_t)i]->S});
   for (int i = 0; i < count; ++i) ICHK(hipEventRecord(ps[i]->run.ev0, st));
   IRET(run_persistent(L, specs, cfg, st, use_graph));
   for (int i = 0; i < count; ++i) {
@@ -138,7 +142,7 @@ int run_batch(ising_problem* const* ps, int count, const std::vector<Table>& tab
     RunBuffers& b = ps[i]->run;
     b.cfg = cfg;
     b.seed = seeds[i];
-    b.t_done = tables[(size_t)i].S;
+    b.t_done = tables[(size_t)i]->S;
     b.valid = true;
     ps[i]->temper.valid = false;  // the last run is this anneal
   }
@@ -167,7 +171,7 @@ int ising_anneal_batch(ising_problem* const* ps, int32_t count, const ising_sche
                        void* stream) {
   if (!ps || count < 1 || !s || n_replicas < 1 || !seeds) return ISING_ERR_INVALID;
   TraceRange tr("ising_anneal_batch");
-  std::vector<Table> tables;
+  std::vector<const Table*> tables;
   IRET(batch_tables(ps, count, s, tables));
   IRET(ensure_all(ps, count));
   DeviceGuard dg(ps[0]->dg.device);
@@ -186,7 +190,7 @@ int ising_anneal_batch(ising_problem* const* ps, int32_t count, const ising_sche
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       load_tune_file();
-      auto it = g_tune.find(batch_key(gs, n_replicas, tables[0].S));
+      auto it = g_tune.find(batch_key(gs, n_replicas, tables[0]->S));
       if (it != g_tune.end() && check_all(ps, count, tables, n_replicas, it->second) == ISING_OK) {
         cfg = it->second;
         found = true;
@@ -197,7 +201,7 @@ int ising_anneal_batch(ising_problem* const* ps, int32_t count, const ising_sche
       int big = 0;
       for (int i = 1; i < count; ++i)
         if (ps[i]->g.n_pad > ps[big]->g.n_pad) big = i;
-      cfg = heuristic_config(ps[big]->g, tables[(size_t)big], n_replicas);
+      cfg = heuristic_config(ps[big]->g, *tables[(size_t)big], n_replicas);
       if (cfg.path != ISING_PATH_PLAIN) {
         // with many problems the unit count is large already: keep G = 1
         // unless the LDS budget allows more and units stay plentiful
@@ -249,13 +253,16 @@ int ising_autotune(ising_problem* const* ps, int32_t count, const ising_schedule
   // timed on `prefix` sweeps; the three fastest are timed again on five
   // times as many, since the cost of a launch is not quite proportional to
   // its sweeps (the longest units set the end of a persistent launch).
-  auto trial_tables = [&](int n, std::vector<Table>& tables) {
-    std::vector<double> pre((size_t)n);
+  // (the trial schedules replace each problem's kept table)
+  std::vector<double> pre;
+  ising_schedule ps_sched{};
+  auto trial_tables = [&](int n, std::vector<const Table*>& tables) {
+    pre.assign((size_t)n, 0.0);
     for (int i = 0; i < n; ++i) pre[(size_t)i] = beta[(size_t)((int64_t)i * S / n)];
-    ising_schedule ps_sched{ISING_SCHED_EXPLICIT, n, 0, 0, pre.data()};
+    ps_sched = ising_schedule{ISING_SCHED_EXPLICIT, n, 0, 0, pre.data()};
     return batch_tables(ps, count, &ps_sched, tables);
   };
-  std::vector<Table> tables;
+  std::vector<const Table*> tables;
   IRET(trial_tables(prefix, tables));
   IRET(ensure_all(ps, count));
   DeviceGuard dg(ps[0]->dg.device);
@@ -276,7 +283,7 @@ int ising_autotune(ising_problem* const* ps, int32_t count, const ising_schedule
     for (int G : {8, 16, 32}) cands.push_back(PersistentConfig{ISING_PATH_MSC, G, block, 0});
 
   Launcher L;
-  auto time_config = [&](const std::vector<Table>& tb, const PersistentConfig& c, double& ms) {
+  auto time_config = [&](const std::vector<const Table*>& tb, const PersistentConfig& c, double& ms) {
     ms = 1e300;
     if (check_all(ps, count, tb, n_replicas, c) != ISING_OK) return ISING_OK;
     for (int rep = 0; rep < 2; ++rep) {  // the first run warms caches and code
@@ -304,7 +311,7 @@ int ising_autotune(ising_problem* const* ps, int32_t count, const ising_schedule
     winner = cands[timed[0].second];
     const int longer = std::min(S, 5 * prefix);
     if (timed.size() > 1 && longer > prefix) {
-      std::vector<Table> tables2;
+      std::vector<const Table*> tables2;
       IRET(trial_tables(longer, tables2));
       double best_ms = 1e300;
       for (size_t k = 0; k < std::min<size_t>(3, timed.size()); ++k) {
