@@ -1668,28 +1668,25 @@ __device__ void msc4_unit(const JobDev& J, const int block, uint32_t* smem, Msc4
       __builtin_amdgcn_sched_barrier(0);
       const uint32_t ent[8] = {a[h][0].x, a[h][0].y, a[h][0].z, a[h][0].w,
                                a[h][1].x, a[h][1].y, a[h][1].z, a[h][1].w};
-      // the slice's twenty reads all go out before any is used, so that a
-      // wave waits for LDS once per slice
-      uint32_t s[4], n[4][4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        s[j] = lds_load<E>(own_addr(gs[h], j));
-        n[j][0] = lds_load<E>(lds_entry_addr<0, sizeof(E)>(ent[2 * j], st_base));
-        n[j][1] = lds_load<E>(lds_entry_addr<1, sizeof(E)>(ent[2 * j], st_base));
-        n[j][2] = lds_load<E>(lds_entry_addr<0, sizeof(E)>(ent[2 * j + 1], st_base));
-        n[j][3] = lds_load<E>(lds_entry_addr<1, sizeof(E)>(ent[2 * j + 1], st_base));
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
+        const uint32_t s = lds_load<E>(own_addr(gs[h], j));
+        const uint32_t n0 = lds_load<E>(lds_entry_addr<0, sizeof(E)>(ent[2 * j], st_base));
+        const uint32_t n1 = lds_load<E>(lds_entry_addr<1, sizeof(E)>(ent[2 * j], st_base));
+        const uint32_t n2 = lds_load<E>(lds_entry_addr<0, sizeof(E)>(ent[2 * j + 1], st_base));
+        const uint32_t n3 = lds_load<E>(lds_entry_addr<1, sizeof(E)>(ent[2 * j + 1], st_base));
         if (h == 0) {
-          S[j] = s[j];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) D[j][e] = n[j][e];
+          S[j] = s;
+          D[j][0] = n0;
+          D[j][1] = n1;
+          D[j][2] = n2;
+          D[j][3] = n3;
         } else {
-          S[j] |= s[j] << (h * W);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) D[j][e] |= n[j][e] << (h * W);
+          S[j] |= s << (h * W);
+          D[j][0] |= n0 << (h * W);
+          D[j][1] |= n1 << (h * W);
+          D[j][2] |= n2 << (h * W);
+          D[j][3] |= n3 << (h * W);
         }
       }
     }
