@@ -317,3 +317,32 @@ def test_back_to_back_batches_on_two_streams():
             np.testing.assert_array_equal(p.best_state(), state, err_msg=inst.name)
     for p in pa + pb:
         p.close()
+
+
+def test_batch_schedule_changes_between_calls():
+    """Each problem keeps its threshold table while its schedule repeats; a
+    batch with another schedule (and then the first one again, and a single
+    anneal of one member in between) must use the right table every time.
+    Twenty problems, so that the whole-problem unit lists are used too."""
+    insts = [I.torus(12 + i, 14 + (i % 5), 800 + i) for i in range(20)]
+    probs = [B.Problem.from_instance(x) for x in insts]
+    hs = [p.handle for p in probs]
+    R = 16
+    seeds = np.array([8100 + i for i in range(len(insts))], np.uint64)
+    sa = B.Schedule.make(B.GEOMETRIC, 120, 0.1, 4.0)
+    sb = B.Schedule.make(B.LINEAR, 90, 0.05, 2.0)
+    tun = B.Tuning(B.PATH_MSC, 8, 256, 0)
+    checks = [(sa, O.GEOMETRIC, 120, 0.1, 4.0), (sb, O.LINEAR, 90, 0.05, 2.0),
+              (sa, O.GEOMETRIC, 120, 0.1, 4.0)]
+    for step, (sched, kind, S, b0, b1) in enumerate(checks):
+        B.ising_anneal_batch(hs, sched, R, seeds, tun)
+        for i in (0, 7, 19):
+            o = O.anneal(insts[i], S, R, int(seeds[i]), kind=kind, beta0=b0, beta1=b1)
+            np.testing.assert_array_equal(B.ising_cut(hs[i], R)[2], o.best_cut, err_msg=f"step {step} problem {i}")
+        if step == 0:
+            # a single anneal of a member with the other schedule
+            probs[7].anneal(sb, R, int(seeds[7]), B.Tuning(B.PATH_FIELD, 1, 256, 0))
+            o = O.anneal(insts[7], 90, R, int(seeds[7]), kind=O.LINEAR, beta0=0.05, beta1=2.0)
+            np.testing.assert_array_equal(B.ising_cut(hs[7], R)[2], o.best_cut)
+    for p in probs:
+        p.close()
