@@ -795,9 +795,19 @@ int run_persistent(Launcher& L, const std::vector<JobSpec>& specs, const Persist
     JobDev base = jobs[0];
     base.temp = pt->swap->temp;
     jobs.assign((size_t)n_segs, base);
+    // Between segments only the exchange kernel runs, and it reads
+    // energies: a degree-4 form keeps its bond words in the save area from
+    // one segment to the next, and only the last segment saves packed
+    // fields.  Cluster moves read the packed form after every round.
+    const bool bond = !pt->cluster && (form == kFormDeg4 || form == kFormHbmDeg4 ||
+                                        (form == kFormPerJob &&
+                                         (base.adj_form == kFormDeg4 || base.adj_form == kFormHbmDeg4)));
     for (int i = 0; i < n_segs; ++i) {
-      jobs[(size_t)i].t_begin = segs[(size_t)i].x;
-      jobs[(size_t)i].t_end = segs[(size_t)i].y;
+      JobDev& J = jobs[(size_t)i];
+      J.t_begin = segs[(size_t)i].x;
+      J.t_end = segs[(size_t)i].y;
+      if (bond && i > 0) J.flags |= kJobLoadBond;
+      if (bond && i + 1 < n_segs) J.flags |= kJobSaveBond;
     }
   }
   const int n_dev_jobs = (int)jobs.size();

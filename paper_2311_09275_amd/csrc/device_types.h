@@ -77,6 +77,11 @@ constexpr int kMaxLdsDegree = 255;         // LDS paths pack degrees in 8 bits
 enum JobFlags : int32_t {
   kJobTrace = 1,      // write E after every sweep to trace[t*R + r]
   kJobInitGiven = 2,  // initial spins come from init_spins
+  // FIELD degree-4 forms, between the segments of one tempering run: the
+  // save area holds the units' bond words as they are in LDS, instead of
+  // packed fields (written by a segment, read by the next one)
+  kJobSaveBond = 4,
+  kJobLoadBond = 8,
 };
 
 // One anneal of one problem for the persistent kernels.  Units of work are

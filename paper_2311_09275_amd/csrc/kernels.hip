@@ -724,7 +724,9 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
 
   int E, best_cut, best_sweep;
   bool snap;
-  if (SOA) {
+  // a resumed tempering segment may have its bond words saved as they were
+  const bool bond_in = SOA && !fresh && (J.flags & kJobLoadBond);
+  if (SOA && !bond_in) {
     // Bond words from the spins (bit 0 of every word at this point), for a
     // fresh start and a resumed chunk alike.  Only bit 0 of other words is
     // read while words are rewritten, and bit 0 keeps the spin.
@@ -1009,7 +1011,10 @@ __device__ void field_unit(const JobDev& J, const int block, int32_t* smem, Fiel
   if (live) {
     for (int g = lt; g < n_grp; g += TPR) {
       int4 w4;
-      if (SOA) {
+      if (SOA && (J.flags & kJobSaveBond)) {
+        // the next segment reads the bond words back as they are
+        w4 = make_int4(st[widx(g, 0)], st[widx(g, 1)], st[widx(g, 2)], st[widx(g, 3)]);
+      } else if (SOA) {
         // bond words back to packed fields: k = 2 popc - 6, h = s k
         int v[4];
 #pragma unroll
