@@ -463,8 +463,8 @@ int ising_last_batch_ms(double* ms);
 /*
  * Autotuner: time each launch candidate on a short trial anneal of the given
  * batch -- prefix_sweeps sweeps whose betas are taken evenly spaced from the
- * schedule -- then the three fastest again on five times as many sweeps (at
- * most S), and return the fastest of those in *best (also cached in memory
+ * schedule -- then the three fastest again on max(5 prefix_sweeps, 4000)
+ * sweeps (at most S), and return the fastest of those in *best (also cached in memory
  * and in the file named by $ISING_TUNE_CACHE when set).  prefix_sweeps <= 0
  * picks 200 (or S when smaller).  The trials' results are discarded: each
  * problem needs a new anneal before its results can be read.

@@ -250,9 +250,10 @@ int ising_autotune(ising_problem* const* ps, int32_t count, const ising_schedule
   // The trial anneals take sweeps spread evenly over the real schedule, so
   // that they meet each temperature for the same share of their sweeps: the
   // paths' costs depend on how many moves are accepted.  Every candidate is
-  // timed on `prefix` sweeps; the three fastest are timed again on five
-  // times as many, since the cost of a launch is not quite proportional to
-  // its sweeps (the longest units set the end of a persistent launch).
+  // timed on `prefix` sweeps; the three fastest are timed again on the whole
+  // schedule (at most max(5 prefix, 4000) sweeps), since the cost of a
+  // launch is not quite proportional to its sweeps (the longest units set
+  // the end of a persistent launch).
   // (the trial schedules replace each problem's kept table)
   std::vector<double> pre;
   ising_schedule ps_sched{};
@@ -309,7 +310,7 @@ int ising_autotune(ising_problem* const* ps, int32_t count, const ising_schedule
   if (!timed.empty()) {
     std::sort(timed.begin(), timed.end());
     winner = cands[timed[0].second];
-    const int longer = std::min(S, 5 * prefix);
+    const int longer = std::min(S, std::max(5 * prefix, 4000));
     if (timed.size() > 1 && longer > prefix) {
       std::vector<const Table*> tables2;
       IRET(trial_tables(longer, tables2));
