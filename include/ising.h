@@ -492,8 +492,14 @@ typedef struct {
  * per step in one persistent launch, finished ones retire and queued ones
  * are admitted between steps.  State stays on the device across steps.
  * backend: 0 = GPU; 1 = host-only null backend that advances sweep counters
- * without computing (to exercise the scheduling logic without a GPU).
+ * without computing (to exercise the scheduling logic without a GPU); 2 = the
+ * null backend that also fails, with ISING_ERR_DEVICE, every step in which a
+ * request submitted with seed ISING_NULL_FAIL_SEED is resident (to exercise
+ * the failure path).  A failed step ends every request resident in it with
+ * that status, frees their memory and slots, and the server goes on with
+ * the queue.
  */
+#define ISING_NULL_FAIL_SEED 0xFA11FA11FA11FA11ull
 int ising_server_create(uint64_t hbm_budget, int32_t max_slots,
                         int32_t chunk_sweeps, int32_t backend, void* stream,
                         ising_server** out);

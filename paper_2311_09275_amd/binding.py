@@ -34,6 +34,8 @@ except ImportError:  # torch is optional for the C ABI itself
 _L = C.CDLL(LIB_PATH)
 
 OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_UNSUPPORTED, ERR_TIMEOUT = 0, -1, -2, -3, -4, -5, -6
+# server backend 2 fails every step in which a request with this seed is resident
+NULL_FAIL_SEED = 0xFA11FA11FA11FA11
 LINEAR, GEOMETRIC, EXPLICIT = 0, 1, 2
 PATH_AUTO, PATH_PLAIN, PATH_FIELD, PATH_MSC = 0, 1, 2, 3
 

@@ -222,8 +222,16 @@ int step_device(ising_server* s, std::vector<std::shared_ptr<Request>>& batch) {
 }
 
 // The null backend advances sweep counters only; its "best cut" is the
-// number of sweeps done, which makes target checks observable.
+// number of sweeps done, which makes target checks observable.  Backend 2
+// also fails (as a device error would) every step in which a request with
+// the seed ISING_NULL_FAIL_SEED is resident.
 int step_null(ising_server* s, std::vector<std::shared_ptr<Request>>& batch) {
+  if (s->backend == 2)
+    for (auto& r : batch)
+      if (r->seed == ISING_NULL_FAIL_SEED) {
+        set_error("null backend: injected step failure");
+        return ISING_ERR_DEVICE;
+      }
   for (auto& r : batch) {
     const int end = next_end(*r, s->chunk);
     r->work.best_cut = end;
@@ -322,7 +330,7 @@ int ising_server_footprint(const ising_problem* p, const ising_schedule* sched, 
 
 int ising_server_create(uint64_t hbm_budget, int32_t max_slots, int32_t chunk_sweeps,
                         int32_t backend, void* stream, ising_server** out) {
-  if (!out || hbm_budget < 4096 || max_slots < 1 || chunk_sweeps < 1 || (backend != 0 && backend != 1))
+  if (!out || hbm_budget < 4096 || max_slots < 1 || chunk_sweeps < 1 || backend < 0 || backend > 2)
     return ISING_ERR_INVALID;
   ising_server* s = nullptr;
   try {

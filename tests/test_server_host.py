@@ -148,3 +148,52 @@ def test_results_are_published_whole_while_polled():
     assert not any(th.is_alive() for th in threads)
     assert problems == []
     B.ising_server_destroy(srv)
+
+
+def test_failed_step_ends_the_request_and_frees_its_slot():
+    """Backend 2 fails every step in which the marked request is resident
+    (as a device error would).  With one slot, the marked request fails
+    alone with ISING_ERR_DEVICE; its memory and slot are freed and the
+    requests queued behind it run to completion."""
+    p = _problem(10)
+    s = B.Schedule.make(B.LINEAR, 200, 0.1, 3.0)
+    need = B.ising_server_footprint(p.handle, s, 32)
+    srv = B.ising_server_create(need + need // 2, 1, 50, backend=2)
+    bad = B.ising_server_submit(srv, p.handle, s, 32, B.NULL_FAIL_SEED, 10 ** 9, 50)
+    good = [B.ising_server_submit(srv, p.handle, s, 32, 10 + i, 10 ** 9, 50) for i in range(3)]
+    rb = B.ising_server_wait(srv, bad, 10.0)
+    assert rb.status == B.ERR_DEVICE and rb.sweeps_done == 0
+    with pytest.raises(B.IsingError) as e:
+        B.ising_server_best_state(srv, bad, p.n)
+    assert e.value.status == B.ERR_STATE
+    for t in good:
+        r = B.ising_server_wait(srv, t, 10.0)
+        assert r.status == 0 and r.sweeps_done == 200
+    steps, finished, peak = B.ising_server_stats(srv)
+    assert finished == 4 and peak == 1
+    B.ising_server_destroy(srv)
+
+
+def test_failed_step_ends_every_request_resident_in_it():
+    """A long request is resident when the marked one joins it: the step
+    they share fails, and both end with ISING_ERR_DEVICE part-way; a
+    request submitted afterwards is served normally."""
+    p = _problem(10)
+    s_long = B.Schedule.make(B.LINEAR, 1_000_000, 0.1, 3.0)
+    s = B.Schedule.make(B.LINEAR, 100, 0.1, 3.0)
+    srv = B.ising_server_create(1 << 30, 4, 1, backend=2)
+    long_t = B.ising_server_submit(srv, p.handle, s_long, 16, 1, 10 ** 9, 0)
+    import time
+    t0 = time.monotonic()
+    while B.ising_server_stats(srv)[0] < 3:  # the long request alone has run a few steps
+        assert time.monotonic() - t0 < 10.0
+        time.sleep(0.001)
+    bad = B.ising_server_submit(srv, p.handle, s, 16, B.NULL_FAIL_SEED, 10 ** 9, 0)
+    rl = B.ising_server_wait(srv, long_t, 30.0)
+    rb = B.ising_server_wait(srv, bad, 30.0)
+    assert rl.status == B.ERR_DEVICE and 0 < rl.sweeps_done < 1_000_000
+    assert rb.status == B.ERR_DEVICE
+    after = B.ising_server_submit(srv, p.handle, s, 16, 2, 10 ** 9, 0)
+    ra = B.ising_server_wait(srv, after, 10.0)
+    assert ra.status == 0 and ra.sweeps_done == 100
+    B.ising_server_destroy(srv)
