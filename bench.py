@@ -113,6 +113,7 @@ def parse():
     ap.add_argument("--no-separate", action="store_true", help="skip the 64 separate launches")
     ap.add_argument("--no-c2", action="store_true", help="skip the 100x80 torus leg")
     ap.add_argument("--no-random", action="store_true", help="skip the sparse random graph leg")
+    ap.add_argument("--no-fields", action="store_true", help="skip the local-fields leg")
     ap.add_argument("--no-temper", action="store_true", help="skip the parallel tempering leg")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests of the Poisson serving leg (0 = skip)")
@@ -451,6 +452,45 @@ def main():
         p3.close()
         log("c3 done")
 
+    # ------------------------------------------------------------ local fields
+    # The 100x80 torus with integer fields b in [-2, 2] on every vertex: the
+    # field term enters the flip key, so the degree-4 bond-word forms do not
+    # apply and the automatic configuration takes a key form.
+    fields = None
+    instf = I.with_fields(inst2, seed=2, bmax=2)
+    attf = instf.n * R2 * S
+    if not args.no_fields:
+        pf = B.Problem.from_instance(instf)
+        auto = B.Tuning(B.PATH_AUTO, 0, 0, 0)
+        pf.anneal(sched, R2, SEED2, auto, stream=stream)
+        pf.cut()
+        ws, ks = [], []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            pf.anneal(sched, R2, SEED2, auto, stream=stream)
+            resf = pf.cut()
+            ws.append(time.perf_counter() - t)
+            ks.append(pf.last_anneal_ms())
+        perf_ = resf.per_replica.copy()
+        wf, kf = float(np.mean(ws)), float(np.mean(ks))
+        info_f = B.ising_last_run_info(pf.handle)
+        fields = {"workload": "torus 100x80 +-1 with local fields b~U{-2..2} on every vertex, "
+                              "256 replicas, 4000 sweeps geometric 0.1->4.0",
+                  "ms_per_anneal": wf * 1e3, "kernel_ms": kf, "kernel_ms_samples": ks,
+                  "attempts_per_s": attf / wf, "best_objective": int(resf.best_cut),
+                  "path": info_f[2]}
+        if not args.no_plain:
+            t = time.perf_counter()
+            pf.anneal(sched, R2, SEED2, B.Tuning(B.PATH_PLAIN, 1, 256, 0), stream=stream)
+            rp = pf.cut()
+            wp = time.perf_counter() - t
+            assert np.array_equal(rp.per_replica, perf_), "plain and automatic forms disagree (fields)"
+            fields["plain_ms"] = wp * 1e3
+            fields["persistent_vs_plain_speedup"] = wp / wf
+        pf.close()
+        log("fields done")
+
     # ------------------------------------------------------------ parallel tempering
     temper = None
     if not args.no_temper:
@@ -516,7 +556,7 @@ def main():
     # ------------------------------------------------------------ oracle: tallies and CPU baseline
     cpu = None
     rooflines = {}
-    pa4 = pa2 = pa3 = None
+    pa4 = pa2 = pa3 = paf = None
     if not args.no_cpu:
         from oracle import oracle as O
         O.build(force=False)
@@ -528,6 +568,8 @@ def main():
         pa2 = per_attempt(oracle_tally([(inst2, S, R2, SEED2, geo, r, r + 1) for r in range(16)], threads))
         pa3 = per_attempt(oracle_tally([(inst3, S3, R3, SEED3, dict(kind=O.LINEAR, beta0=0.05, beta1=3.0),
                                          r, r + 1) for r in range(16)], threads))
+        if fields is not None:
+            paf = per_attempt(oracle_tally([(instf, S, R2, SEED2, geo, r, r + 1) for r in range(16)], threads))
         # CPU baseline: the oracle on replicas 0..7 of every batch problem
         jobs = [(i, r) for i in range(len(insts)) for r in range(8)]
 
@@ -572,6 +614,8 @@ def main():
     if pa3 is not None and c3 is not None:
         rooflines["c3"] = roofline(att3, c3["kernel_ms"] / 1e3, pa3, "keys", lds_peak,
                                    "k_field_random10000_r1024_counters.md")
+    if paf is not None and fields is not None:
+        rooflines["c2_fields"] = roofline(attf, fields["kernel_ms"] / 1e3, paf, "keys", lds_peak)
     roof = rooflines.get("c4_batch")
     if roof is not None:
         roof = dict(roof)
@@ -597,6 +641,7 @@ def main():
         "above_reference": above_reference,
         "torus100x80": c2,
         "random_graph": c3,
+        "local_fields": fields,
         "tempering": temper,
         "serving": serving,
         "rooflines": rooflines,
