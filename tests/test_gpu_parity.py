@@ -345,6 +345,31 @@ def test_schedule_and_table_reuse_across_anneals():
     p.close()
 
 
+@pytest.mark.parametrize("width", [8, 16])
+def test_msc4_at_its_size_limit(width):
+    """The largest torus the multispin degree-4 form takes: 180x180 pads to
+    32,512 tiled words, just under its 2^15 limit (8-bit elements: 65 KB of
+    LDS pairs; 16-bit: 130 KB, one unit per CU).  Every replica against the
+    oracle."""
+    compare(I.torus(180, 180, 7), 30, width, 11, kind=O.GEOMETRIC, b0=0.1, b1=4.0,
+            tuning=B.Tuning(B.PATH_MSC, width, 256, 0))
+
+
+def test_msc4_beyond_its_size_limit_is_refused():
+    """One size up (182x182, 33,124 vertices) the form is refused with
+    ISING_ERR_UNSUPPORTED, as is 32-bit elements at 180x180 (260 KB of
+    pairs), and the automatic configuration still runs both."""
+    sched = B.Schedule.make(B.GEOMETRIC, 5, 0.1, 4.0)
+    for side, width in ((182, 8), (180, 32)):
+        p = B.Problem.from_instance(I.torus(side, side, 8))
+        with pytest.raises(B.IsingError) as e:
+            p.anneal(sched, width, 3, B.Tuning(B.PATH_MSC, width, 256, 0))
+        assert e.value.status == B.ERR_UNSUPPORTED
+        p.anneal(sched, width, 3, None)
+        assert p.cut().best_cut > 0
+        p.close()
+
+
 @pytest.mark.parametrize("path", sorted(DEG4_ONLY - {"field_g1_b512_hbmdeg4"}))
 def test_msc4_small_shapes(path):
     """The multispin degree-4 form on the smallest torus (3 classes of
