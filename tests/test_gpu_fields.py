@@ -39,6 +39,15 @@ def test_fields_automatic_configuration():
     compare(I.with_fields(I.workload_c1(), 6, 3), 400, 8, 63, tuning=None)
 
 
+def test_fields_full_size_sampled_replicas():
+    """The benchmark's local-fields workload at full size, in the launch it
+    times (the automatic configuration): the 100x80 torus with b in [-2, 2]
+    on every vertex, 256 replicas, 4000 sweeps geometric 0.1 -> 4.0; three
+    replicas recomputed by the oracle."""
+    compare(I.with_fields(I.workload_c2(), seed=2, bmax=2), 4000, 256, 1002, kind=O.GEOMETRIC,
+            b0=0.1, b1=4.0, tuning=None, replicas=[0, 129, 255], trace=False)
+
+
 def test_fields_refusals():
     inst = I.with_fields(I.torus(8, 8, 1), 1, 2)
     p = B.Problem.from_instance(inst)
