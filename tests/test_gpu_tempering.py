@@ -141,6 +141,14 @@ def test_full_size_torus_sampled_sets():
             sets=(3, 5), states=False)
 
 
+def test_full_size_torus_whole_run_one_set():
+    """The benchmark's tempering run at its full length (100x80 torus, 32
+    temperatures, 8 sets, a round every 10 sweeps, 4000 sweeps, the
+    automatic configuration): the oracle checks the last set."""
+    compare(I.workload_c2(), list(np.geomspace(0.2, 3.0, 32)), 8, 4000, 10, 1002, None,
+            sets=(7, 8), states=False)
+
+
 def test_errors_and_state():
     inst = I.torus(8, 8, 1)
     p = B.Problem.from_instance(inst)
@@ -197,6 +205,14 @@ def test_cluster_moves_full_size_sampled_pairs():
     temperatures: the oracle checks one pair of sets over 400 sweeps."""
     compare(I.workload_c2(), list(np.geomspace(0.2, 3.0, 32)), 8, 400, 10, 1002, None,
             sets=(2, 4), states=False, cluster_from=16)
+
+
+def test_cluster_moves_full_size_whole_run_one_pair():
+    """The benchmark's run with cluster moves at its full length (moves at
+    the 16 coldest of 32 temperatures, a round every 10 sweeps, 4000
+    sweeps): the oracle checks one pair of sets."""
+    compare(I.workload_c2(), list(np.geomspace(0.2, 3.0, 32)), 8, 4000, 10, 1002, None,
+            sets=(6, 8), states=False, cluster_from=16)
 
 
 @pytest.mark.parametrize("path", ["plain", "field_g1_b256_hbmadj"])
