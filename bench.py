@@ -169,11 +169,15 @@ def lds_bytes_per_attempt(form, pa, width=8):
              its word and 4 neighbour XORs (read and write);
       keys   FIELD key form with HBM adjacency: a group's 4 words, degree and
              base words and 4 thresholds per 4 attempts; per flip one word
-             store and an atomic add (read and write) per neighbour."""
+             store and an atomic add (read and write) per neighbour;
+      csr    the key form with its CSR adjacency staged in LDS: as keys, plus
+             a 2-byte entry read per neighbour of a flip."""
     if form == "msc4":
         return 112.0 / 128.0
     if form == "deg4":
         return 64.0 / 4.0 + pa["flips"] * (4 + 4 * 8)
+    if form == "csr":
+        return 40.0 / 4.0 + pa["flips"] * (4 + 10 * pa["mean_degree"])
     return 40.0 / 4.0 + pa["flips"] * (4 + 8 * pa["mean_degree"])
 
 
@@ -615,7 +619,8 @@ def main():
         rooflines["c3"] = roofline(att3, c3["kernel_ms"] / 1e3, pa3, "keys", lds_peak,
                                    "k_field_random10000_r1024_counters.md")
     if paf is not None and fields is not None:
-        rooflines["c2_fields"] = roofline(attf, fields["kernel_ms"] / 1e3, paf, "keys", lds_peak)
+        rooflines["c2_fields"] = roofline(attf, fields["kernel_ms"] / 1e3, paf, "csr", lds_peak,
+                                          "k_field_torus100x80_fields_r256_counters.md")
     roof = rooflines.get("c4_batch")
     if roof is not None:
         roof = dict(roof)
